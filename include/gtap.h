@@ -1,0 +1,210 @@
+/*
+ * gtap.h -- C ABI of the MI355X (gfx950) fork-join task runtime.
+ *
+ * The runtime executes fine-grained fork-join task trees inside one persistent
+ * kernel (GTaP, Sec. 5.1.1 "Overview"): every wavefront of the grid runs a
+ * scheduler loop that acquires runnable task IDs from its own work-stealing
+ * deque or steals them from another wavefront's, executes them, and publishes
+ * the tasks they make runnable.  A task that forks suspends at its join with
+ * a waiting-child counter and a saved resume point and is re-executed in
+ * place when the last child completes (Sec. 5.1.2 "Implementation of
+ * Fork-Join").  Thread mode runs one task per lane of a 64-lane wavefront;
+ * block mode runs one task per workgroup (Sec. 4.2, Sec. 4.3).
+ *
+ * The paper's host API is initialize(config) / launch(kernel, args) /
+ * finalize() with a configuration giving launch geometry, preallocated task
+ * capacity and the number of DAQ queues, and capacity overflow reported as a
+ * structured error (Sec. 4, "Programming Model", opening paragraphs).  This ABI
+ * splits launch into submit (one root task per job, arguments copied at submit
+ * time like a task's firstprivate arguments, Sec. 4.1) and run (one persistent
+ * launch for every submitted job).
+ *
+ * Conventions for every entry point:
+ *   - returns GTAP_OK (0) on success or a negative gtap_status; no exception
+ *     or abort crosses the ABI;
+ *   - pointers named *_dev are device pointers (hipMalloc or a PyTorch CUDA
+ *     tensor's data_ptr()); all other pointers are host pointers;
+ *   - a gtap_ctx is not thread-safe: one host thread drives one context.
+ */
+#ifndef GTAP_H
+#define GTAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+enum gtap_status {
+    GTAP_OK = 0,
+    GTAP_E_INVAL = -1,     /* bad argument or configuration                   */
+    GTAP_E_NOMEM = -2,     /* device allocation failed / workspace too small   */
+    GTAP_E_HIP = -3,       /* a HIP runtime call failed                        */
+    GTAP_E_STATE = -4,     /* call not valid in the context's current state   */
+    GTAP_E_FULL = -5,      /* max_jobs pending jobs already submitted          */
+    GTAP_E_CAPACITY = -6,  /* frame pool or deque exhausted on the device:
+                              the run was aborted, see gtap_last_error        */
+    GTAP_E_PENDING = -7,   /* job has not completed                           */
+    GTAP_E_TIMEOUT = -8,   /* device watchdog expired: the run was aborted    */
+    GTAP_E_NOJOB = -9      /* unknown job id                                  */
+};
+
+/* ---- execution modes and task kinds -------------------------------------- */
+enum gtap_mode { GTAP_MODE_THREAD = 0, GTAP_MODE_BLOCK = 1 };
+
+enum gtap_kind {
+    GTAP_KIND_FIB = 1,      /* gtap_fib_args                                   */
+    GTAP_KIND_NQUEENS = 2,  /* gtap_nqueens_args                               */
+    GTAP_KIND_UTS = 3,      /* gtap_uts_args                                   */
+    GTAP_KIND_KCLIQUE = 4   /* gtap_kclique_args                               */
+};
+
+/* Fibonacci with a task at every call (Sec. 6.3, microbenchmarks): result is
+ * fib(n), 0 <= n <= 92. */
+typedef struct { int32_t n; int32_t reserved; } gtap_fib_args;
+
+/* N-Queens solution count by bitmask backtracking, one child task per legal
+ * column (Sec. 6.3): 1 <= n <= 31. */
+typedef struct { int32_t n; int32_t reserved; } gtap_nqueens_args;
+
+/* Unbalanced tree search: node count of the tree rooted at mix64(seed).  A
+ * node at depth < max_depth has as many children as leading splitmix64 draws
+ * below `threshold` (geometric, mean T/(2^64-T)); child i of node id has id
+ * split(id, i).  0 <= max_depth <= 255. */
+typedef struct { uint64_t seed; uint64_t threshold; int32_t max_depth; int32_t reserved; } gtap_uts_args;
+
+/* k-clique count on an oriented graph (Sec. 6.4.2, orientation algorithm).
+ * row_ptr_dev: int32[n+1], col_dev: int32[row_ptr[n]]: sorted out-lists of an
+ * acyclic orientation, device-resident and borrowed: the caller keeps them
+ * alive and unchanged until gtap_run returns.  max_outdeg must be >= every
+ * out-degree and <= the context's big_frame_ints.  Vertex ranges larger than
+ * range_leaf are split in halves; smaller ones fork one task per vertex. */
+typedef struct {
+    const int32_t *row_ptr_dev;
+    const int32_t *col_dev;
+    int32_t n;
+    int32_t k;
+    int32_t range_leaf;
+    int32_t max_outdeg;
+} gtap_kclique_args;
+
+/* ---- configuration -------------------------------------------------------- */
+enum gtap_daq_policy {
+    GTAP_DAQ_NONE = 0,      /* every task in queue 0                            */
+    GTAP_DAQ_BY_KIND = 1,   /* queue = task kind (mod num_queues)               */
+    GTAP_DAQ_KCLIQUE = 2    /* k-clique: queue = bucket of the candidate-set
+                               bound, buckets split at daq_bounds[]            */
+};
+
+typedef struct gtap_config {
+    int32_t mode;             /* gtap_mode; only GTAP_MODE_THREAD runs today   */
+    int32_t num_waves;        /* persistent wavefronts; 0 = every wavefront the
+                                 device can keep resident                      */
+    int32_t waves_per_group;  /* wavefronts per workgroup: 1, 2, 4 or 8        */
+    int32_t num_queues;       /* DAQ deques per wavefront, 1..8 (1 = DAQ off)  */
+    int32_t daq_policy;       /* gtap_daq_policy                               */
+    int32_t daq_bounds[7];    /* ascending class boundaries (GTAP_DAQ_KCLIQUE) */
+    uint32_t deque_capacity;  /* slots per deque, power of two >= 128          */
+    uint32_t steal_below;     /* steal when fewer lanes than this hold a task
+                                 after the local pop (1..64)                   */
+    uint32_t steal_probes;    /* victims whose deque size one steal attempt
+                                 reads at once, the fullest is robbed (1..64) */
+    uint32_t steal_div;       /* a steal claims ceil(count / steal_div)
+                                 entries, at most the free lanes (1..64)      */
+    uint64_t small_frames;    /* frames in the 64-byte frame pool              */
+    uint64_t big_frames;      /* frames in the candidate-buffer pool           */
+    uint32_t big_frame_ints;  /* int32 capacity of a big frame's buffer        */
+    uint32_t max_jobs;        /* jobs per run                                  */
+    uint32_t timeout_ms;      /* device watchdog per run (0 = 120000)          */
+    uint32_t flags;           /* reserved, must be 0                           */
+    void *stream;             /* hipStream_t to launch on (NULL = default)     */
+    void *workspace_dev;      /* optional caller-owned device memory of
+                                 workspace_bytes (>= gtap_workspace_size);
+                                 NULL = the library allocates and frees it    */
+    uint64_t workspace_bytes;
+} gtap_config;
+
+/* Fill *cfg with defaults (thread mode, occupancy-sized grid, one queue). */
+void gtap_config_default(gtap_config *cfg);
+
+/* Device bytes a context with this configuration needs (for workspace_dev).
+ * Needs a current HIP device (the grid size depends on it). */
+int gtap_workspace_size(const gtap_config *cfg, uint64_t *bytes);
+
+/* ---- lifecycle ------------------------------------------------------------ */
+typedef struct gtap_ctx gtap_ctx;
+
+/* Validate cfg, size the grid, lay out (and unless cfg->workspace_dev is set,
+ * allocate) frame pools, deques and job tables on the current HIP device.
+ * *out receives a context owned by the caller until gtap_finalize.
+ * Errors: GTAP_E_INVAL, GTAP_E_NOMEM, GTAP_E_HIP. */
+int gtap_init(const gtap_config *cfg, gtap_ctx **out);
+
+/* Queue one root task.  args points to the kind's argument struct (host
+ * memory, args_bytes == sizeof of it); it is copied before the call returns.
+ * *job_id receives the job's id.  Errors: GTAP_E_INVAL (kind, size or value),
+ * GTAP_E_FULL (max_jobs already pending), GTAP_E_STATE. */
+int gtap_submit(gtap_ctx *ctx, int32_t kind, const void *args, size_t args_bytes,
+                uint64_t *job_id);
+
+/* Launch one persistent kernel for every pending job on cfg->stream and wait
+ * for it.  Jobs' results become readable with gtap_result.  Returns
+ * GTAP_E_CAPACITY or GTAP_E_TIMEOUT when the device aborted the run (results
+ * of that run are then invalid; the context stays usable), GTAP_E_HIP on a
+ * HIP failure. */
+int gtap_run(gtap_ctx *ctx);
+
+/* Copy job job_id's result (int64 count, out_bytes >= 8) into host memory
+ * out.  Valid for the jobs of the most recent gtap_run.  Errors:
+ * GTAP_E_NOJOB, GTAP_E_PENDING (not part of a completed run), GTAP_E_INVAL. */
+int gtap_result(gtap_ctx *ctx, uint64_t job_id, void *out, size_t out_bytes);
+
+/* Release the context and any memory the library allocated for it. */
+int gtap_finalize(gtap_ctx *ctx);
+
+/* ---- diagnostics ---------------------------------------------------------- */
+typedef struct gtap_stats {
+    uint64_t tasks;          /* first executions of a task (resume point 0)    */
+    uint64_t conts;          /* re-executions after a join                    */
+    uint64_t spawns;         /* child tasks created                           */
+    uint64_t pushed;         /* task IDs published to a deque                 */
+    uint64_t push_batches;   /* deque publications (one fence + one atomic)   */
+    uint64_t popped;         /* task IDs claimed from the owner's deque       */
+    uint64_t pop_batches;
+    uint64_t stolen;         /* task IDs claimed from another wave's deque    */
+    uint64_t steal_batches;  /* successful steals                             */
+    uint64_t steal_attempts;
+    uint64_t iterations;     /* scheduler loop iterations that ran tasks      */
+    uint64_t idle_iterations;
+    uint64_t small_frames_touched; /* high-water mark of the small pool       */
+    uint64_t big_frames_touched;
+    uint64_t depot_spills;
+    uint64_t depot_refills;
+    uint64_t busy_cycles;    /* shader-clock cycles in iterations that ran tasks */
+    uint64_t idle_cycles;    /* shader-clock cycles in iterations that found none */
+    double kernel_ms;        /* device time of the last run's persistent kernel */
+    int32_t num_waves;
+    int32_t waves_per_group;
+    int32_t num_queues;
+    int32_t reserved;
+} gtap_stats;
+
+typedef struct gtap_error_report {
+    int32_t code;       /* gtap_status of the abort, GTAP_OK if none           */
+    int32_t pool;       /* 0 small frames, 1 big frames, 2 deque, 3 watchdog   */
+    uint64_t capacity;  /* capacity of the exhausted resource                  */
+    uint64_t requested; /* amount requested when it ran out                    */
+    int32_t wave;       /* wavefront that detected it                          */
+    int32_t job;        /* job slot being served, -1 if unknown                */
+} gtap_error_report;
+
+int gtap_stats_get(gtap_ctx *ctx, gtap_stats *out);
+int gtap_last_error(gtap_ctx *ctx, gtap_error_report *out);
+const char *gtap_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GTAP_H */

@@ -1,0 +1,135 @@
+// layout.h -- device memory layout shared by the host library and the kernels.
+//
+// Everything the runtime touches lives in one device workspace, carved into:
+//   control block   (counters, error report, statistics)
+//   job table       (one 128-byte slot per root task)
+//   deque metadata  (one 128-byte line per deque: count, head, lock)
+//   deque rings     (u32 task IDs, `cap` per deque, waves x queues deques)
+//   depot bins      (free-frame chunks shared between wavefronts, per pool)
+//   frame pools     (small: 64-byte frames; big: 64-byte header + int32 buffer)
+// Task IDs are frame indices (GTaP Sec. 5.1.1: a task ID indexes the storage
+// holding its record); bit 31 selects the big pool.
+#pragma once
+#include <stdint.h>
+
+namespace gtap {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;        // "no task" / "no parent"
+constexpr uint32_t kBigBit = 0x80000000u;      // task ID of a big-pool frame
+constexpr uint32_t kFrameWords = 16;           // 64-byte frame header+payload
+constexpr uint32_t kWave = 64;                 // CDNA wavefront width
+constexpr uint32_t kMaxQueues = 8;             // DAQ deques per wavefront
+constexpr uint32_t kDepotBins = 256;           // depot bins per pool
+
+// Per-wave LDS free-stack capacities and depot chunk sizes (IDs).
+constexpr uint32_t kStackSmall = 1024;
+constexpr uint32_t kStackBig = 256;
+constexpr uint32_t kChunkSmall = 256;
+constexpr uint32_t kChunkBig = 64;
+
+// Frame word map (u32 words).  A spawn writes words 0..7 as four 64-bit
+// device-coherent stores; a fork writes the state word, the join counter and
+// the accumulator.  Big frames carry an int32 buffer from word 16 on.
+enum FrameWord : uint32_t {
+  FW_PARENT = 0,   // parent task ID, kNone for a job's root
+  FW_JOB = 1,      // job slot
+  FW_STATE = 2,    // kind | resume point << 8 | queue class << 16
+  FW_P0 = 3,       // payload words 3..7 (p0..p4)
+  FW_JOIN = 8,     // waiting-child counter (device-scope RMW only)
+  FW_ACC = 10,     // int64 accumulator of children's results (words 10,11)
+  FW_BUF = 16,     // big frames: candidate buffer
+};
+constexpr uint32_t kPayloadWords = 5;
+
+// Task kinds of the thread-mode state machines.
+enum TaskKind : uint32_t {
+  TK_FIB = 1,
+  TK_NQ = 2,
+  TK_UTS = 3,
+  TK_KC_RANGE = 4,
+  TK_KC_VERTEX = 5,
+  TK_KC_CAND = 6,
+};
+
+struct alignas(128) DequeMeta {
+  int32_t count;   // unclaimed entries (every claim is a CAS on this word)
+  uint32_t head;   // steal end, advanced by the lock holder after loading
+  int32_t lock;    // serialises thieves
+  int32_t pad[29];
+};
+static_assert(sizeof(DequeMeta) == 128, "deque metadata must fill one line");
+
+struct alignas(128) DepotBin {
+  int32_t lock;
+  int32_t nchunks;
+  int32_t pad[30];
+};
+static_assert(sizeof(DepotBin) == 128, "depot bin must fill one line");
+
+// One job (root task).  Written by the host before a run, results by the
+// device.  128 bytes.
+struct alignas(128) JobSlot {
+  uint32_t kind;       // gtap_kind
+  uint32_t done;       // 1 once the root task completed
+  int64_t result;      // root task's return value
+  uint64_t a[8];       // kind arguments (see runtime.hip: pack_args)
+  uint64_t t_done;     // device wall clock at completion
+  uint64_t pad[4];
+};
+static_assert(sizeof(JobSlot) == 128, "job slot is one 128-byte line");
+
+enum StatIdx : uint32_t {
+  ST_TASKS = 0, ST_CONTS, ST_SPAWNS, ST_PUSHED, ST_PUSH_BATCHES, ST_POPPED,
+  ST_POP_BATCHES, ST_STOLEN, ST_STEAL_BATCHES, ST_STEAL_ATTEMPTS, ST_ITERS,
+  ST_IDLE, ST_SPILLS, ST_REFILLS, ST_BUSY_CYCLES, ST_IDLE_CYCLES, ST_COUNT
+};
+
+// Control block: first 4 KB of the workspace.
+struct alignas(128) Control {
+  int32_t jobs_remaining;   // root tasks not yet completed
+  int32_t error;            // first error wins (CAS from 0)
+  int32_t err_pool;
+  int32_t err_wave;
+  int32_t err_job;
+  int32_t pad0[3];
+  uint64_t err_capacity;
+  uint64_t err_requested;
+  uint64_t pad1[12];
+  uint64_t bump_small;      // 128-byte aligned: fresh-frame bump pointers
+  uint64_t pad2[15];
+  uint64_t bump_big;
+  uint64_t pad3[15];
+  uint64_t stats[ST_COUNT];
+};
+
+// Kernel parameters (passed by value).
+struct Params {
+  Control *ctl;
+  JobSlot *jobs;
+  uint32_t njobs;
+  uint32_t nwaves;          // persistent wavefronts in the grid
+  DequeMeta *dq;            // [wave * Q + q]
+  uint32_t *rings;          // [(wave * Q + q) * cap + slot]
+  uint32_t cap;             // deque capacity (power of two)
+  uint32_t Q;               // queues per wave
+  uint32_t *frames_s;       // small frames, 16 words each
+  uint32_t nframes_s;
+  uint32_t *frames_b;       // big frames, stride_b words each
+  uint32_t nframes_b;
+  uint32_t stride_b;        // words per big frame (16 + buffer ints)
+  uint32_t big_ints;        // buffer capacity of a big frame
+  DepotBin *bins_s;
+  uint32_t *store_s;        // [bin * bincap_s + i]
+  uint32_t bincap_s;        // IDs per small bin
+  DepotBin *bins_b;
+  uint32_t *store_b;
+  uint32_t bincap_b;
+  uint32_t steal_below;
+  uint32_t steal_probes;    // victims probed per steal attempt (1..64)
+  uint32_t steal_div;       // claim ceil(count / steal_div), at most 64 - cnt
+  uint32_t daq_policy;
+  int32_t daq_bounds[kMaxQueues - 1];
+  uint64_t timeout_ticks;   // watchdog, device wall-clock ticks
+};
+
+}  // namespace gtap

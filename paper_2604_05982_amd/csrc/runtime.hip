@@ -1,0 +1,461 @@
+// runtime.hip -- host side of the C ABI declared in include/gtap.h.
+//
+// gtap_init lays out one device workspace (frame pools, deques, depot, job
+// table, control block), gtap_submit packs root-task arguments into job
+// slots, gtap_run resets the scheduler state with a small kernel and launches
+// the persistent scheduler kernel once for every pending job on the caller's
+// stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/gtap.h"
+#include "layout.h"
+#include "sched_thread.h"
+
+using namespace gtap;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  size_t ctl, jobs, dq, rings, bins_s, store_s, bins_b, store_b, frames_s, frames_b, total;
+  uint32_t bincap_s, bincap_b, stride_b;
+};
+
+Layout make_layout(const gtap_config &c, uint32_t nwaves) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const size_t nd = static_cast<size_t>(nwaves) * c.num_queues;
+  L.stride_b = align_up(kFrameWords + c.big_frame_ints, 16);  // 64-byte multiples
+  // Depot capacity covers every frame of the pool plus one chunk per bin.
+  L.bincap_s = static_cast<uint32_t>(align_up((c.small_frames + kDepotBins - 1) / kDepotBins + kChunkSmall, kChunkSmall));
+  L.bincap_b = static_cast<uint32_t>(align_up((c.big_frames + kDepotBins - 1) / kDepotBins + kChunkBig, kChunkBig));
+  L.ctl = take(sizeof(Control));
+  L.jobs = take(sizeof(JobSlot) * static_cast<size_t>(c.max_jobs));
+  L.dq = take(sizeof(DequeMeta) * nd);
+  L.rings = take(sizeof(uint32_t) * nd * c.deque_capacity);
+  L.bins_s = take(sizeof(DepotBin) * kDepotBins);
+  L.store_s = take(sizeof(uint32_t) * static_cast<size_t>(kDepotBins) * L.bincap_s);
+  L.bins_b = take(sizeof(DepotBin) * kDepotBins);
+  L.store_b = take(sizeof(uint32_t) * static_cast<size_t>(kDepotBins) * L.bincap_b);
+  L.frames_s = take(sizeof(uint32_t) * kFrameWords * static_cast<size_t>(c.small_frames));
+  L.frames_b = take(sizeof(uint32_t) * static_cast<size_t>(L.stride_b) * c.big_frames);
+  L.total = off;
+  return L;
+}
+
+template <int WPB>
+int occupancy_blocks(int *blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, thread_sched_kernel<WPB>, 64 * WPB, 0) ==
+                 hipSuccess
+             ? 0
+             : -1;
+}
+
+int max_resident_waves(int wpb, uint32_t *out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GTAP_E_HIP;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return GTAP_E_HIP;
+  int bpc = 0, rc = -1;
+  switch (wpb) {
+    case 1: rc = occupancy_blocks<1>(&bpc); break;
+    case 2: rc = occupancy_blocks<2>(&bpc); break;
+    case 4: rc = occupancy_blocks<4>(&bpc); break;
+    case 8: rc = occupancy_blocks<8>(&bpc); break;
+    default: return GTAP_E_INVAL;
+  }
+  if (rc != 0 || bpc <= 0 || ncu <= 0) return GTAP_E_HIP;
+  *out = static_cast<uint32_t>(bpc) * static_cast<uint32_t>(ncu) * static_cast<uint32_t>(wpb);
+  return GTAP_OK;
+}
+
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+int validate(const gtap_config &c) {
+  if (c.mode != GTAP_MODE_THREAD) return GTAP_E_INVAL;
+  if (c.waves_per_group != 1 && c.waves_per_group != 2 && c.waves_per_group != 4 && c.waves_per_group != 8)
+    return GTAP_E_INVAL;
+  if (c.num_waves < 0 || c.num_queues < 1 || c.num_queues > static_cast<int32_t>(kMaxQueues)) return GTAP_E_INVAL;
+  if (c.daq_policy < GTAP_DAQ_NONE || c.daq_policy > GTAP_DAQ_KCLIQUE) return GTAP_E_INVAL;
+  if (!is_pow2(c.deque_capacity) || c.deque_capacity < 128 || c.deque_capacity > (1u << 28)) return GTAP_E_INVAL;
+  if (c.steal_below < 1 || c.steal_below > 64) return GTAP_E_INVAL;
+  if (c.steal_probes < 1 || c.steal_probes > 64 || c.steal_div < 1 || c.steal_div > 64) return GTAP_E_INVAL;
+  if (c.small_frames < 1024 || c.small_frames >= (1ull << 31)) return GTAP_E_INVAL;
+  if (c.big_frames >= (1ull << 31)) return GTAP_E_INVAL;
+  if (c.big_frame_ints > (1u << 24)) return GTAP_E_INVAL;
+  if (c.max_jobs < 1 || c.max_jobs > (1u << 24)) return GTAP_E_INVAL;
+  if (c.flags != 0) return GTAP_E_INVAL;
+  return GTAP_OK;
+}
+
+__global__ void reset_kernel(Params p, uint32_t ndeques) {
+  const size_t i0 = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  for (size_t d = i0; d < ndeques; d += stride) {
+    p.dq[d].count = 0;
+    p.dq[d].head = 0;
+    p.dq[d].lock = 0;
+  }
+  for (size_t b = i0; b < kDepotBins; b += stride) {
+    p.bins_s[b].lock = 0;
+    p.bins_s[b].nchunks = 0;
+    p.bins_b[b].lock = 0;
+    p.bins_b[b].nchunks = 0;
+  }
+  if (i0 == 0) {
+    Control *c = p.ctl;
+    c->jobs_remaining = static_cast<int32_t>(p.njobs);
+    c->error = 0;
+    c->err_pool = 0;
+    c->err_wave = -1;
+    c->err_job = -1;
+    c->err_capacity = 0;
+    c->err_requested = 0;
+    c->bump_small = 0;
+    c->bump_big = 0;
+    for (int s = 0; s < static_cast<int>(ST_COUNT); ++s) c->stats[s] = 0;
+  }
+}
+
+}  // namespace
+
+struct gtap_ctx {
+  gtap_config cfg;
+  hipStream_t stream = nullptr;
+  uint32_t nwaves = 0;
+  Layout lay{};
+  char *ws = nullptr;
+  bool owns_ws = false;
+  Params params{};
+  std::vector<JobSlot> pending;
+  std::vector<JobSlot> done_jobs;
+  uint64_t next_job_id = 0;
+  uint64_t pending_first = 0;
+  uint64_t done_first = 0;
+  bool have_done = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  uint32_t clock_khz = 100000;
+  gtap_stats stats{};
+  gtap_error_report err{};
+};
+
+extern "C" {
+
+void gtap_config_default(gtap_config *cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->mode = GTAP_MODE_THREAD;
+  cfg->num_waves = 0;
+  cfg->waves_per_group = 4;
+  cfg->num_queues = 1;
+  cfg->daq_policy = GTAP_DAQ_NONE;
+  const int32_t bounds[7] = {8, 32, 128, 1 << 30, 1 << 30, 1 << 30, 1 << 30};
+  std::memcpy(cfg->daq_bounds, bounds, sizeof(bounds));
+  cfg->deque_capacity = 1u << 15;
+  cfg->steal_below = 64;
+  cfg->steal_probes = 16;
+  cfg->steal_div = 2;
+  cfg->small_frames = 1ull << 24;
+  cfg->big_frames = 1ull << 16;
+  cfg->big_frame_ints = 512;
+  cfg->max_jobs = 1u << 15;
+  cfg->timeout_ms = 120000;
+}
+
+int gtap_workspace_size(const gtap_config *cfg, uint64_t *bytes) {
+  if (!cfg || !bytes) return GTAP_E_INVAL;
+  int rc = validate(*cfg);
+  if (rc) return rc;
+  uint32_t maxw = 0;
+  rc = max_resident_waves(cfg->waves_per_group, &maxw);
+  if (rc) return rc;
+  uint32_t nw = cfg->num_waves ? std::min<uint32_t>(cfg->num_waves, maxw) : maxw;
+  nw = std::max<uint32_t>(nw / cfg->waves_per_group, 1) * cfg->waves_per_group;
+  *bytes = make_layout(*cfg, nw).total;
+  return GTAP_OK;
+}
+
+int gtap_init(const gtap_config *cfg, gtap_ctx **out) {
+  if (!cfg || !out) return GTAP_E_INVAL;
+  *out = nullptr;
+  int rc = validate(*cfg);
+  if (rc) return rc;
+  uint32_t maxw = 0;
+  rc = max_resident_waves(cfg->waves_per_group, &maxw);
+  if (rc) return rc;
+  gtap_ctx *c = new (std::nothrow) gtap_ctx();
+  if (!c) return GTAP_E_NOMEM;
+  c->cfg = *cfg;
+  if (c->cfg.timeout_ms == 0) c->cfg.timeout_ms = 120000;
+  c->stream = static_cast<hipStream_t>(cfg->stream);
+  uint32_t nw = cfg->num_waves ? std::min<uint32_t>(cfg->num_waves, maxw) : maxw;
+  nw = std::max<uint32_t>(nw / cfg->waves_per_group, 1) * cfg->waves_per_group;
+  c->nwaves = nw;
+  c->lay = make_layout(c->cfg, nw);
+  if (cfg->workspace_dev) {
+    if (cfg->workspace_bytes < c->lay.total || (reinterpret_cast<uintptr_t>(cfg->workspace_dev) % kAlign)) {
+      delete c;
+      return GTAP_E_NOMEM;
+    }
+    c->ws = static_cast<char *>(cfg->workspace_dev);
+  } else {
+    if (hipMalloc(&c->ws, c->lay.total) != hipSuccess) {
+      delete c;
+      return GTAP_E_NOMEM;
+    }
+    c->owns_ws = true;
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    gtap_finalize(c);
+    return GTAP_E_HIP;
+  }
+  Params &p = c->params;
+  p.ctl = reinterpret_cast<Control *>(c->ws + c->lay.ctl);
+  p.jobs = reinterpret_cast<JobSlot *>(c->ws + c->lay.jobs);
+  p.njobs = 0;
+  p.nwaves = nw;
+  p.dq = reinterpret_cast<DequeMeta *>(c->ws + c->lay.dq);
+  p.rings = reinterpret_cast<uint32_t *>(c->ws + c->lay.rings);
+  p.cap = c->cfg.deque_capacity;
+  p.Q = static_cast<uint32_t>(c->cfg.num_queues);
+  p.frames_s = reinterpret_cast<uint32_t *>(c->ws + c->lay.frames_s);
+  p.nframes_s = static_cast<uint32_t>(c->cfg.small_frames);
+  p.frames_b = reinterpret_cast<uint32_t *>(c->ws + c->lay.frames_b);
+  p.nframes_b = static_cast<uint32_t>(c->cfg.big_frames);
+  p.stride_b = c->lay.stride_b;
+  p.big_ints = c->cfg.big_frame_ints;
+  p.bins_s = reinterpret_cast<DepotBin *>(c->ws + c->lay.bins_s);
+  p.store_s = reinterpret_cast<uint32_t *>(c->ws + c->lay.store_s);
+  p.bincap_s = c->lay.bincap_s;
+  p.bins_b = reinterpret_cast<DepotBin *>(c->ws + c->lay.bins_b);
+  p.store_b = reinterpret_cast<uint32_t *>(c->ws + c->lay.store_b);
+  p.bincap_b = c->lay.bincap_b;
+  p.steal_below = c->cfg.steal_below;
+  p.steal_probes = c->cfg.steal_probes;
+  p.steal_div = c->cfg.steal_div;
+  p.daq_policy = static_cast<uint32_t>(c->cfg.daq_policy);
+  for (uint32_t i = 0; i < kMaxQueues - 1; ++i) p.daq_bounds[i] = c->cfg.daq_bounds[i];
+  int dev = 0, rate_khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
+    rate_khz = 100000;  // gfx9 constant clock: 100 MHz
+  c->clock_khz = static_cast<uint32_t>(rate_khz);
+  p.timeout_ticks = static_cast<uint64_t>(c->cfg.timeout_ms) * static_cast<uint64_t>(rate_khz);
+  c->stats.num_waves = static_cast<int32_t>(nw);
+  c->stats.waves_per_group = c->cfg.waves_per_group;
+  c->stats.num_queues = c->cfg.num_queues;
+  *out = c;
+  return GTAP_OK;
+}
+
+int gtap_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, uint64_t *job_id) {
+  if (!c || !args) return GTAP_E_INVAL;
+  if (c->pending.size() >= c->cfg.max_jobs) return GTAP_E_FULL;
+  JobSlot J;
+  std::memset(&J, 0, sizeof(J));
+  J.kind = static_cast<uint32_t>(kind);
+  switch (kind) {
+    case GTAP_KIND_FIB: {
+      if (args_bytes != sizeof(gtap_fib_args)) return GTAP_E_INVAL;
+      gtap_fib_args a;
+      std::memcpy(&a, args, sizeof(a));
+      if (a.n < 0 || a.n > 92) return GTAP_E_INVAL;
+      J.a[0] = static_cast<uint64_t>(a.n);
+      break;
+    }
+    case GTAP_KIND_NQUEENS: {
+      if (args_bytes != sizeof(gtap_nqueens_args)) return GTAP_E_INVAL;
+      gtap_nqueens_args a;
+      std::memcpy(&a, args, sizeof(a));
+      if (a.n < 1 || a.n > 31) return GTAP_E_INVAL;
+      J.a[0] = static_cast<uint64_t>(a.n);
+      J.a[1] = (1ull << a.n) - 1ull;
+      break;
+    }
+    case GTAP_KIND_UTS: {
+      if (args_bytes != sizeof(gtap_uts_args)) return GTAP_E_INVAL;
+      gtap_uts_args a;
+      std::memcpy(&a, args, sizeof(a));
+      if (a.max_depth < 0 || a.max_depth > 255) return GTAP_E_INVAL;
+      J.a[0] = a.seed;
+      J.a[1] = a.threshold;
+      J.a[2] = static_cast<uint64_t>(a.max_depth);
+      break;
+    }
+    case GTAP_KIND_KCLIQUE: {
+      if (args_bytes != sizeof(gtap_kclique_args)) return GTAP_E_INVAL;
+      gtap_kclique_args a;
+      std::memcpy(&a, args, sizeof(a));
+      if (a.n < 0 || a.k < 1 || a.range_leaf < 1 || a.max_outdeg < 0) return GTAP_E_INVAL;
+      if (a.n > 0 && (!a.row_ptr_dev || !a.col_dev)) return GTAP_E_INVAL;
+      // candidate tasks at level >= 2 keep C' in a big frame (k >= 4)
+      if (a.k >= 4 && static_cast<uint32_t>(a.max_outdeg) > c->cfg.big_frame_ints) return GTAP_E_INVAL;
+      if (a.k >= 4 && c->cfg.big_frames == 0) return GTAP_E_INVAL;
+      J.a[0] = reinterpret_cast<uint64_t>(a.row_ptr_dev);
+      J.a[1] = reinterpret_cast<uint64_t>(a.col_dev);
+      J.a[2] = static_cast<uint64_t>(a.n);
+      J.a[3] = static_cast<uint64_t>(a.k);
+      J.a[4] = static_cast<uint64_t>(a.range_leaf);
+      J.a[5] = static_cast<uint64_t>(a.max_outdeg);
+      break;
+    }
+    default:
+      return GTAP_E_INVAL;
+  }
+  if (c->pending.empty()) c->pending_first = c->next_job_id;
+  c->pending.push_back(J);
+  if (job_id) *job_id = c->next_job_id;
+  c->next_job_id++;
+  return GTAP_OK;
+}
+
+static int launch_sched(gtap_ctx *c) {
+  const uint32_t wpb = static_cast<uint32_t>(c->cfg.waves_per_group);
+  const dim3 grid(c->nwaves / wpb), block(64 * wpb);
+  switch (wpb) {
+    case 1: hipLaunchKernelGGL(thread_sched_kernel<1>, grid, block, 0, c->stream, c->params); break;
+    case 2: hipLaunchKernelGGL(thread_sched_kernel<2>, grid, block, 0, c->stream, c->params); break;
+    case 4: hipLaunchKernelGGL(thread_sched_kernel<4>, grid, block, 0, c->stream, c->params); break;
+    case 8: hipLaunchKernelGGL(thread_sched_kernel<8>, grid, block, 0, c->stream, c->params); break;
+    default: return GTAP_E_INVAL;
+  }
+  return hipGetLastError() == hipSuccess ? GTAP_OK : GTAP_E_HIP;
+}
+
+int gtap_run(gtap_ctx *c) {
+  if (!c) return GTAP_E_INVAL;
+  const size_t nj = c->pending.size();
+  c->err = gtap_error_report{};
+  if (nj == 0) return GTAP_OK;
+  Params &p = c->params;
+  p.njobs = static_cast<uint32_t>(nj);
+  if (hipMemcpyAsync(p.jobs, c->pending.data(), nj * sizeof(JobSlot), hipMemcpyHostToDevice, c->stream) !=
+      hipSuccess)
+    return GTAP_E_HIP;
+  const uint32_t ndq = c->nwaves * p.Q;
+  hipLaunchKernelGGL(reset_kernel, dim3(std::max<uint32_t>((ndq + 255) / 256, 1)), dim3(256), 0, c->stream, p,
+                     ndq);
+  if (hipGetLastError() != hipSuccess) return GTAP_E_HIP;
+  if (hipEventRecord(c->ev0, c->stream) != hipSuccess) return GTAP_E_HIP;
+  int rc = launch_sched(c);
+  if (rc) return rc;
+  if (hipEventRecord(c->ev1, c->stream) != hipSuccess) return GTAP_E_HIP;
+  c->done_jobs.resize(nj);
+  Control ctl;
+  if (hipMemcpyAsync(c->done_jobs.data(), p.jobs, nj * sizeof(JobSlot), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return GTAP_E_HIP;
+  if (hipMemcpyAsync(&ctl, p.ctl, sizeof(Control), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return GTAP_E_HIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return GTAP_E_HIP;
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+  c->done_first = c->pending_first;
+  c->pending.clear();
+  c->have_done = true;
+
+  gtap_stats &s = c->stats;
+  s.tasks = ctl.stats[ST_TASKS];
+  s.conts = ctl.stats[ST_CONTS];
+  s.spawns = ctl.stats[ST_SPAWNS];
+  s.pushed = ctl.stats[ST_PUSHED];
+  s.push_batches = ctl.stats[ST_PUSH_BATCHES];
+  s.popped = ctl.stats[ST_POPPED];
+  s.pop_batches = ctl.stats[ST_POP_BATCHES];
+  s.stolen = ctl.stats[ST_STOLEN];
+  s.steal_batches = ctl.stats[ST_STEAL_BATCHES];
+  s.steal_attempts = ctl.stats[ST_STEAL_ATTEMPTS];
+  s.iterations = ctl.stats[ST_ITERS];
+  s.idle_iterations = ctl.stats[ST_IDLE];
+  s.small_frames_touched = ctl.bump_small;
+  s.big_frames_touched = ctl.bump_big;
+  s.depot_spills = ctl.stats[ST_SPILLS];
+  s.depot_refills = ctl.stats[ST_REFILLS];
+  s.busy_cycles = ctl.stats[ST_BUSY_CYCLES];
+  s.idle_cycles = ctl.stats[ST_IDLE_CYCLES];
+  s.kernel_ms = ms;
+
+  if (ctl.error != 0) {
+    c->err.code = ctl.error;
+    c->err.pool = ctl.err_pool;
+    c->err.capacity = ctl.err_capacity;
+    c->err.requested = ctl.err_requested;
+    c->err.wave = ctl.err_wave;
+    c->err.job = ctl.err_job;
+    c->have_done = false;
+    return ctl.error;
+  }
+  for (size_t j = 0; j < nj; ++j)
+    if (c->done_jobs[j].done != 1) {
+      c->have_done = false;
+      return GTAP_E_STATE;
+    }
+  return GTAP_OK;
+}
+
+int gtap_result(gtap_ctx *c, uint64_t job_id, void *out, size_t out_bytes) {
+  if (!c || !out || out_bytes < sizeof(int64_t)) return GTAP_E_INVAL;
+  if (c->have_done && job_id >= c->done_first && job_id < c->done_first + c->done_jobs.size()) {
+    const JobSlot &J = c->done_jobs[job_id - c->done_first];
+    std::memcpy(out, &J.result, sizeof(int64_t));
+    return GTAP_OK;
+  }
+  if (!c->pending.empty() && job_id >= c->pending_first && job_id < c->pending_first + c->pending.size())
+    return GTAP_E_PENDING;
+  if (job_id < c->next_job_id) return GTAP_E_PENDING;
+  return GTAP_E_NOJOB;
+}
+
+int gtap_finalize(gtap_ctx *c) {
+  if (!c) return GTAP_E_INVAL;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->owns_ws && c->ws) (void)hipFree(c->ws);
+  delete c;
+  return GTAP_OK;
+}
+
+int gtap_stats_get(gtap_ctx *c, gtap_stats *out) {
+  if (!c || !out) return GTAP_E_INVAL;
+  *out = c->stats;
+  return GTAP_OK;
+}
+
+int gtap_last_error(gtap_ctx *c, gtap_error_report *out) {
+  if (!c || !out) return GTAP_E_INVAL;
+  *out = c->err;
+  return GTAP_OK;
+}
+
+const char *gtap_status_string(int32_t s) {
+  switch (s) {
+    case GTAP_OK: return "ok";
+    case GTAP_E_INVAL: return "invalid argument";
+    case GTAP_E_NOMEM: return "out of device memory or workspace too small";
+    case GTAP_E_HIP: return "HIP runtime error";
+    case GTAP_E_STATE: return "invalid state";
+    case GTAP_E_FULL: return "too many pending jobs";
+    case GTAP_E_CAPACITY: return "frame pool or deque capacity exhausted";
+    case GTAP_E_PENDING: return "job not completed";
+    case GTAP_E_TIMEOUT: return "device watchdog expired";
+    case GTAP_E_NOJOB: return "unknown job";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,675 @@
+// sched_thread.h -- persistent thread-mode scheduler for gfx950.
+//
+// Each 64-lane wavefront is one scheduler (GTaP Sec. 5.1.1, Algorithm 1,
+// with a warp of 32 replaced by a wavefront of 64):
+//   loop: top up the lanes [cnt,64) by a batched pop from the own deque, then
+//         by a batched steal from a random victim; run one task per lane;
+//         retain up to 64 of the task IDs made runnable in this iteration
+//         (resumed parents first, then new children) and publish the rest
+//         with one batched push; exit once every job's root has completed.
+// Deques follow Sec. 5.1.3: a ring of task IDs with `head` (steal end) and
+// `count` (unclaimed entries) in global memory, the owner-only `tail` in LDS,
+// a lock per deque for thieves; every claim is a CAS on `count`; a push makes
+// its slot stores complete before raising `count`; a thief advances `head`
+// only after its slot loads have returned; the owner's capacity check uses
+// head/tail.  "Complete before" is drain() over device-coherent accesses
+// (see wave.h), not an L2 writeback fence.
+//
+// Frames come from two pools (64-byte frames; big frames that carry an int32
+// buffer).  Each wavefront keeps a free stack per pool in LDS, spills and
+// refills fixed-size chunks through a depot of locked bins in global memory,
+// and takes never-used frames from a bump pointer.  Capacity exhaustion sets
+// a device error word and every wavefront leaves the loop (Sec. 4: overflow
+// aborts with a structured report).
+#pragma once
+#include "layout.h"
+#include "tasks.h"
+#include "wave.h"
+
+namespace gtap {
+
+constexpr uint32_t kPushSpinLimit = 1u << 16;
+constexpr uint32_t kDescStride = 10;   // LDS words per lane: parent, job, ckind, d[0..5]
+
+struct WaveLds {
+  uint32_t stk_s[kStackSmall];
+  uint32_t stk_b[kStackBig];
+  uint32_t offs_s[kWave + 1];
+  uint32_t offs_b[kWave + 1];
+  uint32_t desc[kWave * kDescStride];
+  uint32_t res[kWave];
+  uint32_t tail[kMaxQueues];
+  uint32_t hint[kMaxQueues];   // 0: own deque q certainly has nothing to pop
+  uint32_t head_seen[kMaxQueues];  // last head read by the owner (a lower bound)
+  int32_t sz_s;
+  int32_t sz_b;
+  uint64_t stats[ST_COUNT];
+};
+
+// Per-wave statistics live in LDS (wave-uniform adds; lane 0 writes).
+struct WaveCounters {
+  uint64_t *v;
+  GTAP_DEV void add(uint32_t i, uint64_t x) {
+    if (lane_id() == 0) v[i] += x;
+  }
+};
+
+GTAP_DEV void raise_error(const Params &p, int32_t code, int32_t pool, uint64_t cap,
+                          uint64_t req, uint32_t wave, int32_t job) {
+  int32_t zero = 0;
+  if (cas_relaxed(&p.ctl->error, &zero, code)) {
+    st_relaxed(&p.ctl->err_pool, pool);
+    st_relaxed(&p.ctl->err_wave, static_cast<int32_t>(wave));
+    st_relaxed(&p.ctl->err_job, job);
+    st_relaxed(&p.ctl->err_capacity, cap);
+    st_relaxed(&p.ctl->err_requested, req);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Frame pools.
+struct PoolView {
+  uint32_t *stk;        // LDS free stack
+  int32_t *sz;          // LDS stack size
+  uint32_t stk_cap;
+  uint32_t chunk;
+  DepotBin *bins;
+  uint32_t *store;
+  uint32_t bincap;      // IDs per bin
+  uint64_t *bump;
+  uint32_t nframes;
+  uint32_t tag;         // kBigBit for the big pool
+  int32_t pool_id;
+};
+
+GTAP_DEV PoolView small_pool(const Params &p, WaveLds &L) {
+  return PoolView{L.stk_s, &L.sz_s, kStackSmall, kChunkSmall, p.bins_s, p.store_s,
+                  p.bincap_s, &p.ctl->bump_small, p.nframes_s, 0u, 0};
+}
+GTAP_DEV PoolView big_pool(const Params &p, WaveLds &L) {
+  return PoolView{L.stk_b, &L.sz_b, kStackBig, kChunkBig, p.bins_b, p.store_b,
+                  p.bincap_b, &p.ctl->bump_big, p.nframes_b, kBigBit, 1};
+}
+
+// Lock a depot bin (lane 0 probes up to `probes` bins from the wave's home
+// bin).  want_room: the bin must have room for a chunk, else it must hold one.
+// Returns the bin and its chunk count, or kNone.
+GTAP_DEV uint32_t depot_lock(const PoolView &P, uint32_t me, bool want_room, uint32_t probes,
+                             int32_t &nch_out) {
+  const int32_t maxchunks = static_cast<int32_t>(P.bincap / P.chunk);
+  uint32_t got = kNone;
+  int32_t nch = 0;
+  if (lane_id() == 0) {
+    for (uint32_t t = 0; t < probes; ++t) {
+      const uint32_t b = (me + t) % kDepotBins;
+      DepotBin *bin = P.bins + b;
+      const int32_t seen = ld_relaxed(&bin->nchunks);
+      if (want_room ? seen >= maxchunks : seen <= 0) continue;
+      int32_t z = 0;
+      if (!cas_relaxed(&bin->lock, &z, 1)) continue;
+      nch = ld_relaxed(&bin->nchunks);
+      if (want_room ? nch < maxchunks : nch > 0) {
+        got = b;
+        break;
+      }
+      st_relaxed(&bin->lock, 0);
+    }
+  }
+  nch_out = uniform(nch);
+  return uniform(got);
+}
+
+GTAP_DEV void depot_unlock(const PoolView &P, uint32_t bin, int32_t nchunks) {
+  drain();  // chunk slot accesses complete before the count and lock change
+  if (lane_id() == 0) {
+    st_relaxed(&P.bins[bin].nchunks, nchunks);
+    drain();
+    st_relaxed(&P.bins[bin].lock, 0);
+  }
+}
+
+// Move one chunk from the top of the local stack into a depot bin.  Returns
+// false if no bin took it (the IDs then stay on the stack).
+GTAP_DEV bool depot_spill(const PoolView &P, uint32_t me, WaveCounters &wc) {
+  const uint32_t ln = lane_id();
+  const int32_t sz = *P.sz;
+  int32_t nch = 0;
+  const uint32_t got = depot_lock(P, me, true, kDepotBins, nch);
+  if (got == kNone) return false;
+  uint32_t *dst = P.store + static_cast<size_t>(got) * P.bincap + static_cast<size_t>(nch) * P.chunk;
+  for (uint32_t i = ln; i < P.chunk; i += kWave) co_st32(dst + i, P.stk[sz - static_cast<int32_t>(P.chunk) + i]);
+  depot_unlock(P, got, nch + 1);
+  wave_sync();
+  *P.sz = sz - static_cast<int32_t>(P.chunk);
+  wc.add(ST_SPILLS, 1);
+  return true;
+}
+
+// Pull one chunk from a depot bin onto the local stack.  `all` probes every
+// bin, otherwise only a few from the wavefront's home bin.
+GTAP_DEV bool depot_refill(const PoolView &P, uint32_t me, bool all, WaveCounters &wc) {
+  const uint32_t ln = lane_id();
+  const int32_t sz = *P.sz;
+  if (sz + static_cast<int32_t>(P.chunk) > static_cast<int32_t>(P.stk_cap)) return false;
+  int32_t nch = 0;
+  const uint32_t got = depot_lock(P, me, false, all ? kDepotBins : 4u, nch);
+  if (got == kNone) return false;
+  const uint32_t *src = P.store + static_cast<size_t>(got) * P.bincap + static_cast<size_t>(nch - 1) * P.chunk;
+  for (uint32_t i = ln; i < P.chunk; i += kWave) P.stk[sz + i] = co_ld32(src + i);
+  depot_unlock(P, got, nch - 1);
+  wave_sync();
+  *P.sz = sz + static_cast<int32_t>(P.chunk);
+  wc.add(ST_REFILLS, 1);
+  return true;
+}
+
+// Claim `n` fresh frames from the bump pointer; returns the first index or
+// kNone when the pool has fewer than n untouched frames left.
+GTAP_DEV uint32_t bump_claim(const PoolView &P, uint32_t n) {
+  uint32_t base = kNone;
+  if (lane_id() == 0) {
+    uint64_t cur = ld_relaxed(P.bump);
+    while (cur + n <= P.nframes) {
+      if (cas_relaxed(P.bump, &cur, cur + n)) {
+        base = static_cast<uint32_t>(cur);
+        break;
+      }
+    }
+  }
+  return uniform(base);
+}
+
+// Reserve F frame IDs.  Afterwards ID g (0 <= g < F) is
+//   g < taken ? stk[top - 1 - g] : (base + g - taken) | tag,
+// with top the stack size before the call.  Returns false on exhaustion.
+struct AllocResult {
+  int32_t top;
+  uint32_t taken;
+  uint32_t base;
+};
+
+GTAP_DEV bool alloc_frames(const Params &p, const PoolView &P, uint32_t me, uint32_t F,
+                           AllocResult &r, WaveCounters &wc) {
+  if (F == 0) {
+    r.top = *P.sz;
+    r.taken = 0;
+    r.base = 0;
+    return true;
+  }
+  // Prefer recycled frames: refill from nearby bins while short.
+  while (static_cast<uint32_t>(*P.sz) < F) {
+    if (!depot_refill(P, me, false, wc)) break;
+  }
+  int32_t sz = *P.sz;
+  uint32_t taken = static_cast<uint32_t>(sz) < F ? static_cast<uint32_t>(sz) : F;
+  uint32_t rest = F - taken;
+  uint32_t base = 0;
+  if (rest > 0) {
+    base = bump_claim(P, rest);
+    if (base == kNone) {
+      // Pool fully touched: reclaim from every bin before giving up.
+      while (static_cast<uint32_t>(*P.sz) < F) {
+        if (!depot_refill(P, me, true, wc)) break;
+      }
+      sz = *P.sz;
+      taken = static_cast<uint32_t>(sz) < F ? static_cast<uint32_t>(sz) : F;
+      rest = F - taken;
+      if (rest > 0) {
+        base = bump_claim(P, rest);
+        if (base == kNone) {
+          if (lane_id() == 0)
+            raise_error(p, -6 /*GTAP_E_CAPACITY*/, P.pool_id, P.nframes, F, me, -1);
+          return false;
+        }
+      }
+    }
+  }
+  r.top = sz;
+  r.taken = taken;
+  r.base = base;
+  wave_sync();
+  *P.sz = sz - static_cast<int32_t>(taken);
+  return true;
+}
+
+GTAP_DEV uint32_t alloc_id(const PoolView &P, const AllocResult &r, uint32_t g) {
+  return g < r.taken ? P.stk[r.top - 1 - static_cast<int32_t>(g)] : ((r.base + (g - r.taken)) | P.tag);
+}
+
+// Push the frame of every lane with `mine` set onto its pool's free stack.
+GTAP_DEV void free_frames(const PoolView &P, uint32_t me, bool mine, uint32_t id, WaveCounters &wc) {
+  const uint64_t m = ballot(mine);
+  const uint32_t n = __popcll(m);
+  if (n == 0) return;
+  if (*P.sz + static_cast<int32_t>(n) > static_cast<int32_t>(P.stk_cap)) {
+    if (!depot_spill(P, me, wc)) return;  // no bin took a chunk: these frames are not reused
+  }
+  const int32_t sz = *P.sz;
+  if (mine) P.stk[sz + static_cast<int32_t>(rank_below(m))] = id;
+  wave_sync();
+  *P.sz = sz + static_cast<int32_t>(n);
+}
+
+// ---------------------------------------------------------------------------
+// Deques.
+GTAP_DEV DequeMeta *deque_meta(const Params &p, uint32_t wave, uint32_t q) {
+  return p.dq + static_cast<size_t>(wave) * p.Q + q;
+}
+GTAP_DEV uint32_t *deque_ring(const Params &p, uint32_t wave, uint32_t q) {
+  return p.rings + (static_cast<size_t>(wave) * p.Q + q) * p.cap;
+}
+
+// PopBatch (Algorithm 2): claim up to 64-cnt IDs from the tail of own deque q.
+GTAP_DEV uint32_t pop_batch(const Params &p, WaveLds &L, uint32_t me, uint32_t q, uint32_t cnt,
+                            uint32_t &tid, WaveCounters &wc) {
+  // Only the owner raises count, so once a pop found it empty (or took all of
+  // it) nothing can be popped until the owner pushes again.
+  if (L.hint[q] == 0) return 0;
+  DequeMeta *m = deque_meta(p, me, q);
+  const uint32_t ln = lane_id();
+  const int32_t want = static_cast<int32_t>(kWave - cnt);
+  int32_t claim = 0;
+  uint32_t drained = 0;
+  if (ln == 0) {
+    int32_t c = ld_relaxed(&m->count);
+    for (;;) {
+      if (c <= 0) {
+        drained = 1;
+        break;
+      }
+      const int32_t take = c < want ? c : want;
+      if (cas_relaxed(&m->count, &c, c - take)) {
+        claim = take;
+        drained = (take == c) ? 1u : 0u;
+        break;
+      }
+    }
+  }
+  claim = uniform(claim);
+  if (uniform(drained)) {
+    wave_sync();
+    if (ln == 0) L.hint[q] = 0;
+    wave_sync();
+  }
+  if (claim == 0) return 0;
+  const uint32_t t = L.tail[q] - static_cast<uint32_t>(claim);
+  const uint32_t *ring = deque_ring(p, me, q);
+  if (ln >= cnt && ln < cnt + static_cast<uint32_t>(claim)) tid = co_ld32(ring + ((t + ln - cnt) & (p.cap - 1)));
+  wave_sync();
+  if (ln == 0) L.tail[q] = t;
+  wave_sync();
+  wc.add(ST_POPPED, static_cast<uint32_t>(claim));
+  wc.add(ST_POP_BATCHES, 1);
+  return static_cast<uint32_t>(claim);
+}
+
+// StealBatch.  Lanes [0, steal_probes) each read the count of one random
+// victim's deque q in a single round trip; the fullest victim is locked, a
+// share of its entries is claimed by CAS on count, the IDs are loaded from
+// head, then head advances and the lock is released.
+GTAP_DEV uint32_t steal_batch(const Params &p, uint32_t me, uint32_t &rng, uint32_t q, uint32_t cnt,
+                              uint32_t &tid, WaveCounters &wc) {
+  const uint32_t ln = lane_id();
+  wc.add(ST_STEAL_ATTEMPTS, 1);
+  // per-lane victim from the wave's xorshift state and the lane index
+  const uint32_t base = xorshift32(rng);
+  uint32_t v = (base + ln * 0x9E3779B9u) ^ (ln * 0x85EBCA6Bu);
+  v ^= v >> 15;
+  v *= 0x2C1B3C6Du;
+  v ^= v >> 12;
+  v = v % (p.nwaves - 1);
+  if (v >= me) ++v;
+  int32_t c = 0;
+  if (ln < p.steal_probes) c = ld_relaxed(&deque_meta(p, v, q)->count);
+  // wave arg-max of the observed counts
+  uint32_t key = c > 0 ? ((static_cast<uint32_t>(c < (1 << 24) ? c : (1 << 24) - 1) << 6) | ln) : 0u;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint32_t other = __shfl_xor(key, d, 64);
+    key = other > key ? other : key;
+  }
+  key = uniform(key);
+  if (key == 0) return 0;
+  const uint32_t victim = uniform(static_cast<uint32_t>(__shfl(static_cast<int>(v), static_cast<int>(key & 63u), 64)));
+  DequeMeta *m = deque_meta(p, victim, q);
+  const int32_t want = static_cast<int32_t>(kWave - cnt);
+  int32_t claim = 0;
+  uint32_t h = 0;
+  if (ln == 0) {
+    int32_t z = 0;
+    if (cas_relaxed(&m->lock, &z, 1)) {
+      int32_t cc = static_cast<int32_t>(key >> 6);
+      h = ld_relaxed(&m->head);  // stable while we hold the lock
+      while (cc > 0) {
+        int32_t take = (cc + static_cast<int32_t>(p.steal_div) - 1) / static_cast<int32_t>(p.steal_div);
+        take = take < want ? take : want;
+        if (cas_relaxed(&m->count, &cc, cc - take)) {
+          claim = take;
+          break;
+        }
+      }
+      if (claim == 0) st_relaxed(&m->lock, 0);
+    }
+  }
+  claim = uniform(claim);
+  if (claim == 0) return 0;
+  h = uniform(h);
+  const uint32_t *ring = deque_ring(p, victim, q);
+  if (ln >= cnt && ln < cnt + static_cast<uint32_t>(claim)) tid = co_ld32(ring + ((h + ln - cnt) & (p.cap - 1)));
+  drain();  // slot loads returned before head moves past them
+  if (ln == 0) {
+    st_relaxed(&m->head, h + static_cast<uint32_t>(claim));
+    drain();
+    st_relaxed(&m->lock, 0);
+  }
+  wc.add(ST_STOLEN, static_cast<uint32_t>(claim));
+  wc.add(ST_STEAL_BATCHES, 1);
+  return static_cast<uint32_t>(claim);
+}
+
+// PushBatch: write n IDs at the tail of own deque q, drain, raise count once.
+template <class IdFn>
+GTAP_DEV bool push_batch(const Params &p, WaveLds &L, uint32_t me, uint32_t q, uint32_t n,
+                         IdFn id_of, WaveCounters &wc) {
+  if (n == 0) return true;
+  DequeMeta *m = deque_meta(p, me, q);
+  const uint32_t ln = lane_id();
+  const uint32_t t = L.tail[q];
+  uint32_t ok = 1;
+  // head only grows, so a stale copy makes the capacity check conservative;
+  // reload it only when the check fails.
+  if (t + n - L.head_seen[q] > p.cap) {
+    uint32_t h = 0;
+    if (ln == 0) {
+      h = ld_relaxed(&m->head);
+      uint32_t spins = 0;
+      while (t + n - h > p.cap) {
+        if (++spins > kPushSpinLimit) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        h = ld_relaxed(&m->head);
+      }
+    }
+    ok = uniform(ok);
+    h = uniform(h);
+    wave_sync();
+    if (ln == 0) L.head_seen[q] = h;
+    wave_sync();
+  }
+  if (!ok) {
+    if (ln == 0) raise_error(p, -6 /*GTAP_E_CAPACITY*/, 2, p.cap, n, me, -1);
+    return false;
+  }
+  uint32_t *ring = deque_ring(p, me, q);
+  for (uint32_t i = ln; i < n; i += kWave) co_st32(ring + ((t + i) & (p.cap - 1)), id_of(i));
+  wave_sync();
+  if (ln == 0) {
+    L.tail[q] = t + n;
+    L.hint[q] = 1;
+  }
+  drain();  // slots (and the frames they name) complete before count rises
+  if (ln == 0) fetch_add_relaxed(&m->count, static_cast<int32_t>(n));
+  wave_sync();
+  wc.add(ST_PUSHED, n);
+  wc.add(ST_PUSH_BATCHES, 1);
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Largest index l in [0,64) with offs[l] <= g (offs ascending, offs[64] = F > g).
+GTAP_DEV uint32_t owner_of(const uint32_t *offs, uint32_t g) {
+  uint32_t lo = 0, hi = kWave;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (offs[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Root frame of job j (payload from the job's arguments).
+GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
+  const JobSlot &J = p.jobs[j];
+  ChildInit c;
+  for (uint32_t i = 0; i < kPayloadWords; ++i) c.p[i] = 0;
+  uint32_t kind = TK_FIB;
+  switch (J.kind) {
+    case 1:  // fib
+      kind = TK_FIB;
+      c.p[0] = static_cast<uint32_t>(J.a[0]);
+      break;
+    case 2:  // n-queens: empty board
+      kind = TK_NQ;
+      break;
+    case 3: {  // uts: root id = mix64(seed), depth 0
+      kind = TK_UTS;
+      const uint64_t rid = mix64(J.a[0]);
+      c.p[0] = static_cast<uint32_t>(rid);
+      c.p[1] = static_cast<uint32_t>(rid >> 32);
+      break;
+    }
+    case 4:  // k-clique: the whole vertex range
+      kind = TK_KC_RANGE;
+      c.p[0] = 0;
+      c.p[1] = static_cast<uint32_t>(J.a[2]);
+      break;
+    default:
+      break;
+  }
+  write_frame(frame_ptr(p, id), kNone, j, state_word(kind, 0, 0), c);
+}
+
+// ---------------------------------------------------------------------------
+// Staged IDs S = res[0..nres) ++ small children ++ big children.
+struct Staged {
+  uint32_t nres, Fs, Fb;
+  AllocResult as, ab;
+};
+
+GTAP_DEV uint32_t staged_id(const WaveLds &L, const PoolView &PS, const PoolView &PB,
+                            const Staged &S, uint32_t i) {
+  if (i < S.nres) return L.res[i];
+  i -= S.nres;
+  if (i < S.Fs) return alloc_id(PS, S.as, i);
+  return alloc_id(PB, S.ab, i - S.Fs);
+}
+
+template <int WPB>
+__global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
+  __shared__ WaveLds lds_all[WPB];
+  const uint32_t wv = threadIdx.x >> 6;
+  WaveLds &L = lds_all[wv];
+  const uint32_t me = blockIdx.x * WPB + wv;
+  const uint32_t ln = lane_id();
+  const uint64_t deadline = wall_ticks() + p.timeout_ticks;
+
+  WaveCounters wc{L.stats};
+  if (ln == 0) {
+    for (int i = 0; i < static_cast<int>(ST_COUNT); ++i) L.stats[i] = 0;
+    L.sz_s = 0;
+    L.sz_b = 0;
+    for (uint32_t q = 0; q < kMaxQueues; ++q) {
+      L.tail[q] = 0;
+      L.hint[q] = 0;
+      L.head_seen[q] = 0;
+    }
+  }
+  wave_sync();
+
+  PoolView PS = small_pool(p, L);
+  PoolView PB = big_pool(p, L);
+  uint32_t rng = 0x9E3779B9u ^ (me * 0x85EBCA6Bu + 1u);
+
+  uint32_t cnt = 0;
+  uint32_t tid = kNone;
+  const uint32_t q = 0;  // single queue (DAQ classes select q when enabled)
+
+  // Root admission: job j goes to wave j mod P (the paper's grid leader
+  // enqueues the single root; with many jobs every wave seeds its share).
+  {
+    const uint32_t nroots = me < p.njobs ? (p.njobs - me + p.nwaves - 1) / p.nwaves : 0u;
+    Staged S{};
+    S.nres = 0;
+    S.Fs = nroots;
+    S.Fb = 0;
+    const bool ok = alloc_frames(p, PS, me, nroots, S.as, wc);
+    S.ab = AllocResult{*PB.sz, 0, 0};
+    if (ok && nroots > 0) {
+      for (uint32_t g = ln; g < nroots; g += kWave) write_root(p, alloc_id(PS, S.as, g), me + g * p.nwaves);
+      drain();
+      const uint32_t keep = nroots < kWave ? nroots : kWave;
+      if (ln < keep) tid = staged_id(L, PS, PB, S, ln);
+      cnt = keep;
+      push_batch(p, L, me, q, nroots - keep,
+                 [&](uint32_t i) { return staged_id(L, PS, PB, S, keep + i); }, wc);
+    }
+  }
+
+  uint32_t idle = 0;
+  uint32_t iter = 0;
+  uint64_t t_loop = clock64();
+  for (;;) {
+    // ---- acquire work ----
+    if (cnt < kWave) cnt += pop_batch(p, L, me, q, cnt, tid, wc);
+    if (cnt < p.steal_below && p.nwaves > 1) cnt += steal_batch(p, me, rng, q, cnt, tid, wc);
+    if (cnt == 0) {
+      ++idle;
+      wc.add(ST_IDLE, 1);
+      // termination: every root completed (the implicit join at each task's
+      // end makes a root the last task of its job), an error, or the watchdog
+      uint32_t stop = 0;
+      if ((idle & 3u) == 1u && ln == 0) {
+        if (ld_relaxed(&p.ctl->jobs_remaining) <= 0 || ld_relaxed(&p.ctl->error) != 0) stop = 1;
+        else if (wall_ticks() > deadline) {
+          raise_error(p, -8 /*GTAP_E_TIMEOUT*/, 3, p.timeout_ticks, 0, me, -1);
+          stop = 1;
+        }
+      }
+      if (uniform(stop)) break;
+      backoff_sleep(idle);
+      const uint64_t now = clock64();
+      wc.add(ST_IDLE_CYCLES, now - t_loop);
+      t_loop = now;
+      continue;
+    }
+    idle = 0;
+    ++iter;
+    if ((iter & 63u) == 0) {
+      uint32_t stop = 0;
+      if (ln == 0) {
+        if (ld_relaxed(&p.ctl->error) != 0) stop = 1;
+        else if (wall_ticks() > deadline) {
+          raise_error(p, -8 /*GTAP_E_TIMEOUT*/, 3, p.timeout_ticks, 0, me, -1);
+          stop = 1;
+        }
+      }
+      if (uniform(stop)) break;
+    }
+    wc.add(ST_ITERS, 1);
+
+    // ---- execute one task per lane ----
+    Outcome o;
+    o.type = OUT_NONE;
+    o.nchild = 0;
+    o.big = 0;
+    o.first = 0;
+    if (ln < cnt) exec_task(p, tid, o);
+    const uint32_t nfirst = __popcll(ballot(o.first != 0));
+    wc.add(ST_TASKS, nfirst);
+    wc.add(ST_CONTS, cnt - nfirst);
+
+    // ---- completions, part 1: deliver results (performed by the drain below) ----
+    const bool done = (o.type == OUT_DONE);
+    const bool to_parent = done && o.parent != kNone;
+    if (to_parent && o.value != 0) fetch_add_relaxed(acc_ptr(frame_ptr(p, o.parent)), o.value);
+    if (done && o.parent == kNone) {
+      JobSlot &J = p.jobs[o.job];
+      st_relaxed(&J.result, o.value);
+      st_relaxed(&J.t_done, wall_ticks());
+      st_relaxed(&J.done, 1u);
+    }
+    // the completed frames are dead: recycle them
+    free_frames(PS, me, done && !(tid & kBigBit), tid, wc);
+    free_frames(PB, me, done && (tid & kBigBit), tid, wc);
+
+    // ---- forks: allocate and initialise children, suspend parents ----
+    const bool fork = (o.type == OUT_FORK);
+    const uint32_t fs = (fork && !o.big) ? o.nchild : 0u;
+    const uint32_t fb = (fork && o.big) ? o.nchild : 0u;
+    Staged S;
+    const uint32_t offs = wave_exclusive_scan(fs, &S.Fs);
+    const uint32_t offb = wave_exclusive_scan(fb, &S.Fb);
+    L.offs_s[ln] = offs;
+    L.offs_b[ln] = offb;
+    if (ln == 0) {
+      L.offs_s[kWave] = S.Fs;
+      L.offs_b[kWave] = S.Fb;
+    }
+    if (fork) {
+      uint32_t *dsc = L.desc + ln * kDescStride;
+      dsc[0] = tid;
+      dsc[1] = o.job;
+      dsc[2] = o.ckind;
+      for (int i = 0; i < 6; ++i) dsc[3 + i] = o.d[i];
+    }
+    wave_sync();
+    bool ok = alloc_frames(p, PS, me, S.Fs, S.as, wc);
+    ok = ok && alloc_frames(p, PB, me, S.Fb, S.ab, wc);
+    if (!ok) break;
+    wc.add(ST_SPAWNS, S.Fs + S.Fb);
+    for (uint32_t g = ln; g < S.Fs + S.Fb; g += kWave) {
+      const bool isbig = g >= S.Fs;
+      const uint32_t gg = isbig ? g - S.Fs : g;
+      const uint32_t *offs_arr = isbig ? L.offs_b : L.offs_s;
+      const uint32_t own = owner_of(offs_arr, gg);
+      const uint32_t j = gg - offs_arr[own];
+      const uint32_t *dsc = L.desc + own * kDescStride;
+      ChildInit c;
+      make_child(dsc[2], dsc + 3, j, c);
+      const uint32_t cid = isbig ? alloc_id(PB, S.ab, gg) : alloc_id(PS, S.as, gg);
+      write_frame(frame_ptr(p, cid), dsc[0], dsc[1], state_word(dsc[2], 0, 0), c);
+    }
+    if (fork) {
+      uint32_t *f = frame_ptr(p, tid);
+      co_st32(f + FW_STATE, state_word(o.kind, 1, 0));
+      st_relaxed(acc_ptr(f), static_cast<int64_t>(0));
+      st_relaxed(join_ptr(f), static_cast<int32_t>(o.nchild));
+    }
+    // Results delivered to parents, root results, new children and suspended
+    // parents are all performed before any join counter moves or any ID is
+    // published or retained.
+    drain();
+
+    // ---- completions, part 2: the child that brings join to zero resumes its parent ----
+    uint32_t resumed = kNone;
+    if (to_parent) {
+      const int32_t old = fetch_add_relaxed(join_ptr(frame_ptr(p, o.parent)), -1);
+      if (old == 1) resumed = o.parent;
+    }
+    if (done && o.parent == kNone) fetch_add_relaxed(&p.ctl->jobs_remaining, -1);
+
+    // ---- stage: resumed parents first, then the new children ----
+    const uint64_t m_res = ballot(resumed != kNone);
+    S.nres = __popcll(m_res);
+    if (resumed != kNone) L.res[rank_below(m_res)] = resumed;
+    wave_sync();
+    const uint32_t total = S.nres + S.Fs + S.Fb;
+    const uint32_t keep = total < kWave ? total : kWave;
+    tid = (ln < keep) ? staged_id(L, PS, PB, S, ln) : kNone;
+    cnt = keep;
+    if (!push_batch(p, L, me, q, total - keep,
+                    [&](uint32_t i) { return staged_id(L, PS, PB, S, keep + i); }, wc))
+      break;
+    const uint64_t now = clock64();
+    wc.add(ST_BUSY_CYCLES, now - t_loop);
+    t_loop = now;
+  }
+
+  // ---- flush counters ----
+  wave_sync();
+  if (ln < ST_COUNT && L.stats[ln] != 0) fetch_add_relaxed(&p.ctl->stats[ln], L.stats[ln]);
+}
+
+}  // namespace gtap

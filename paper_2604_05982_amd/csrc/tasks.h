@@ -1,0 +1,329 @@
+// tasks.h -- thread-mode task bodies as hand-written resumable state machines.
+//
+// The paper's compiler turns a pragma-annotated task function into one that
+// stores join-crossing values in its task record and, when re-invoked,
+// switches on the saved resume point (Sec. 5.2).  Here every task kind is
+// written in that lowered form by hand: exec_task() reads the frame, switches
+// on (kind, resume point) and reports one of
+//   OUT_DONE  -- the task returned `value` (to its parent, or as the job result)
+//   OUT_FORK  -- the task spawned `nchild` children described by `d[]` and
+//                suspended at its join; the runtime sets the waiting-child
+//                counter and re-executes the frame at resume point 1 after the
+//                last child completed (Sec. 5.1.2).
+// Children are materialised later, by the whole wavefront, from the
+// descriptor: make_child() builds child j of a forked parent.  A child's
+// arguments are copied into its own frame at spawn time (firstprivate
+// semantics, Sec. 4.1).  Each task has an implicit join at its end, so a
+// parent always completes after all of its children.
+#pragma once
+#include "layout.h"
+#include "wave.h"
+
+namespace gtap {
+
+enum OutType : uint32_t { OUT_NONE = 0, OUT_DONE = 1, OUT_FORK = 2 };
+
+struct Outcome {
+  uint32_t type;
+  uint32_t nchild;   // OUT_FORK: number of children
+  uint32_t big;      // OUT_FORK: children need big frames
+  uint32_t ckind;    // OUT_FORK: children's task kind
+  uint32_t d[6];     // OUT_FORK: child-generation descriptor
+  int64_t value;     // OUT_DONE: return value
+  uint32_t parent;   // parent task ID (kNone for a root)
+  uint32_t job;
+  uint32_t kind;     // this task's kind
+  uint32_t first;    // 1: first execution (resume point 0), 0: continuation
+};
+
+// Payload of a new frame (words 3..7).
+struct ChildInit {
+  uint32_t p[kPayloadWords];
+};
+
+GTAP_DEV uint32_t *frame_ptr(const Params &p, uint32_t tid) {
+  return (tid & kBigBit) ? p.frames_b + static_cast<size_t>(tid & ~kBigBit) * p.stride_b
+                         : p.frames_s + static_cast<size_t>(tid) * kFrameWords;
+}
+GTAP_DEV uint64_t *frame64(uint32_t *f) { return reinterpret_cast<uint64_t *>(f); }
+GTAP_DEV int64_t *acc_ptr(uint32_t *f) { return reinterpret_cast<int64_t *>(f + FW_ACC); }
+GTAP_DEV int32_t *join_ptr(uint32_t *f) { return reinterpret_cast<int32_t *>(f + FW_JOIN); }
+
+GTAP_DEV uint32_t state_word(uint32_t kind, uint32_t pc, uint32_t cls) {
+  return kind | (pc << 8) | (cls << 16);
+}
+GTAP_DEV uint64_t pack(uint32_t lo, uint32_t hi) {
+  return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32);
+}
+
+// Spawn-time frame image: four coherent 64-bit stores.
+GTAP_DEV void write_frame(uint32_t *f, uint32_t parent, uint32_t job, uint32_t state,
+                          const ChildInit &c) {
+  uint64_t *f64 = frame64(f);
+  co_st64(f64 + 0, pack(parent, job));
+  co_st64(f64 + 1, pack(state, c.p[0]));
+  co_st64(f64 + 2, pack(c.p[1], c.p[2]));
+  co_st64(f64 + 3, pack(c.p[3], c.p[4]));
+}
+
+// splitmix64 output function (Steele, Lea, Flood, OOPSLA 2014), from its
+// published definition: add the golden gamma, two xor-shift-multiply rounds,
+// a final xor-shift.
+GTAP_DEV uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// Child i of a node: mix64 of the parent id advanced by (i+1) gammas.
+GTAP_DEV uint64_t split_id(uint64_t a, uint64_t i) { return mix64(a + (i + 1) * 0x9E3779B97F4A7C15ull); }
+
+// Geometric child count: leading draws j = 1, 2, ... whose hash is below thr.
+GTAP_DEV uint32_t uts_children(uint64_t id, uint32_t depth, uint64_t thr, uint32_t max_depth) {
+  if (depth >= max_depth) return 0;
+  uint32_t c = 0;
+  for (uint64_t j = 1;; ++j) {
+    if (mix64(id ^ (j * 0xD1B54A32D192ED03ull)) < thr) ++c;
+    else break;
+  }
+  return c;
+}
+
+// |C /\ B| for an ascending candidate list C (read coherently: it may be a
+// buffer another wavefront wrote) and an ascending CSR list B (read-only
+// input); writes the intersection coherently if out != 0.
+GTAP_DEV uint32_t intersect_sorted(const int32_t *C, uint32_t nc, const int32_t *B, uint32_t nb,
+                                   int32_t *out) {
+  uint32_t i = 0, j = 0, o = 0;
+  if (nc == 0 || nb == 0) return 0;
+  int32_t x = co_ld32i(C), y = B[0];
+  for (;;) {
+    if (x < y) {
+      if (++i == nc) break;
+      x = co_ld32i(C + i);
+    } else if (x > y) {
+      if (++j == nb) break;
+      y = B[j];
+    } else {
+      if (out) co_st32i(out + o, x);
+      ++o;
+      if (++i == nc || ++j == nb) break;
+      x = co_ld32i(C + i);
+      y = B[j];
+    }
+  }
+  return o;
+}
+
+GTAP_DEV const uint64_t *job_args(const Params &p, uint32_t job) { return p.jobs[job].a; }
+
+// ---------------------------------------------------------------------------
+// Execute one task on this lane.
+GTAP_DEV void exec_task(const Params &p, uint32_t tid, Outcome &o) {
+  uint32_t *f = frame_ptr(p, tid);
+  const uint64_t *f64 = frame64(f);
+  const uint64_t w01 = co_ld64(f64 + 0);
+  const uint64_t w23 = co_ld64(f64 + 1);
+  const uint32_t state = static_cast<uint32_t>(w23);
+  const uint32_t kind = state & 0xFFu;
+  const uint32_t pc = (state >> 8) & 0xFFu;
+  o.parent = static_cast<uint32_t>(w01);
+  o.job = static_cast<uint32_t>(w01 >> 32);
+  o.kind = kind;
+  o.first = pc == 0 ? 1u : 0u;
+  o.type = OUT_DONE;
+  o.nchild = 0;
+  o.big = 0;
+  o.value = 0;
+
+  if (pc != 0) {
+    // Continuation after the join: every kind sums its children's results;
+    // a UTS node adds itself.
+    const int64_t acc = ld_relaxed(acc_ptr(f));
+    o.value = (kind == TK_UTS) ? acc + 1 : acc;
+    return;
+  }
+
+  const uint64_t w45 = co_ld64(f64 + 2);
+  const uint64_t w67 = co_ld64(f64 + 3);
+  const uint32_t p0 = static_cast<uint32_t>(w23 >> 32);
+  const uint32_t p1 = static_cast<uint32_t>(w45), p2 = static_cast<uint32_t>(w45 >> 32);
+  const uint32_t p3 = static_cast<uint32_t>(w67), p4 = static_cast<uint32_t>(w67 >> 32);
+  switch (kind) {
+    case TK_FIB: {
+      // fib(n): n < 2 returns n, else spawn fib(n-1), fib(n-2) and join.
+      const uint32_t n = p0;
+      if (n < 2) {
+        o.value = n;
+        return;
+      }
+      o.type = OUT_FORK;
+      o.nchild = 2;
+      o.ckind = TK_FIB;
+      o.d[0] = n;
+      return;
+    }
+    case TK_NQ: {
+      // Rows [0,row) hold queens; one child per unattacked column of `row`.
+      const uint64_t *a = job_args(p, o.job);
+      const uint32_t n = static_cast<uint32_t>(a[0]);
+      const uint32_t full = static_cast<uint32_t>(a[1]);
+      const uint32_t cols = p0, dl = p1, dr = p2, row = p3;
+      if (row == n) {
+        o.value = 1;
+        return;
+      }
+      const uint32_t avail = full & ~(cols | dl | dr);
+      if (avail == 0) return;  // dead end: 0
+      o.type = OUT_FORK;
+      o.nchild = __popc(avail);
+      o.ckind = TK_NQ;
+      o.d[0] = cols; o.d[1] = dl; o.d[2] = dr; o.d[3] = row; o.d[4] = avail; o.d[5] = full;
+      return;
+    }
+    case TK_UTS: {
+      const uint64_t *a = job_args(p, o.job);
+      const uint64_t id = pack(p0, p1);
+      const uint32_t depth = p2;
+      const uint32_t nc = uts_children(id, depth, a[1], static_cast<uint32_t>(a[2]));
+      if (nc == 0) {
+        o.value = 1;
+        return;
+      }
+      o.type = OUT_FORK;
+      o.nchild = nc;
+      o.ckind = TK_UTS;
+      o.d[0] = p0; o.d[1] = p1; o.d[2] = depth;
+      return;
+    }
+    case TK_KC_RANGE: {
+      // Vertex range [lo,hi): halve while larger than range_leaf, else one
+      // vertex task per vertex.
+      const uint64_t *a = job_args(p, o.job);
+      const uint32_t lo = p0, hi = p1;
+      const uint32_t leaf = static_cast<uint32_t>(a[4]);
+      if (hi <= lo) return;
+      o.type = OUT_FORK;
+      o.d[0] = lo; o.d[1] = hi;
+      if (hi - lo > leaf) {
+        o.nchild = 2;
+        o.ckind = TK_KC_RANGE;
+      } else {
+        o.nchild = hi - lo;
+        o.ckind = TK_KC_VERTEX;
+      }
+      return;
+    }
+    case TK_KC_VERTEX: {
+      // K(N+(v), k-1): k = 1 counts the vertex, k = 2 its out-degree, else one
+      // candidate task per out-neighbour with C = N+(v).
+      const uint64_t *a = job_args(p, o.job);
+      const int32_t *rp = reinterpret_cast<const int32_t *>(a[0]);
+      const int32_t *col = reinterpret_cast<const int32_t *>(a[1]);
+      const uint32_t k = static_cast<uint32_t>(a[3]);
+      const uint32_t v = p0;
+      if (k == 1) {
+        o.value = 1;
+        return;
+      }
+      const int32_t s = rp[v], e = rp[v + 1];
+      const uint32_t deg = static_cast<uint32_t>(e - s);
+      if (k == 2) {
+        o.value = deg;
+        return;
+      }
+      if (deg == 0) return;
+      const uint64_t cptr = reinterpret_cast<uint64_t>(col + s);
+      o.type = OUT_FORK;
+      o.nchild = deg;
+      o.ckind = TK_KC_CAND;
+      o.big = (k - 2 >= 2) ? 1u : 0u;
+      o.d[0] = static_cast<uint32_t>(cptr); o.d[1] = static_cast<uint32_t>(cptr >> 32);
+      o.d[2] = deg; o.d[3] = k - 2;
+      return;
+    }
+    case TK_KC_CAND: {
+      // K(C /\ N+(u), l): l = 1 counts the intersection, else stores it in this
+      // frame's buffer and forks one child per element.
+      const uint64_t *a = job_args(p, o.job);
+      const int32_t *rp = reinterpret_cast<const int32_t *>(a[0]);
+      const int32_t *col = reinterpret_cast<const int32_t *>(a[1]);
+      const uint32_t u = p0, l = p1;
+      const int32_t *C = reinterpret_cast<const int32_t *>(pack(p2, p3));
+      const uint32_t nC = p4;
+      const int32_t s = rp[u], e = rp[u + 1];
+      const uint32_t nu = static_cast<uint32_t>(e - s);
+      if (l == 1) {
+        o.value = intersect_sorted(C, nC, col + s, nu, nullptr);
+        return;
+      }
+      int32_t *buf = reinterpret_cast<int32_t *>(f + FW_BUF);
+      const uint32_t m = intersect_sorted(C, nC, col + s, nu, buf);
+      if (m == 0) return;
+      const uint64_t cptr = reinterpret_cast<uint64_t>(buf);
+      o.type = OUT_FORK;
+      o.nchild = m;
+      o.ckind = TK_KC_CAND;
+      o.big = (l - 1 >= 2) ? 1u : 0u;
+      o.d[0] = static_cast<uint32_t>(cptr); o.d[1] = static_cast<uint32_t>(cptr >> 32);
+      o.d[2] = m; o.d[3] = l - 1;
+      return;
+    }
+    default:
+      return;
+  }
+}
+
+GTAP_DEV uint32_t nth_set_bit(uint32_t m, uint32_t j) {
+  for (uint32_t i = 0; i < j; ++i) m &= m - 1;
+  return m & (0u - m);
+}
+
+// Payload of child j of a forked parent with child kind `ckind` and
+// descriptor d.
+GTAP_DEV void make_child(uint32_t ckind, const uint32_t *d, uint32_t j, ChildInit &c) {
+  for (uint32_t i = 0; i < kPayloadWords; ++i) c.p[i] = 0;
+  switch (ckind) {
+    case TK_FIB:
+      c.p[0] = d[0] - 1 - j;
+      break;
+    case TK_NQ: {
+      const uint32_t b = nth_set_bit(d[4], j);
+      const uint32_t full = d[5];
+      c.p[0] = d[0] | b;
+      c.p[1] = ((d[1] | b) << 1) & full;
+      c.p[2] = (d[2] | b) >> 1;
+      c.p[3] = d[3] + 1;
+      break;
+    }
+    case TK_UTS: {
+      const uint64_t cid = split_id(pack(d[0], d[1]), j);
+      c.p[0] = static_cast<uint32_t>(cid);
+      c.p[1] = static_cast<uint32_t>(cid >> 32);
+      c.p[2] = d[2] + 1;
+      break;
+    }
+    case TK_KC_RANGE: {
+      const uint32_t lo = d[0], hi = d[1], mid = lo + (hi - lo) / 2;
+      c.p[0] = j == 0 ? lo : mid;
+      c.p[1] = j == 0 ? mid : hi;
+      break;
+    }
+    case TK_KC_VERTEX:
+      c.p[0] = d[0] + j;
+      break;
+    case TK_KC_CAND: {
+      const int32_t *C = reinterpret_cast<const int32_t *>(pack(d[0], d[1]));
+      c.p[0] = static_cast<uint32_t>(co_ld32i(C + j));
+      c.p[1] = d[3];
+      c.p[2] = d[0];
+      c.p[3] = d[1];
+      c.p[4] = d[2];
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+}  // namespace gtap

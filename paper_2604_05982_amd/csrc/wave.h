@@ -1,0 +1,136 @@
+// wave.h -- wavefront-level primitives and memory-ordering helpers for gfx950.
+//
+// The paper publishes task IDs with a fence before the queue-size update and
+// relies on one L2 shared by every SM as the coherence point (Sec. 2.3,
+// Sec. 5.1.3).  On MI355X each XCD has its own L2, and an agent-scope
+// release/acquire fence is a whole-L2 writeback/invalidate: measured on the
+// device, such fences sustain only ~0.04-0.14 G wave-ops/s chip-wide while
+// device-scope atomic loads, stores and relaxed RMWs sustain 1.4-9 G/s.
+// So the runtime never uses agent-scope fences on its hot path.  Every datum
+// one wavefront hands to another (frames, ring slots, depot chunks, candidate
+// buffers, results) is written with a device-scope coherent store and read
+// with a device-scope coherent load (co_st*/co_ld*: the "sc1" cache policy,
+// performed at the device coherence point), and ordering between such
+// accesses and the publishing RMW comes from drain(): the wavefront waits
+// until every memory operation it issued has completed before issuing the
+// next one.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.h"
+
+#define GTAP_DEV __device__ __forceinline__
+
+namespace gtap {
+
+GTAP_DEV uint32_t lane_id() { return __lane_id(); }
+
+GTAP_DEV uint64_t ballot(bool p) { return __ballot(p); }
+
+// Number of set bits of m in lanes below this one.
+GTAP_DEV uint32_t rank_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+
+// Value of the first active lane (wave-uniform, lives in an SGPR).
+GTAP_DEV uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+GTAP_DEV int32_t uniform(int32_t x) { return static_cast<int32_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x))); }
+GTAP_DEV uint64_t uniform64(uint64_t x) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x));
+  uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Exclusive prefix sum over the 64 lanes; *total = sum over all lanes.
+// Must be called with every lane active.
+GTAP_DEV uint32_t wave_exclusive_scan(uint32_t x, uint32_t *total) {
+  uint32_t s = x;
+  const uint32_t ln = lane_id();
+#pragma unroll
+  for (uint32_t d = 1; d < 64u; d <<= 1) {
+    uint32_t y = __shfl_up(s, d, 64);
+    if (ln >= d) s += y;
+  }
+  *total = __shfl(s, 63, 64);
+  return s - x;
+}
+
+// ---- device-scope atomics (relaxed; ordering comes from drain()) ----------
+template <typename T>
+GTAP_DEV T ld_relaxed(T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+GTAP_DEV void st_relaxed(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+GTAP_DEV T fetch_add_relaxed(T *p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// CAS; on failure *expected receives the current value.
+template <typename T>
+GTAP_DEV bool cas_relaxed(T *p, T *expected, T desired) {
+  return __hip_atomic_compare_exchange_strong(p, expected, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- device-coherent data accesses -----------------------------------------
+GTAP_DEV void co_st32(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+GTAP_DEV void co_st64(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+GTAP_DEV uint32_t co_ld32(const uint32_t *p) {
+  return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+GTAP_DEV int32_t co_ld32i(const int32_t *p) {
+  return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+GTAP_DEV void co_st32i(int32_t *p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+GTAP_DEV uint64_t co_ld64(const uint64_t *p) {
+  return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until every memory operation this wavefront has issued is complete
+// (stores and RMWs performed at their coherence point, loads returned).  The
+// wavefront-scope fences keep the compiler from moving memory accesses across
+// the wait.
+GTAP_DEV void drain() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+// Orders LDS and global accesses between the lanes of one wavefront.
+GTAP_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Constant-rate device clock (rate: hipDeviceAttributeWallClockRate).
+GTAP_DEV uint64_t wall_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+// Idle backoff: s_sleep k waits about 64*k cycles; k is an immediate.
+GTAP_DEV void backoff_sleep(uint32_t n) {
+  if (n < 2) __builtin_amdgcn_s_sleep(2);
+  else if (n < 8) __builtin_amdgcn_s_sleep(8);
+  else if (n < 32) __builtin_amdgcn_s_sleep(24);
+  else __builtin_amdgcn_s_sleep(64);
+}
+
+// xorshift32 step (Marsaglia 2003); wave-uniform state.
+GTAP_DEV uint32_t xorshift32(uint32_t &s) {
+  s ^= s << 13;
+  s ^= s >> 17;
+  s ^= s << 5;
+  return s;
+}
+
+}  // namespace gtap

@@ -1,0 +1,322 @@
+"""Python binding of the C ABI in ``include/gtap.h`` (argument marshalling only).
+
+Every step of the fork-join runtime runs in the HIP library
+``libgtap.so``; this module only converts arguments.  The functions keep the
+C names (``gtap_init``, ``gtap_submit``, ``gtap_run``, ``gtap_result``,
+``gtap_finalize``, ...).  :class:`Runtime` wraps them for convenience and uses
+PyTorch for the two things the runtime borrows from its caller: device memory
+(the workspace tensor, k-clique CSR tensors) and the HIP stream.
+
+If ``libgtap.so`` has not been built this module raises on import: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgtap.so")
+
+# ---- status codes, kinds, modes (mirror include/gtap.h) --------------------
+GTAP_OK = 0
+GTAP_E_INVAL = -1
+GTAP_E_NOMEM = -2
+GTAP_E_HIP = -3
+GTAP_E_STATE = -4
+GTAP_E_FULL = -5
+GTAP_E_CAPACITY = -6
+GTAP_E_PENDING = -7
+GTAP_E_TIMEOUT = -8
+GTAP_E_NOJOB = -9
+
+GTAP_MODE_THREAD = 0
+GTAP_MODE_BLOCK = 1
+
+GTAP_KIND_FIB = 1
+GTAP_KIND_NQUEENS = 2
+GTAP_KIND_UTS = 3
+GTAP_KIND_KCLIQUE = 4
+
+GTAP_DAQ_NONE = 0
+GTAP_DAQ_BY_KIND = 1
+GTAP_DAQ_KCLIQUE = 2
+
+
+class gtap_config(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int32),
+        ("num_waves", ctypes.c_int32),
+        ("waves_per_group", ctypes.c_int32),
+        ("num_queues", ctypes.c_int32),
+        ("daq_policy", ctypes.c_int32),
+        ("daq_bounds", ctypes.c_int32 * 7),
+        ("deque_capacity", ctypes.c_uint32),
+        ("steal_below", ctypes.c_uint32),
+        ("steal_probes", ctypes.c_uint32),
+        ("steal_div", ctypes.c_uint32),
+        ("small_frames", ctypes.c_uint64),
+        ("big_frames", ctypes.c_uint64),
+        ("big_frame_ints", ctypes.c_uint32),
+        ("max_jobs", ctypes.c_uint32),
+        ("timeout_ms", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("stream", ctypes.c_void_p),
+        ("workspace_dev", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_uint64),
+    ]
+
+
+class gtap_fib_args(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class gtap_nqueens_args(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class gtap_uts_args(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("threshold", ctypes.c_uint64),
+                ("max_depth", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class gtap_kclique_args(ctypes.Structure):
+    _fields_ = [("row_ptr_dev", ctypes.c_void_p), ("col_dev", ctypes.c_void_p),
+                ("n", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("range_leaf", ctypes.c_int32), ("max_outdeg", ctypes.c_int32)]
+
+
+class gtap_stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "tasks", "conts", "spawns", "pushed", "push_batches", "popped", "pop_batches",
+        "stolen", "steal_batches", "steal_attempts", "iterations", "idle_iterations",
+        "small_frames_touched", "big_frames_touched", "depot_spills", "depot_refills",
+        "busy_cycles", "idle_cycles")] + [
+        ("kernel_ms", ctypes.c_double),
+        ("num_waves", ctypes.c_int32),
+        ("waves_per_group", ctypes.c_int32),
+        ("num_queues", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class gtap_error_report(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_int32), ("pool", ctypes.c_int32),
+                ("capacity", ctypes.c_uint64), ("requested", ctypes.c_uint64),
+                ("wave", ctypes.c_int32), ("job", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+# ---- library loading --------------------------------------------------------
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP runtime first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.gtap_config_default.argtypes = [P(gtap_config)]
+    lib.gtap_config_default.restype = None
+    lib.gtap_workspace_size.argtypes = [P(gtap_config), P(ctypes.c_uint64)]
+    lib.gtap_init.argtypes = [P(gtap_config), P(vp)]
+    lib.gtap_submit.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_size_t, P(ctypes.c_uint64)]
+    lib.gtap_run.argtypes = [vp]
+    lib.gtap_result.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t]
+    lib.gtap_finalize.argtypes = [vp]
+    lib.gtap_stats_get.argtypes = [vp, P(gtap_stats)]
+    lib.gtap_last_error.argtypes = [vp, P(gtap_error_report)]
+    lib.gtap_status_string.argtypes = [ctypes.c_int32]
+    lib.gtap_status_string.restype = ctypes.c_char_p
+    for fn in ("gtap_workspace_size", "gtap_init", "gtap_submit", "gtap_run", "gtap_result",
+               "gtap_finalize", "gtap_stats_get", "gtap_last_error"):
+        getattr(lib, fn).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+# Names every test checks the library exports (the declarations of gtap.h).
+EXPORTED = ("gtap_config_default", "gtap_workspace_size", "gtap_init", "gtap_submit", "gtap_run",
+            "gtap_result", "gtap_finalize", "gtap_stats_get", "gtap_last_error",
+            "gtap_status_string")
+
+
+class GtapError(RuntimeError):
+    def __init__(self, code: int, what: str, report: Optional[dict] = None):
+        self.code = code
+        self.report = report
+        msg = f"{what}: {gtap_status_string(code)} ({code})"
+        if report:
+            msg += f" report={report}"
+        super().__init__(msg)
+
+
+def gtap_status_string(code: int) -> str:
+    return _lib.gtap_status_string(int(code)).decode()
+
+
+def gtap_config_default() -> gtap_config:
+    cfg = gtap_config()
+    _lib.gtap_config_default(ctypes.byref(cfg))
+    return cfg
+
+
+def gtap_workspace_size(cfg: gtap_config) -> int:
+    out = ctypes.c_uint64(0)
+    rc = _lib.gtap_workspace_size(ctypes.byref(cfg), ctypes.byref(out))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_workspace_size")
+    return int(out.value)
+
+
+def gtap_init(cfg: gtap_config) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    rc = _lib.gtap_init(ctypes.byref(cfg), ctypes.byref(ctx))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_init")
+    return ctx
+
+
+def gtap_submit(ctx, kind: int, args: ctypes.Structure) -> int:
+    jid = ctypes.c_uint64(0)
+    rc = _lib.gtap_submit(ctx, int(kind), ctypes.byref(args), ctypes.sizeof(args), ctypes.byref(jid))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_submit")
+    return int(jid.value)
+
+
+def gtap_last_error(ctx) -> dict:
+    rep = gtap_error_report()
+    _lib.gtap_last_error(ctx, ctypes.byref(rep))
+    return rep.as_dict()
+
+
+def gtap_run(ctx) -> None:
+    rc = _lib.gtap_run(ctx)
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_run", gtap_last_error(ctx))
+
+
+def gtap_result(ctx, job_id: int) -> int:
+    out = ctypes.c_int64(0)
+    rc = _lib.gtap_result(ctx, int(job_id), ctypes.byref(out), ctypes.sizeof(out))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_result")
+    return int(out.value)
+
+
+def gtap_stats_get(ctx) -> dict:
+    st = gtap_stats()
+    rc = _lib.gtap_stats_get(ctx, ctypes.byref(st))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_stats_get")
+    return st.as_dict()
+
+
+def gtap_finalize(ctx) -> None:
+    rc = _lib.gtap_finalize(ctx)
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_finalize")
+
+
+def uts_threshold(m: float) -> int:
+    """floor(2^64 * m / (m+1)): continue-threshold of a geometric law with mean m."""
+    from fractions import Fraction
+    f = Fraction(m).limit_denominator(1 << 20)
+    return int((Fraction(1 << 64) * f) // (f + 1))
+
+
+class Runtime:
+    """One runtime context on the current device, memory and stream from PyTorch."""
+
+    def __init__(self, **overrides):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the GTaP runtime needs a HIP device")
+        self._torch = torch
+        cfg = gtap_config_default()
+        for key, val in overrides.items():
+            if key == "daq_bounds":
+                arr = (ctypes.c_int32 * 7)(*(list(val) + [1 << 30] * (7 - len(val))))
+                cfg.daq_bounds = arr
+            elif hasattr(cfg, key):
+                setattr(cfg, key, val)
+            else:
+                raise TypeError(f"unknown runtime option {key!r}")
+        if cfg.stream is None:
+            cfg.stream = torch.cuda.current_stream().cuda_stream
+        nbytes = gtap_workspace_size(cfg)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        cfg.workspace_dev = self.workspace.data_ptr()
+        cfg.workspace_bytes = nbytes
+        self.cfg = cfg
+        self.ctx = gtap_init(cfg)
+        self._keep = []          # device tensors borrowed by pending jobs
+
+    # -- submission -----------------------------------------------------------
+    def submit_fib(self, n: int) -> int:
+        return gtap_submit(self.ctx, GTAP_KIND_FIB, gtap_fib_args(int(n), 0))
+
+    def submit_nqueens(self, n: int) -> int:
+        return gtap_submit(self.ctx, GTAP_KIND_NQUEENS, gtap_nqueens_args(int(n), 0))
+
+    def submit_uts(self, seed: int, threshold: int, max_depth: int) -> int:
+        return gtap_submit(self.ctx, GTAP_KIND_UTS,
+                           gtap_uts_args(int(seed) & (2**64 - 1), int(threshold), int(max_depth), 0))
+
+    def submit_kclique(self, row_ptr, col, k: int, range_leaf: int = 64,
+                       max_outdeg: Optional[int] = None) -> int:
+        torch = self._torch
+        rp = row_ptr if isinstance(row_ptr, torch.Tensor) else torch.as_tensor(row_ptr)
+        cl = col if isinstance(col, torch.Tensor) else torch.as_tensor(col)
+        rp = rp.to(device="cuda", dtype=torch.int32).contiguous()
+        cl = cl.to(device="cuda", dtype=torch.int32).contiguous()
+        if cl.numel() == 0:
+            cl = torch.zeros(1, dtype=torch.int32, device="cuda")
+        n = rp.numel() - 1
+        if max_outdeg is None:
+            max_outdeg = int((rp[1:] - rp[:-1]).max().item()) if n > 0 else 0
+        self._keep.append((rp, cl))
+        return gtap_submit(self.ctx, GTAP_KIND_KCLIQUE,
+                           gtap_kclique_args(rp.data_ptr(), cl.data_ptr(), n, int(k),
+                                             int(range_leaf), int(max_outdeg)))
+
+    # -- execution ------------------------------------------------------------
+    def run(self) -> None:
+        try:
+            gtap_run(self.ctx)
+        finally:
+            self._keep = []
+
+    def result(self, job_id: int) -> int:
+        return gtap_result(self.ctx, job_id)
+
+    def stats(self) -> dict:
+        return gtap_stats_get(self.ctx)
+
+    def last_error(self) -> dict:
+        return gtap_last_error(self.ctx)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None) is not None:
+            gtap_finalize(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
