@@ -80,7 +80,8 @@ typedef struct { uint64_t seed; uint64_t threshold; int32_t max_depth; int32_t r
  * acyclic orientation, device-resident and borrowed: the caller keeps them
  * alive and unchanged until gtap_run returns.  max_outdeg must be >= every
  * out-degree and <= the context's big_frame_ints.  Vertex ranges larger than
- * range_leaf are split in halves; smaller ones fork one task per vertex. */
+ * range_leaf are split in halves; smaller ones fork one task per vertex.
+ * range_leaf and max_outdeg are at most 2^20 - 1 (children per fork). */
 typedef struct {
     const int32_t *row_ptr_dev;
     const int32_t *col_dev;

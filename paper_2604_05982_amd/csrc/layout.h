@@ -35,11 +35,22 @@ enum FrameWord : uint32_t {
   FW_JOB = 1,      // job slot
   FW_STATE = 2,    // kind | resume point << 8 | queue class << 16
   FW_P0 = 3,       // payload words 3..7 (p0..p4)
-  FW_JOIN = 8,     // waiting-child counter (device-scope RMW only)
-  FW_ACC = 10,     // int64 accumulator of children's results (words 10,11)
+  FW_JOIN = 8,     // join word (words 8,9): children's results << 20 | waiting children
+  FW_BIGACC = 10,  // int64 accumulator for results too large for the join word
   FW_BUF = 16,     // big frames: candidate buffer
 };
 constexpr uint32_t kPayloadWords = 5;
+
+// Join word: one 64-bit RMW per completing child both adds its result and
+// decrements the waiting-child count, so no ordering is needed between the
+// two.  The low kJoinBits bits hold the count; the rest a signed sum of
+// results.  A delivery whose value has magnitude >= 2^kSmallValueBits goes to
+// the separate 64-bit accumulator first, which bounds the packed sum by
+// 2^(kSmallValueBits + kJoinBits) < 2^43.
+constexpr uint32_t kJoinBits = 20;
+constexpr uint64_t kJoinMask = (1ull << kJoinBits) - 1;
+constexpr uint32_t kMaxChildren = (1u << kJoinBits) - 1;
+constexpr uint32_t kSmallValueBits = 23;
 
 // Task kinds of the thread-mode state machines.
 enum TaskKind : uint32_t {

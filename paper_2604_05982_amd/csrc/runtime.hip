@@ -300,6 +300,9 @@ int gtap_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, 
       gtap_kclique_args a;
       std::memcpy(&a, args, sizeof(a));
       if (a.n < 0 || a.k < 1 || a.range_leaf < 1 || a.max_outdeg < 0) return GTAP_E_INVAL;
+      // a task forks at most range_leaf or max_outdeg children (join-word count field)
+      if (static_cast<uint32_t>(a.range_leaf) > kMaxChildren || static_cast<uint32_t>(a.max_outdeg) > kMaxChildren)
+        return GTAP_E_INVAL;
       if (a.n > 0 && (!a.row_ptr_dev || !a.col_dev)) return GTAP_E_INVAL;
       // candidate tasks at level >= 2 keep C' in a big frame (k >= 4)
       if (a.k >= 4 && static_cast<uint32_t>(a.max_outdeg) > c->cfg.big_frame_ints) return GTAP_E_INVAL;

@@ -29,29 +29,31 @@
 namespace gtap {
 
 constexpr uint32_t kPushSpinLimit = 1u << 16;
-constexpr uint32_t kDescStride = 10;   // LDS words per lane: parent, job, ckind, d[0..5]
+
+// Fork descriptor a lane leaves in LDS for the wave-wide child builder:
+// {parent frame, job, child kind | d5 << 8, d0..d4}, 32 bytes.
+struct alignas(16) ForkDesc {
+  uint32_t self, job, ckind_d5, d0, d1, d2, d3, d4;
+};
 
 struct WaveLds {
   uint32_t stk_s[kStackSmall];
   uint32_t stk_b[kStackBig];
   uint32_t offs_s[kWave + 1];
   uint32_t offs_b[kWave + 1];
-  uint32_t desc[kWave * kDescStride];
-  uint32_t res[kWave];
+  ForkDesc desc[kWave];
+  uint32_t res[kWave];         // parents resumed last iteration, staged this one
+  uint4 vdesc[kWave * 2];      // images of retained tasks that have no frame
   uint32_t tail[kMaxQueues];
   uint32_t hint[kMaxQueues];   // 0: own deque q certainly has nothing to pop
   uint32_t head_seen[kMaxQueues];  // last head read by the owner (a lower bound)
-  int32_t sz_s;
-  int32_t sz_b;
-  uint64_t stats[ST_COUNT];
 };
 
-// Per-wave statistics live in LDS (wave-uniform adds; lane 0 writes).
+// Per-wave statistics: wave-uniform counters kept in registers, added to the
+// control block when the wave leaves.
 struct WaveCounters {
-  uint64_t *v;
-  GTAP_DEV void add(uint32_t i, uint64_t x) {
-    if (lane_id() == 0) v[i] += x;
-  }
+  uint32_t v[ST_COUNT];
+  GTAP_DEV void add(uint32_t i, uint32_t x) { v[i] += x; }
 };
 
 GTAP_DEV void raise_error(const Params &p, int32_t code, int32_t pool, uint64_t cap,
@@ -70,7 +72,7 @@ GTAP_DEV void raise_error(const Params &p, int32_t code, int32_t pool, uint64_t 
 // Frame pools.
 struct PoolView {
   uint32_t *stk;        // LDS free stack
-  int32_t *sz;          // LDS stack size
+  int32_t sz;           // stack size (wave-uniform register)
   uint32_t stk_cap;
   uint32_t chunk;
   DepotBin *bins;
@@ -83,11 +85,11 @@ struct PoolView {
 };
 
 GTAP_DEV PoolView small_pool(const Params &p, WaveLds &L) {
-  return PoolView{L.stk_s, &L.sz_s, kStackSmall, kChunkSmall, p.bins_s, p.store_s,
+  return PoolView{L.stk_s, 0, kStackSmall, kChunkSmall, p.bins_s, p.store_s,
                   p.bincap_s, &p.ctl->bump_small, p.nframes_s, 0u, 0};
 }
 GTAP_DEV PoolView big_pool(const Params &p, WaveLds &L) {
-  return PoolView{L.stk_b, &L.sz_b, kStackBig, kChunkBig, p.bins_b, p.store_b,
+  return PoolView{L.stk_b, 0, kStackBig, kChunkBig, p.bins_b, p.store_b,
                   p.bincap_b, &p.ctl->bump_big, p.nframes_b, kBigBit, 1};
 }
 
@@ -130,9 +132,9 @@ GTAP_DEV void depot_unlock(const PoolView &P, uint32_t bin, int32_t nchunks) {
 
 // Move one chunk from the top of the local stack into a depot bin.  Returns
 // false if no bin took it (the IDs then stay on the stack).
-GTAP_DEV bool depot_spill(const PoolView &P, uint32_t me, WaveCounters &wc) {
+GTAP_DEV bool depot_spill(PoolView &P, uint32_t me, WaveCounters &wc) {
   const uint32_t ln = lane_id();
-  const int32_t sz = *P.sz;
+  const int32_t sz = P.sz;
   int32_t nch = 0;
   const uint32_t got = depot_lock(P, me, true, kDepotBins, nch);
   if (got == kNone) return false;
@@ -140,16 +142,16 @@ GTAP_DEV bool depot_spill(const PoolView &P, uint32_t me, WaveCounters &wc) {
   for (uint32_t i = ln; i < P.chunk; i += kWave) co_st32(dst + i, P.stk[sz - static_cast<int32_t>(P.chunk) + i]);
   depot_unlock(P, got, nch + 1);
   wave_sync();
-  *P.sz = sz - static_cast<int32_t>(P.chunk);
+  P.sz = sz - static_cast<int32_t>(P.chunk);
   wc.add(ST_SPILLS, 1);
   return true;
 }
 
 // Pull one chunk from a depot bin onto the local stack.  `all` probes every
 // bin, otherwise only a few from the wavefront's home bin.
-GTAP_DEV bool depot_refill(const PoolView &P, uint32_t me, bool all, WaveCounters &wc) {
+GTAP_DEV bool depot_refill(PoolView &P, uint32_t me, bool all, WaveCounters &wc) {
   const uint32_t ln = lane_id();
-  const int32_t sz = *P.sz;
+  const int32_t sz = P.sz;
   if (sz + static_cast<int32_t>(P.chunk) > static_cast<int32_t>(P.stk_cap)) return false;
   int32_t nch = 0;
   const uint32_t got = depot_lock(P, me, false, all ? kDepotBins : 4u, nch);
@@ -158,7 +160,7 @@ GTAP_DEV bool depot_refill(const PoolView &P, uint32_t me, bool all, WaveCounter
   for (uint32_t i = ln; i < P.chunk; i += kWave) P.stk[sz + i] = co_ld32(src + i);
   depot_unlock(P, got, nch - 1);
   wave_sync();
-  *P.sz = sz + static_cast<int32_t>(P.chunk);
+  P.sz = sz + static_cast<int32_t>(P.chunk);
   wc.add(ST_REFILLS, 1);
   return true;
 }
@@ -188,19 +190,19 @@ struct AllocResult {
   uint32_t base;
 };
 
-GTAP_DEV bool alloc_frames(const Params &p, const PoolView &P, uint32_t me, uint32_t F,
+GTAP_DEV bool alloc_frames(const Params &p, PoolView &P, uint32_t me, uint32_t F,
                            AllocResult &r, WaveCounters &wc) {
   if (F == 0) {
-    r.top = *P.sz;
+    r.top = P.sz;
     r.taken = 0;
     r.base = 0;
     return true;
   }
   // Prefer recycled frames: refill from nearby bins while short.
-  while (static_cast<uint32_t>(*P.sz) < F) {
+  while (static_cast<uint32_t>(P.sz) < F) {
     if (!depot_refill(P, me, false, wc)) break;
   }
-  int32_t sz = *P.sz;
+  int32_t sz = P.sz;
   uint32_t taken = static_cast<uint32_t>(sz) < F ? static_cast<uint32_t>(sz) : F;
   uint32_t rest = F - taken;
   uint32_t base = 0;
@@ -208,10 +210,10 @@ GTAP_DEV bool alloc_frames(const Params &p, const PoolView &P, uint32_t me, uint
     base = bump_claim(P, rest);
     if (base == kNone) {
       // Pool fully touched: reclaim from every bin before giving up.
-      while (static_cast<uint32_t>(*P.sz) < F) {
+      while (static_cast<uint32_t>(P.sz) < F) {
         if (!depot_refill(P, me, true, wc)) break;
       }
-      sz = *P.sz;
+      sz = P.sz;
       taken = static_cast<uint32_t>(sz) < F ? static_cast<uint32_t>(sz) : F;
       rest = F - taken;
       if (rest > 0) {
@@ -227,8 +229,7 @@ GTAP_DEV bool alloc_frames(const Params &p, const PoolView &P, uint32_t me, uint
   r.top = sz;
   r.taken = taken;
   r.base = base;
-  wave_sync();
-  *P.sz = sz - static_cast<int32_t>(taken);
+  P.sz = sz - static_cast<int32_t>(taken);
   return true;
 }
 
@@ -237,17 +238,16 @@ GTAP_DEV uint32_t alloc_id(const PoolView &P, const AllocResult &r, uint32_t g) 
 }
 
 // Push the frame of every lane with `mine` set onto its pool's free stack.
-GTAP_DEV void free_frames(const PoolView &P, uint32_t me, bool mine, uint32_t id, WaveCounters &wc) {
+GTAP_DEV void free_frames(PoolView &P, uint32_t me, bool mine, uint32_t id, WaveCounters &wc) {
   const uint64_t m = ballot(mine);
   const uint32_t n = __popcll(m);
   if (n == 0) return;
-  if (*P.sz + static_cast<int32_t>(n) > static_cast<int32_t>(P.stk_cap)) {
+  if (P.sz + static_cast<int32_t>(n) > static_cast<int32_t>(P.stk_cap)) {
     if (!depot_spill(P, me, wc)) return;  // no bin took a chunk: these frames are not reused
   }
-  const int32_t sz = *P.sz;
+  const int32_t sz = P.sz;
   if (mine) P.stk[sz + static_cast<int32_t>(rank_below(m))] = id;
-  wave_sync();
-  *P.sz = sz + static_cast<int32_t>(n);
+  P.sz = sz + static_cast<int32_t>(n);
 }
 
 // ---------------------------------------------------------------------------
@@ -440,14 +440,18 @@ GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
       kind = TK_FIB;
       c.p[0] = static_cast<uint32_t>(J.a[0]);
       break;
-    case 2:  // n-queens: empty board
+    case 2:  // n-queens: empty board of size n
       kind = TK_NQ;
+      c.p[4] = static_cast<uint32_t>(J.a[0]);
       break;
     case 3: {  // uts: root id = mix64(seed), depth 0
       kind = TK_UTS;
       const uint64_t rid = mix64(J.a[0]);
       c.p[0] = static_cast<uint32_t>(rid);
       c.p[1] = static_cast<uint32_t>(rid >> 32);
+      c.p[2] = static_cast<uint32_t>(J.a[2]) << 16;
+      c.p[3] = static_cast<uint32_t>(J.a[1]);
+      c.p[4] = static_cast<uint32_t>(J.a[1] >> 32);
       break;
     }
     case 4:  // k-clique: the whole vertex range
@@ -462,18 +466,26 @@ GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
 }
 
 // ---------------------------------------------------------------------------
-// Staged IDs S = res[0..nres) ++ small children ++ big children.
+// Staging.  The task IDs made runnable in one iteration are ordered
+//   S = resumed parents (nres) ++ small-frame children (Fs) ++ big-frame children (Fb)
+// and the first `keep` = min(64, |S|) run on the lanes next iteration; the rest
+// are pushed.  A retained small-frame child gets no frame: its image goes to
+// LDS and it runs as a frameless task.  Frames are allocated only for
+// children that are pushed, for big-frame children (their buffer is written
+// while they run) and for a frameless task that forks (its join counter and
+// resume point must live somewhere other wavefronts can reach).
 struct Staged {
-  uint32_t nres, Fs, Fb;
+  uint32_t nres, Fs, Fb, keep, gs0, nself;
   AllocResult as, ab;
 };
 
+// Frame ID of staged entry i (kNone for a retained frameless child).
 GTAP_DEV uint32_t staged_id(const WaveLds &L, const PoolView &PS, const PoolView &PB,
                             const Staged &S, uint32_t i) {
   if (i < S.nres) return L.res[i];
-  i -= S.nres;
-  if (i < S.Fs) return alloc_id(PS, S.as, i);
-  return alloc_id(PB, S.ab, i - S.Fs);
+  const uint32_t g = i - S.nres;
+  if (g < S.Fs) return g < S.gs0 ? kNone : alloc_id(PS, S.as, S.nself + g - S.gs0);
+  return alloc_id(PB, S.ab, g - S.Fs);
 }
 
 template <int WPB>
@@ -485,11 +497,10 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   const uint32_t ln = lane_id();
   const uint64_t deadline = wall_ticks() + p.timeout_ticks;
 
-  WaveCounters wc{L.stats};
+  WaveCounters wc;
+  for (int i = 0; i < static_cast<int>(ST_COUNT); ++i) wc.v[i] = 0;
+  uint64_t busy_cycles = 0, idle_cycles = 0;
   if (ln == 0) {
-    for (int i = 0; i < static_cast<int>(ST_COUNT); ++i) L.stats[i] = 0;
-    L.sz_s = 0;
-    L.sz_b = 0;
     for (uint32_t q = 0; q < kMaxQueues; ++q) {
       L.tail[q] = 0;
       L.hint[q] = 0;
@@ -504,36 +515,48 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
 
   uint32_t cnt = 0;
   uint32_t tid = kNone;
+  uint32_t npend = 0;  // parents resumed in the last iteration (IDs in L.res)
   const uint32_t q = 0;  // single queue (DAQ classes select q when enabled)
 
   // Root admission: job j goes to wave j mod P (the paper's grid leader
   // enqueues the single root; with many jobs every wave seeds its share).
+  // Roots get frames.
   {
     const uint32_t nroots = me < p.njobs ? (p.njobs - me + p.nwaves - 1) / p.nwaves : 0u;
-    Staged S{};
-    S.nres = 0;
-    S.Fs = nroots;
-    S.Fb = 0;
-    const bool ok = alloc_frames(p, PS, me, nroots, S.as, wc);
-    S.ab = AllocResult{*PB.sz, 0, 0};
+    AllocResult ar{};
+    const bool ok = alloc_frames(p, PS, me, nroots, ar, wc);
     if (ok && nroots > 0) {
-      for (uint32_t g = ln; g < nroots; g += kWave) write_root(p, alloc_id(PS, S.as, g), me + g * p.nwaves);
+      wave_sync();
+      for (uint32_t g = ln; g < nroots; g += kWave) write_root(p, alloc_id(PS, ar, g), me + g * p.nwaves);
       drain();
       const uint32_t keep = nroots < kWave ? nroots : kWave;
-      if (ln < keep) tid = staged_id(L, PS, PB, S, ln);
+      if (ln < keep) tid = alloc_id(PS, ar, ln);
       cnt = keep;
-      push_batch(p, L, me, q, nroots - keep,
-                 [&](uint32_t i) { return staged_id(L, PS, PB, S, keep + i); }, wc);
+      push_batch(p, L, me, q, nroots - keep, [&](uint32_t i) { return alloc_id(PS, ar, keep + i); }, wc);
     }
   }
 
   uint32_t idle = 0;
   uint32_t iter = 0;
+  bool tcont = false;  // this lane's task is a resumed parent (runs its continuation)
   uint64_t t_loop = clock64();
   for (;;) {
     // ---- acquire work ----
+    // Parents resumed in the last iteration are normally staged with this
+    // iteration's children; with no lanes busy they run right away.
+    if (cnt == 0 && npend > 0) {
+      if (ln < npend) {
+        tid = L.res[ln];
+        tcont = true;
+      }
+      cnt = npend;
+      npend = 0;
+    }
+    // popped and stolen tasks are children with frames (resume point 0)
+    const uint32_t cnt0 = cnt;
     if (cnt < kWave) cnt += pop_batch(p, L, me, q, cnt, tid, wc);
     if (cnt < p.steal_below && p.nwaves > 1) cnt += steal_batch(p, me, rng, q, cnt, tid, wc);
+    if (ln >= cnt0) tcont = false;
     if (cnt == 0) {
       ++idle;
       wc.add(ST_IDLE, 1);
@@ -550,7 +573,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       if (uniform(stop)) break;
       backoff_sleep(idle);
       const uint64_t now = clock64();
-      wc.add(ST_IDLE_CYCLES, now - t_loop);
+      idle_cycles += now - t_loop;
       t_loop = now;
       continue;
     }
@@ -575,101 +598,165 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     o.nchild = 0;
     o.big = 0;
     o.first = 0;
-    if (ln < cnt) exec_task(p, tid, o);
+    for (int i = 0; i < 6; ++i) o.d[i] = 0;
+    if (ln < cnt) {
+      TaskImage img;
+      if (tid == kNone) {
+        const uint4 a = L.vdesc[2 * ln], b = L.vdesc[2 * ln + 1];
+        img = TaskImage{pack(a.x, a.y), pack(a.z, a.w), pack(b.x, b.y), pack(b.z, b.w)};
+      } else if (tcont) {
+        img = load_continuation(p, tid);
+      } else {
+        img = load_image(p, tid);
+      }
+      exec_task(p, tid, img, o);
+    }
     const uint32_t nfirst = __popcll(ballot(o.first != 0));
     wc.add(ST_TASKS, nfirst);
     wc.add(ST_CONTS, cnt - nfirst);
 
-    // ---- completions, part 1: deliver results (performed by the drain below) ----
+    // ---- completions ----
+    // A child's completion adds its result to the parent's join word and
+    // decrements the waiting-child count in the same RMW; the child that
+    // brings the count to zero resumes the parent (Sec. 5.1.2).  Siblings that
+    // completed on adjacent lanes are summed first (a prefix sum over the wave
+    // minus the prefix before the run's first lane), so each parent receives
+    // one RMW per wavefront.  The RMW's old value is examined after this
+    // iteration's final drain and the resumed parents are staged next iteration.
     const bool done = (o.type == OUT_DONE);
     const bool to_parent = done && o.parent != kNone;
-    if (to_parent && o.value != 0) fetch_add_relaxed(acc_ptr(frame_ptr(p, o.parent)), o.value);
-    if (done && o.parent == kNone) {
+    const bool root_done = done && o.parent == kNone;
+    if (root_done) {
       JobSlot &J = p.jobs[o.job];
       st_relaxed(&J.result, o.value);
       st_relaxed(&J.t_done, wall_ticks());
       st_relaxed(&J.done, 1u);
     }
-    // the completed frames are dead: recycle them
-    free_frames(PS, me, done && !(tid & kBigBit), tid, wc);
-    free_frames(PB, me, done && (tid & kBigBit), tid, wc);
+    const uint32_t par = to_parent ? o.parent : kNone;
+    const uint32_t prev_par = wave_from_below(par, kNone);
+    const uint32_t next_par = wave_from_above(par, kNone);
+    const bool head = !to_parent || prev_par != par;
+    const bool tail = to_parent && next_par != par;
+    const uint32_t hidx = wave_inclusive_max(head ? ln : 0u);
+    const uint64_t pre = wave_inclusive_sum64(to_parent ? static_cast<uint64_t>(o.value) : 0ull);
+    const uint32_t src = hidx > 0 ? hidx - 1 : 0;
+    const uint64_t pre_lo = static_cast<uint32_t>(__shfl(static_cast<int>(static_cast<uint32_t>(pre)), static_cast<int>(src), 64));
+    const uint64_t pre_hi = static_cast<uint32_t>(__shfl(static_cast<int>(static_cast<uint32_t>(pre >> 32)), static_cast<int>(src), 64));
+    const uint64_t before = hidx > 0 ? (pre_lo | (pre_hi << 32)) : 0ull;
+    const int64_t run_val = static_cast<int64_t>(pre - before);
+    const uint32_t run_len = ln - hidx + 1;
+    const int64_t lim = static_cast<int64_t>(1) << kSmallValueBits;
+    const bool big_val = tail && (run_val >= lim || run_val <= -lim);
+    if (ballot(big_val)) {
+      if (big_val) fetch_add_relaxed(bigacc_ptr(frame_ptr(p, o.parent)), run_val);
+      drain();  // the large result is in place before the count can reach zero
+    }
+    int64_t join_old = 0;
+    if (tail) {
+      const int64_t delta = (big_val ? 0 : run_val * (static_cast<int64_t>(1) << kJoinBits)) -
+                            static_cast<int64_t>(run_len);
+      join_old = fetch_add_relaxed(join_ptr(frame_ptr(p, o.parent)), delta);
+    }
+    if (root_done) {
+      drain();  // the job's result is in place before the run can end
+      fetch_add_relaxed(&p.ctl->jobs_remaining, -1);
+    }
+    // completed tasks that had frames release them
+    free_frames(PS, me, done && tid != kNone && !(tid & kBigBit), tid, wc);
+    free_frames(PB, me, done && tid != kNone && (tid & kBigBit), tid, wc);
 
-    // ---- forks: allocate and initialise children, suspend parents ----
+    // ---- forks ----
+    if (ballot(o.type == OUT_FORK && o.nchild > kMaxChildren)) {
+      if (ln == 0) raise_error(p, -6 /*GTAP_E_CAPACITY*/, 4, kMaxChildren, 0, me, -1);
+      break;
+    }
     const bool fork = (o.type == OUT_FORK);
+    const bool need_self = fork && tid == kNone;  // a frameless task suspends: give it a frame
     const uint32_t fs = (fork && !o.big) ? o.nchild : 0u;
     const uint32_t fb = (fork && o.big) ? o.nchild : 0u;
     Staged S;
     const uint32_t offs = wave_exclusive_scan(fs, &S.Fs);
     const uint32_t offb = wave_exclusive_scan(fb, &S.Fb);
+    const uint64_t m_self = ballot(need_self);
+    S.nself = __popcll(m_self);
+    S.nres = npend;
+    const uint32_t total = S.nres + S.Fs + S.Fb;
+    S.keep = total < kWave ? total : kWave;
+    S.gs0 = (S.keep - S.nres) < S.Fs ? (S.keep - S.nres) : S.Fs;
     L.offs_s[ln] = offs;
     L.offs_b[ln] = offb;
     if (ln == 0) {
       L.offs_s[kWave] = S.Fs;
       L.offs_b[kWave] = S.Fb;
     }
-    if (fork) {
-      uint32_t *dsc = L.desc + ln * kDescStride;
-      dsc[0] = tid;
-      dsc[1] = o.job;
-      dsc[2] = o.ckind;
-      for (int i = 0; i < 6; ++i) dsc[3 + i] = o.d[i];
-    }
-    wave_sync();
-    bool ok = alloc_frames(p, PS, me, S.Fs, S.as, wc);
+    bool ok = alloc_frames(p, PS, me, S.nself + (S.Fs - S.gs0), S.as, wc);
     ok = ok && alloc_frames(p, PB, me, S.Fb, S.ab, wc);
     if (!ok) break;
+    wave_sync();
     wc.add(ST_SPAWNS, S.Fs + S.Fb);
+    if (fork) {
+      // suspend at the join: resume point 1, count = #children, sums 0
+      const uint32_t self = need_self ? alloc_id(PS, S.as, rank_below(m_self)) : tid;
+      uint32_t *f = frame_ptr(p, self);
+      if (need_self) co_st64(frame64(f), pack(o.parent, o.job));
+      co_st32(f + FW_STATE, state_word(o.kind, 1, 0));
+      st_relaxed(bigacc_ptr(f), static_cast<int64_t>(0));
+      st_relaxed(join_ptr(f), static_cast<int64_t>(o.nchild));
+      L.desc[ln] = ForkDesc{self, o.job, o.ckind | (o.d[5] << 8), o.d[0], o.d[1], o.d[2], o.d[3], o.d[4]};
+    }
+    wave_sync();
+    // children, built by the whole wavefront
     for (uint32_t g = ln; g < S.Fs + S.Fb; g += kWave) {
       const bool isbig = g >= S.Fs;
       const uint32_t gg = isbig ? g - S.Fs : g;
       const uint32_t *offs_arr = isbig ? L.offs_b : L.offs_s;
       const uint32_t own = owner_of(offs_arr, gg);
       const uint32_t j = gg - offs_arr[own];
-      const uint32_t *dsc = L.desc + own * kDescStride;
+      const ForkDesc dsc = L.desc[own];
+      const uint32_t ckind = dsc.ckind_d5 & 0xFFu;
+      const uint32_t d[6] = {dsc.d0, dsc.d1, dsc.d2, dsc.d3, dsc.d4, dsc.ckind_d5 >> 8};
       ChildInit c;
-      make_child(dsc[2], dsc + 3, j, c);
-      const uint32_t cid = isbig ? alloc_id(PB, S.ab, gg) : alloc_id(PS, S.as, gg);
-      write_frame(frame_ptr(p, cid), dsc[0], dsc[1], state_word(dsc[2], 0, 0), c);
+      make_child(ckind, d, j, c);
+      const uint32_t st = state_word(ckind, 0, 0);
+      if (!isbig && gg < S.gs0) {
+        uint4 *v = L.vdesc + 2 * (S.nres + gg);
+        v[0] = make_uint4(dsc.self, dsc.job, st, c.p[0]);
+        v[1] = make_uint4(c.p[1], c.p[2], c.p[3], c.p[4]);
+      } else {
+        const uint32_t cid = isbig ? alloc_id(PB, S.ab, gg) : alloc_id(PS, S.as, S.nself + gg - S.gs0);
+        write_frame(frame_ptr(p, cid), dsc.self, dsc.job, st, c);
+      }
     }
-    if (fork) {
-      uint32_t *f = frame_ptr(p, tid);
-      co_st32(f + FW_STATE, state_word(o.kind, 1, 0));
-      st_relaxed(acc_ptr(f), static_cast<int64_t>(0));
-      st_relaxed(join_ptr(f), static_cast<int32_t>(o.nchild));
-    }
-    // Results delivered to parents, root results, new children and suspended
-    // parents are all performed before any join counter moves or any ID is
-    // published or retained.
-    drain();
-
-    // ---- completions, part 2: the child that brings join to zero resumes its parent ----
-    uint32_t resumed = kNone;
-    if (to_parent) {
-      const int32_t old = fetch_add_relaxed(join_ptr(frame_ptr(p, o.parent)), -1);
-      if (old == 1) resumed = o.parent;
-    }
-    if (done && o.parent == kNone) fetch_add_relaxed(&p.ctl->jobs_remaining, -1);
-
-    // ---- stage: resumed parents first, then the new children ----
-    const uint64_t m_res = ballot(resumed != kNone);
-    S.nres = __popcll(m_res);
-    if (resumed != kNone) L.res[rank_below(m_res)] = resumed;
     wave_sync();
-    const uint32_t total = S.nres + S.Fs + S.Fb;
-    const uint32_t keep = total < kWave ? total : kWave;
-    tid = (ln < keep) ? staged_id(L, PS, PB, S, ln) : kNone;
-    cnt = keep;
-    if (!push_batch(p, L, me, q, total - keep,
-                    [&](uint32_t i) { return staged_id(L, PS, PB, S, keep + i); }, wc))
+
+    // ---- stage: retain the first `keep`, publish the rest ----
+    tid = (ln < S.keep) ? staged_id(L, PS, PB, S, ln) : kNone;
+    tcont = ln < S.nres;
+    cnt = S.keep;
+    const uint32_t npush = total - S.keep;
+    if (!push_batch(p, L, me, q, npush, [&](uint32_t i) { return staged_id(L, PS, PB, S, S.keep + i); }, wc))
       break;
+    // frames written this iteration are complete before they run, and the
+    // join RMWs have returned
+    if (npush == 0) drain();
+    const bool resumed = tail && (static_cast<uint64_t>(join_old) & kJoinMask) == run_len;
+    const uint64_t m_res = ballot(resumed);
+    wave_sync();
+    if (resumed) L.res[rank_below(m_res)] = o.parent;
+    npend = __popcll(m_res);
+    wave_sync();
     const uint64_t now = clock64();
-    wc.add(ST_BUSY_CYCLES, now - t_loop);
+    busy_cycles += now - t_loop;
     t_loop = now;
   }
 
   // ---- flush counters ----
-  wave_sync();
-  if (ln < ST_COUNT && L.stats[ln] != 0) fetch_add_relaxed(&p.ctl->stats[ln], L.stats[ln]);
+  if (ln == 0) {
+    for (int i = 0; i < static_cast<int>(ST_COUNT); ++i)
+      if (wc.v[i]) fetch_add_relaxed(&p.ctl->stats[i], static_cast<uint64_t>(wc.v[i]));
+    if (busy_cycles) fetch_add_relaxed(&p.ctl->stats[ST_BUSY_CYCLES], busy_cycles);
+    if (idle_cycles) fetch_add_relaxed(&p.ctl->stats[ST_IDLE_CYCLES], idle_cycles);
+  }
 }
 
 }  // namespace gtap

@@ -46,8 +46,8 @@ GTAP_DEV uint32_t *frame_ptr(const Params &p, uint32_t tid) {
                          : p.frames_s + static_cast<size_t>(tid) * kFrameWords;
 }
 GTAP_DEV uint64_t *frame64(uint32_t *f) { return reinterpret_cast<uint64_t *>(f); }
-GTAP_DEV int64_t *acc_ptr(uint32_t *f) { return reinterpret_cast<int64_t *>(f + FW_ACC); }
-GTAP_DEV int32_t *join_ptr(uint32_t *f) { return reinterpret_cast<int32_t *>(f + FW_JOIN); }
+GTAP_DEV int64_t *join_ptr(uint32_t *f) { return reinterpret_cast<int64_t *>(f + FW_JOIN); }
+GTAP_DEV int64_t *bigacc_ptr(uint32_t *f) { return reinterpret_cast<int64_t *>(f + FW_BIGACC); }
 
 GTAP_DEV uint32_t state_word(uint32_t kind, uint32_t pc, uint32_t cls) {
   return kind | (pc << 8) | (cls << 16);
@@ -117,13 +117,33 @@ GTAP_DEV uint32_t intersect_sorted(const int32_t *C, uint32_t nc, const int32_t 
 
 GTAP_DEV const uint64_t *job_args(const Params &p, uint32_t job) { return p.jobs[job].a; }
 
-// ---------------------------------------------------------------------------
-// Execute one task on this lane.
-GTAP_DEV void exec_task(const Params &p, uint32_t tid, Outcome &o) {
+// Words 0..7 of a task: its frame's first half, or the LDS descriptor of a
+// task that has no frame (a child retained by the wavefront that spawned it).
+struct TaskImage {
+  uint64_t w01, w23, w45, w67;
+};
+
+GTAP_DEV TaskImage load_image(const Params &p, uint32_t tid) {
+  const uint64_t *f64 = frame64(frame_ptr(p, tid));
+  return TaskImage{co_ld64(f64 + 0), co_ld64(f64 + 1), co_ld64(f64 + 2), co_ld64(f64 + 3)};
+}
+
+// A resumed parent needs its header and its join state only; all four loads
+// go out together.  w45/w67 carry the join word and the large-value sum.
+GTAP_DEV TaskImage load_continuation(const Params &p, uint32_t tid) {
   uint32_t *f = frame_ptr(p, tid);
   const uint64_t *f64 = frame64(f);
-  const uint64_t w01 = co_ld64(f64 + 0);
-  const uint64_t w23 = co_ld64(f64 + 1);
+  return TaskImage{co_ld64(f64 + 0), co_ld64(f64 + 1), static_cast<uint64_t>(ld_relaxed(join_ptr(f))),
+                   static_cast<uint64_t>(ld_relaxed(bigacc_ptr(f)))};
+}
+
+// ---------------------------------------------------------------------------
+// Execute one task on this lane.  tid is its frame, or kNone for a task
+// without one (then it runs at resume point 0 and needs no buffer).
+GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Outcome &o) {
+  uint32_t *f = tid != kNone ? frame_ptr(p, tid) : nullptr;
+  const uint64_t w01 = img.w01;
+  const uint64_t w23 = img.w23;
   const uint32_t state = static_cast<uint32_t>(w23);
   const uint32_t kind = state & 0xFFu;
   const uint32_t pc = (state >> 8) & 0xFFu;
@@ -137,15 +157,15 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, Outcome &o) {
   o.value = 0;
 
   if (pc != 0) {
-    // Continuation after the join: every kind sums its children's results;
-    // a UTS node adds itself.
-    const int64_t acc = ld_relaxed(acc_ptr(f));
+    // Continuation after the join (image from load_continuation): every kind
+    // sums its children's results; a UTS node adds itself.
+    const int64_t acc = (static_cast<int64_t>(img.w45) >> kJoinBits) + static_cast<int64_t>(img.w67);
     o.value = (kind == TK_UTS) ? acc + 1 : acc;
     return;
   }
 
-  const uint64_t w45 = co_ld64(f64 + 2);
-  const uint64_t w67 = co_ld64(f64 + 3);
+  const uint64_t w45 = img.w45;
+  const uint64_t w67 = img.w67;
   const uint32_t p0 = static_cast<uint32_t>(w23 >> 32);
   const uint32_t p1 = static_cast<uint32_t>(w45), p2 = static_cast<uint32_t>(w45 >> 32);
   const uint32_t p3 = static_cast<uint32_t>(w67), p4 = static_cast<uint32_t>(w67 >> 32);
@@ -165,9 +185,9 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, Outcome &o) {
     }
     case TK_NQ: {
       // Rows [0,row) hold queens; one child per unattacked column of `row`.
-      const uint64_t *a = job_args(p, o.job);
-      const uint32_t n = static_cast<uint32_t>(a[0]);
-      const uint32_t full = static_cast<uint32_t>(a[1]);
+      // The board size travels in the payload (p4).
+      const uint32_t n = p4;
+      const uint32_t full = (1u << n) - 1u;
       const uint32_t cols = p0, dl = p1, dr = p2, row = p3;
       if (row == n) {
         o.value = 1;
@@ -178,14 +198,14 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, Outcome &o) {
       o.type = OUT_FORK;
       o.nchild = __popc(avail);
       o.ckind = TK_NQ;
-      o.d[0] = cols; o.d[1] = dl; o.d[2] = dr; o.d[3] = row; o.d[4] = avail; o.d[5] = full;
+      o.d[0] = cols; o.d[1] = dl; o.d[2] = dr; o.d[3] = row; o.d[4] = avail; o.d[5] = n;
       return;
     }
     case TK_UTS: {
-      const uint64_t *a = job_args(p, o.job);
+      // payload: id (p0,p1), depth | depth limit << 16 (p2), threshold (p3,p4)
       const uint64_t id = pack(p0, p1);
-      const uint32_t depth = p2;
-      const uint32_t nc = uts_children(id, depth, a[1], static_cast<uint32_t>(a[2]));
+      const uint32_t depth = p2 & 0xFFFFu, max_depth = p2 >> 16;
+      const uint32_t nc = uts_children(id, depth, pack(p3, p4), max_depth);
       if (nc == 0) {
         o.value = 1;
         return;
@@ -193,7 +213,7 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, Outcome &o) {
       o.type = OUT_FORK;
       o.nchild = nc;
       o.ckind = TK_UTS;
-      o.d[0] = p0; o.d[1] = p1; o.d[2] = depth;
+      o.d[0] = p0; o.d[1] = p1; o.d[2] = p2; o.d[3] = p3; o.d[4] = p4;
       return;
     }
     case TK_KC_RANGE: {
@@ -289,18 +309,21 @@ GTAP_DEV void make_child(uint32_t ckind, const uint32_t *d, uint32_t j, ChildIni
       break;
     case TK_NQ: {
       const uint32_t b = nth_set_bit(d[4], j);
-      const uint32_t full = d[5];
+      const uint32_t full = (1u << d[5]) - 1u;
       c.p[0] = d[0] | b;
       c.p[1] = ((d[1] | b) << 1) & full;
       c.p[2] = (d[2] | b) >> 1;
       c.p[3] = d[3] + 1;
+      c.p[4] = d[5];
       break;
     }
     case TK_UTS: {
       const uint64_t cid = split_id(pack(d[0], d[1]), j);
       c.p[0] = static_cast<uint32_t>(cid);
       c.p[1] = static_cast<uint32_t>(cid >> 32);
-      c.p[2] = d[2] + 1;
+      c.p[2] = d[2] + 1;  // depth + 1, depth limit unchanged in the high half
+      c.p[3] = d[3];
+      c.p[4] = d[4];
       break;
     }
     case TK_KC_RANGE: {

@@ -43,17 +43,74 @@ GTAP_DEV uint64_t uniform64(uint64_t x) {
   return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
+// ---- cross-lane scans with DPP (VALU data-parallel primitives) ---------------
+// Rows of 16 lanes: row_shr:n shifts within a row (lanes whose source lies
+// outside the row read 0), row_bcast:15 / row_bcast:31 broadcast the last lane
+// of row 0 (2) into rows 1,3 (2,3).  Must be called with every lane active.
+enum DppCtrl : int {
+  kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118,
+  kRowBcast15 = 0x142, kRowBcast31 = 0x143
+};
+
+template <int CTRL, int ROWMASK>
+GTAP_DEV uint32_t dpp_in(uint32_t x) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(x), CTRL, ROWMASK, 0xF, true));
+}
+template <int CTRL, int ROWMASK>
+GTAP_DEV uint64_t dpp_in64(uint64_t x) {
+  const uint32_t lo = dpp_in<CTRL, ROWMASK>(static_cast<uint32_t>(x));
+  const uint32_t hi = dpp_in<CTRL, ROWMASK>(static_cast<uint32_t>(x >> 32));
+  return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32);
+}
+
+// Inclusive prefix sum over the wave.
+GTAP_DEV uint32_t wave_inclusive_sum(uint32_t x) {
+  x += dpp_in<kRowShr1, 0xF>(x);
+  x += dpp_in<kRowShr2, 0xF>(x);
+  x += dpp_in<kRowShr4, 0xF>(x);
+  x += dpp_in<kRowShr8, 0xF>(x);
+  x += dpp_in<kRowBcast15, 0xA>(x);
+  x += dpp_in<kRowBcast31, 0xC>(x);
+  return x;
+}
+GTAP_DEV uint64_t wave_inclusive_sum64(uint64_t x) {
+  x += dpp_in64<kRowShr1, 0xF>(x);
+  x += dpp_in64<kRowShr2, 0xF>(x);
+  x += dpp_in64<kRowShr4, 0xF>(x);
+  x += dpp_in64<kRowShr8, 0xF>(x);
+  x += dpp_in64<kRowBcast15, 0xA>(x);
+  x += dpp_in64<kRowBcast31, 0xC>(x);
+  return x;
+}
+// Inclusive prefix maximum (values >= 0).
+GTAP_DEV uint32_t wave_inclusive_max(uint32_t x) {
+  uint32_t y;
+  y = dpp_in<kRowShr1, 0xF>(x); x = x > y ? x : y;
+  y = dpp_in<kRowShr2, 0xF>(x); x = x > y ? x : y;
+  y = dpp_in<kRowShr4, 0xF>(x); x = x > y ? x : y;
+  y = dpp_in<kRowShr8, 0xF>(x); x = x > y ? x : y;
+  y = dpp_in<kRowBcast15, 0xA>(x); x = x > y ? x : y;
+  y = dpp_in<kRowBcast31, 0xC>(x); x = x > y ? x : y;
+  return x;
+}
+
+// Value of the lane below / above; lane 0 / lane 63 receive `fill`.  Like
+// every DPP helper here it must run with all 64 lanes active: call it
+// unconditionally (a disabled source lane would read as `fill`).
+GTAP_DEV uint32_t wave_from_below(uint32_t x, uint32_t fill) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(static_cast<int>(fill), static_cast<int>(x), 0x138, 0xF, 0xF, false));
+}
+GTAP_DEV uint32_t wave_from_above(uint32_t x, uint32_t fill) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(static_cast<int>(fill), static_cast<int>(x), 0x130, 0xF, 0xF, false));
+}
+
 // Exclusive prefix sum over the 64 lanes; *total = sum over all lanes.
-// Must be called with every lane active.
 GTAP_DEV uint32_t wave_exclusive_scan(uint32_t x, uint32_t *total) {
-  uint32_t s = x;
-  const uint32_t ln = lane_id();
-#pragma unroll
-  for (uint32_t d = 1; d < 64u; d <<= 1) {
-    uint32_t y = __shfl_up(s, d, 64);
-    if (ln >= d) s += y;
-  }
-  *total = __shfl(s, 63, 64);
+  const uint32_t s = wave_inclusive_sum(x);
+  *total = __builtin_amdgcn_readlane(s, 63);
   return s - x;
 }
 

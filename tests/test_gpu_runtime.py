@@ -223,7 +223,7 @@ def test_deque_exhaustion_reports(gtap):
     edges = [(0, j) for j in range(1, n)]
     g = graphs.oriented_from_edges(n, edges, "id")
     with make_rt(gtap, num_waves=1, waves_per_group=1, deque_capacity=128, big_frame_ints=2048) as r:
-        r.submit_kclique(g.row_ptr32, g.col, 3, range_leaf=1 << 20)
+        r.submit_kclique(g.row_ptr32, g.col, 3, range_leaf=(1 << 20) - 1)
         with pytest.raises(gtap.GtapError) as ei:
             r.run()
         assert ei.value.code == gtap.GTAP_E_CAPACITY and ei.value.report["pool"] == 2
