@@ -12,6 +12,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -44,6 +46,50 @@ def algorithmic_bytes(st: dict) -> int:
             + (BYTES_FORK + BYTES_CONT_READ) * st["conts"] + BYTES_PUSHED * st["pushed"])
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "thread_sched_kernel_microbench_traffic.txt")
+
+
+def kernel_source_sha() -> str:
+    """Hash of the HIP sources the scheduler kernel is built from."""
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_2604_05982_amd", "csrc", "*"))):
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(nbytes: int, reps: int = 3) -> None:
+    """A plain device copy of known size (calibrates FETCH_SIZE/WRITE_SIZE)."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "reps": reps}), flush=True)
+
+
 def workload_jobs(rt, gtap):
     thr = gtap.uts_threshold(4)
     return [rt.submit_fib(32), rt.submit_nqueens(13), rt.submit_uts(1, thr, 13)]
@@ -74,8 +120,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--waves-per-group", type=int, default=4)
-    ap.add_argument("--num-waves", type=int, default=0)
+    ap.add_argument("--num-waves", type=int, default=512)
     ap.add_argument("--steal-below", type=int, default=64)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="run only a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -83,9 +131,12 @@ def main() -> int:
         return 2
 
     import torch
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return 0
     from paper_2604_05982_amd import gtap
 
-    torch.cuda.set_device(0)
     rt = gtap.Runtime(waves_per_group=args.waves_per_group, num_waves=args.num_waves,
                       steal_below=args.steal_below, small_frames=1 << 25, timeout_ms=60000)
     expect = (2178309, 73712, 102971195)
@@ -143,7 +194,7 @@ def main() -> int:
         "kernel_tasks_per_s": tasks / args.steps / (mean_kernel_ms * 1e-3),
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
             "kernel": "thread_sched_kernel",
             "algorithmic_bytes_per_launch": alg_bytes_launch,
         },
