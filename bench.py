@@ -120,7 +120,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--waves-per-group", type=int, default=4)
-    ap.add_argument("--num-waves", type=int, default=512)
+    ap.add_argument("--num-waves", type=int, default=1024)
     ap.add_argument("--steal-below", type=int, default=64)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run only a plain device copy of this many bytes (counter calibration)")

@@ -30,23 +30,28 @@ namespace gtap {
 
 constexpr uint32_t kPushSpinLimit = 1u << 16;
 
+constexpr uint32_t kClassCache = 1024;  // children whose DAQ class is kept from the counting pass
+
 // Fork descriptor a lane leaves in LDS for the wave-wide child builder:
-// {parent frame, job, child kind | d5 << 8, d0..d4}, 32 bytes.
+// {parent frame, job, child kind | big << 7 | d5 << 8, d0..d4}, 32 bytes.
 struct alignas(16) ForkDesc {
-  uint32_t self, job, ckind_d5, d0, d1, d2, d3, d4;
+  uint32_t self, job, ckind_big_d5, d0, d1, d2, d3, d4;
 };
 
 struct WaveLds {
   uint32_t stk_s[kStackSmall];
   uint32_t stk_b[kStackBig];
-  uint32_t offs_s[kWave + 1];
-  uint32_t offs_b[kWave + 1];
+  uint32_t offs[kWave + 1];
   ForkDesc desc[kWave];
   uint32_t res[kWave];         // parents resumed last iteration, staged this one
+  uint32_t next_tid[kWave];    // retained children, by lane, for the next iteration
   uint4 vdesc[kWave * 2];      // images of retained tasks that have no frame
+  uint8_t cls[kClassCache];    // DAQ class of child g (counting pass -> build pass)
   uint32_t tail[kMaxQueues];
   uint32_t hint[kMaxQueues];   // 0: own deque q certainly has nothing to pop
   uint32_t head_seen[kMaxQueues];  // last head read by the owner (a lower bound)
+  uint32_t qn[kMaxQueues];     // children per class this iteration
+  uint32_t qbase[kMaxQueues];  // running rank per class in the build pass
 };
 
 // Per-wave statistics: wave-uniform counters kept in registers, added to the
@@ -73,6 +78,7 @@ GTAP_DEV void raise_error(const Params &p, int32_t code, int32_t pool, uint64_t 
 struct PoolView {
   uint32_t *stk;        // LDS free stack
   int32_t sz;           // stack size (wave-uniform register)
+  uint32_t skip;        // allocations left before the depot is probed again
   uint32_t stk_cap;
   uint32_t chunk;
   DepotBin *bins;
@@ -85,40 +91,48 @@ struct PoolView {
 };
 
 GTAP_DEV PoolView small_pool(const Params &p, WaveLds &L) {
-  return PoolView{L.stk_s, 0, kStackSmall, kChunkSmall, p.bins_s, p.store_s,
+  return PoolView{L.stk_s, 0, 0, kStackSmall, kChunkSmall, p.bins_s, p.store_s,
                   p.bincap_s, &p.ctl->bump_small, p.nframes_s, 0u, 0};
 }
 GTAP_DEV PoolView big_pool(const Params &p, WaveLds &L) {
-  return PoolView{L.stk_b, 0, kStackBig, kChunkBig, p.bins_b, p.store_b,
+  return PoolView{L.stk_b, 0, 0, kStackBig, kChunkBig, p.bins_b, p.store_b,
                   p.bincap_b, &p.ctl->bump_big, p.nframes_b, kBigBit, 1};
 }
 
-// Lock a depot bin (lane 0 probes up to `probes` bins from the wave's home
-// bin).  want_room: the bin must have room for a chunk, else it must hold one.
-// Returns the bin and its chunk count, or kNone.
+// Lock a depot bin.  Lanes [0, probes) read the chunk counts of consecutive
+// bins from the wave's home bin in one round trip; lane 0 then tries the
+// locks of the suitable ones in order.  want_room: the bin must have room for
+// a chunk, else it must hold one.  Returns the bin and its chunk count, or kNone.
 GTAP_DEV uint32_t depot_lock(const PoolView &P, uint32_t me, bool want_room, uint32_t probes,
                              int32_t &nch_out) {
   const int32_t maxchunks = static_cast<int32_t>(P.bincap / P.chunk);
+  const uint32_t ln = lane_id();
   uint32_t got = kNone;
   int32_t nch = 0;
-  if (lane_id() == 0) {
-    for (uint32_t t = 0; t < probes; ++t) {
-      const uint32_t b = (me + t) % kDepotBins;
-      DepotBin *bin = P.bins + b;
-      const int32_t seen = ld_relaxed(&bin->nchunks);
-      if (want_room ? seen >= maxchunks : seen <= 0) continue;
-      int32_t z = 0;
-      if (!cas_relaxed(&bin->lock, &z, 1)) continue;
-      nch = ld_relaxed(&bin->nchunks);
-      if (want_room ? nch < maxchunks : nch > 0) {
-        got = b;
-        break;
+  for (uint32_t t0 = 0; t0 < probes && got == kNone; t0 += kWave) {
+    const uint32_t t = t0 + ln;
+    int32_t seen = want_room ? maxchunks : 0;
+    if (t < probes) seen = ld_relaxed(&P.bins[(me + t) % kDepotBins].nchunks);
+    uint64_t cand = ballot(t < probes && (want_room ? seen < maxchunks : seen > 0));
+    if (ln == 0) {
+      while (cand) {
+        const uint32_t b = (me + t0 + static_cast<uint32_t>(__ffsll(static_cast<long long>(cand)) - 1)) % kDepotBins;
+        cand &= cand - 1;
+        DepotBin *bin = P.bins + b;
+        int32_t z = 0;
+        if (!cas_relaxed(&bin->lock, &z, 1)) continue;
+        nch = ld_relaxed(&bin->nchunks);
+        if (want_room ? nch < maxchunks : nch > 0) {
+          got = b;
+          break;
+        }
+        st_relaxed(&bin->lock, 0);
       }
-      st_relaxed(&bin->lock, 0);
     }
+    got = uniform(got);
   }
   nch_out = uniform(nch);
-  return uniform(got);
+  return got;
 }
 
 GTAP_DEV void depot_unlock(const PoolView &P, uint32_t bin, int32_t nchunks) {
@@ -154,7 +168,7 @@ GTAP_DEV bool depot_refill(PoolView &P, uint32_t me, bool all, WaveCounters &wc)
   const int32_t sz = P.sz;
   if (sz + static_cast<int32_t>(P.chunk) > static_cast<int32_t>(P.stk_cap)) return false;
   int32_t nch = 0;
-  const uint32_t got = depot_lock(P, me, false, all ? kDepotBins : 4u, nch);
+  const uint32_t got = depot_lock(P, me, false, all ? kDepotBins : 8u, nch);
   if (got == kNone) return false;
   const uint32_t *src = P.store + static_cast<size_t>(got) * P.bincap + static_cast<size_t>(nch - 1) * P.chunk;
   for (uint32_t i = ln; i < P.chunk; i += kWave) P.stk[sz + i] = co_ld32(src + i);
@@ -190,47 +204,61 @@ struct AllocResult {
   uint32_t base;
 };
 
+// Every ID handed out by one call must be read (alloc_id) before the next
+// allocation from the same pool: the spares of a bump claim are pushed where
+// earlier calls' IDs were taken from.
 GTAP_DEV bool alloc_frames(const Params &p, PoolView &P, uint32_t me, uint32_t F,
                            AllocResult &r, WaveCounters &wc) {
-  if (F == 0) {
-    r.top = P.sz;
-    r.taken = 0;
-    r.base = 0;
-    return true;
-  }
-  // Prefer recycled frames: refill from nearby bins while short.
-  while (static_cast<uint32_t>(P.sz) < F) {
-    if (!depot_refill(P, me, false, wc)) break;
-  }
-  int32_t sz = P.sz;
-  uint32_t taken = static_cast<uint32_t>(sz) < F ? static_cast<uint32_t>(sz) : F;
-  uint32_t rest = F - taken;
-  uint32_t base = 0;
-  if (rest > 0) {
-    base = bump_claim(P, rest);
-    if (base == kNone) {
-      // Pool fully touched: reclaim from every bin before giving up.
+  if (static_cast<uint32_t>(P.sz) < F) {
+    // Short: recycled frames from nearby depot bins first, unless the last
+    // probe found none.
+    if (P.skip == 0) {
       while (static_cast<uint32_t>(P.sz) < F) {
-        if (!depot_refill(P, me, true, wc)) break;
-      }
-      sz = P.sz;
-      taken = static_cast<uint32_t>(sz) < F ? static_cast<uint32_t>(sz) : F;
-      rest = F - taken;
-      if (rest > 0) {
-        base = bump_claim(P, rest);
-        if (base == kNone) {
-          if (lane_id() == 0)
-            raise_error(p, -6 /*GTAP_E_CAPACITY*/, P.pool_id, P.nframes, F, me, -1);
-          return false;
+        if (!depot_refill(P, me, false, wc)) {
+          P.skip = 32;
+          break;
         }
       }
+    } else {
+      --P.skip;
     }
   }
-  r.top = sz;
-  r.taken = taken;
-  r.base = base;
-  P.sz = sz - static_cast<int32_t>(taken);
-  return true;
+  if (static_cast<uint32_t>(P.sz) >= F) {
+    r.top = P.sz;
+    r.taken = F;
+    r.base = 0;
+    P.sz -= static_cast<int32_t>(F);
+    return true;
+  }
+  // Never-used frames: claim F plus a chunk of spares for the local stack.
+  uint32_t spare = (P.stk_cap - static_cast<uint32_t>(P.sz)) >= P.chunk ? P.chunk : 0u;
+  uint32_t base = bump_claim(P, F + spare);
+  if (base == kNone && spare > 0) {
+    spare = 0;
+    base = bump_claim(P, F);
+  }
+  if (base != kNone) {
+    for (uint32_t i = lane_id(); i < spare; i += kWave) P.stk[P.sz + static_cast<int32_t>(i)] = (base + F + i) | P.tag;
+    wave_sync();
+    P.sz += static_cast<int32_t>(spare);
+    r.top = P.sz;
+    r.taken = 0;
+    r.base = base;
+    return true;
+  }
+  // The pool is fully touched: reclaim from every bin before giving up.
+  while (static_cast<uint32_t>(P.sz) < F) {
+    if (!depot_refill(P, me, true, wc)) break;
+  }
+  if (static_cast<uint32_t>(P.sz) >= F) {
+    r.top = P.sz;
+    r.taken = F;
+    r.base = 0;
+    P.sz -= static_cast<int32_t>(F);
+    return true;
+  }
+  if (lane_id() == 0) raise_error(p, -6 /*GTAP_E_CAPACITY*/, P.pool_id, P.nframes, F, me, -1);
+  return false;
 }
 
 GTAP_DEV uint32_t alloc_id(const PoolView &P, const AllocResult &r, uint32_t g) {
@@ -303,24 +331,25 @@ GTAP_DEV uint32_t pop_batch(const Params &p, WaveLds &L, uint32_t me, uint32_t q
   return static_cast<uint32_t>(claim);
 }
 
-// StealBatch.  Lanes [0, steal_probes) each read the count of one random
-// victim's deque q in a single round trip; the fullest victim is locked, a
-// share of its entries is claimed by CAS on count, the IDs are loaded from
-// head, then head advances and the lock is released.
-GTAP_DEV uint32_t steal_batch(const Params &p, uint32_t me, uint32_t &rng, uint32_t q, uint32_t cnt,
-                              uint32_t &tid, WaveCounters &wc) {
+// StealBatch.  Lanes [0, steal_probes * Q) each read the count of one
+// (random victim, queue) pair in a single round trip; the fullest deque is
+// locked, a share of its entries is claimed by CAS on count, the IDs are
+// loaded from head, then head advances and the lock is released.  With DAQ
+// this takes the victim's fullest queue (Sec. 5.1.3, thread mode).
+GTAP_DEV uint32_t steal_batch(const Params &p, uint32_t me, uint32_t &rng, uint32_t cnt, uint32_t &tid,
+                              uint32_t &qout, WaveCounters &wc) {
   const uint32_t ln = lane_id();
   wc.add(ST_STEAL_ATTEMPTS, 1);
-  // per-lane victim from the wave's xorshift state and the lane index
+  const uint32_t probe = ln / p.Q, qi = ln % p.Q;
   const uint32_t base = xorshift32(rng);
-  uint32_t v = (base + ln * 0x9E3779B9u) ^ (ln * 0x85EBCA6Bu);
+  uint32_t v = (base + probe * 0x9E3779B9u) ^ (probe * 0x85EBCA6Bu);
   v ^= v >> 15;
   v *= 0x2C1B3C6Du;
   v ^= v >> 12;
   v = v % (p.nwaves - 1);
   if (v >= me) ++v;
   int32_t c = 0;
-  if (ln < p.steal_probes) c = ld_relaxed(&deque_meta(p, v, q)->count);
+  if (probe < p.steal_probes) c = ld_relaxed(&deque_meta(p, v, qi)->count);
   // wave arg-max of the observed counts
   uint32_t key = c > 0 ? ((static_cast<uint32_t>(c < (1 << 24) ? c : (1 << 24) - 1) << 6) | ln) : 0u;
 #pragma unroll
@@ -330,7 +359,9 @@ GTAP_DEV uint32_t steal_batch(const Params &p, uint32_t me, uint32_t &rng, uint3
   }
   key = uniform(key);
   if (key == 0) return 0;
-  const uint32_t victim = uniform(static_cast<uint32_t>(__shfl(static_cast<int>(v), static_cast<int>(key & 63u), 64)));
+  const uint32_t win = key & 63u;
+  const uint32_t victim = uniform(static_cast<uint32_t>(__shfl(static_cast<int>(v), static_cast<int>(win), 64)));
+  const uint32_t q = win % p.Q;
   DequeMeta *m = deque_meta(p, victim, q);
   const int32_t want = static_cast<int32_t>(kWave - cnt);
   int32_t claim = 0;
@@ -362,46 +393,65 @@ GTAP_DEV uint32_t steal_batch(const Params &p, uint32_t me, uint32_t &rng, uint3
     drain();
     st_relaxed(&m->lock, 0);
   }
+  qout = q;
   wc.add(ST_STOLEN, static_cast<uint32_t>(claim));
   wc.add(ST_STEAL_BATCHES, 1);
   return static_cast<uint32_t>(claim);
 }
 
-// PushBatch: write n IDs at the tail of own deque q, drain, raise count once.
+// The owner's fullest deque (DAQ: a wavefront with no tasks starts a batch from
+// it); kNone if every hint says empty.
+GTAP_DEV uint32_t fullest_own_queue(const Params &p, const WaveLds &L, uint32_t me) {
+  const uint32_t ln = lane_id();
+  int32_t c = 0;
+  if (ln < p.Q && L.hint[ln]) c = ld_relaxed(&deque_meta(p, me, ln)->count);
+  uint32_t key = c > 0 ? ((static_cast<uint32_t>(c < (1 << 24) ? c : (1 << 24) - 1) << 6) | ln) : 0u;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint32_t other = __shfl_xor(key, d, 64);
+    key = other > key ? other : key;
+  }
+  key = uniform(key);
+  return key == 0 ? kNone : (key & 63u);
+}
+
+// Make room for n more IDs in own deque q: head only grows, so a stale copy
+// makes the check conservative; reload it only when the check fails.
+GTAP_DEV bool ensure_room(const Params &p, WaveLds &L, uint32_t me, uint32_t q, uint32_t n) {
+  const uint32_t t = L.tail[q];
+  if (t + n - L.head_seen[q] <= p.cap) return true;
+  uint32_t ok = 1, h = 0;
+  if (lane_id() == 0) {
+    DequeMeta *m = deque_meta(p, me, q);
+    h = ld_relaxed(&m->head);
+    uint32_t spins = 0;
+    while (t + n - h > p.cap) {
+      if (++spins > kPushSpinLimit) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      h = ld_relaxed(&m->head);
+    }
+  }
+  ok = uniform(ok);
+  h = uniform(h);
+  wave_sync();
+  if (lane_id() == 0) L.head_seen[q] = h;
+  wave_sync();
+  if (!ok && lane_id() == 0) raise_error(p, -6 /*GTAP_E_CAPACITY*/, 2, p.cap, n, me, -1);
+  return ok != 0;
+}
+
+// PushBatch: write n IDs at the tail of own deque q, drain, raise count once
+// (the fence and the atomic are paid once per batch, Sec. 5.1.1).
 template <class IdFn>
 GTAP_DEV bool push_batch(const Params &p, WaveLds &L, uint32_t me, uint32_t q, uint32_t n,
                          IdFn id_of, WaveCounters &wc) {
   if (n == 0) return true;
-  DequeMeta *m = deque_meta(p, me, q);
+  if (!ensure_room(p, L, me, q, n)) return false;
   const uint32_t ln = lane_id();
   const uint32_t t = L.tail[q];
-  uint32_t ok = 1;
-  // head only grows, so a stale copy makes the capacity check conservative;
-  // reload it only when the check fails.
-  if (t + n - L.head_seen[q] > p.cap) {
-    uint32_t h = 0;
-    if (ln == 0) {
-      h = ld_relaxed(&m->head);
-      uint32_t spins = 0;
-      while (t + n - h > p.cap) {
-        if (++spins > kPushSpinLimit) {
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-        h = ld_relaxed(&m->head);
-      }
-    }
-    ok = uniform(ok);
-    h = uniform(h);
-    wave_sync();
-    if (ln == 0) L.head_seen[q] = h;
-    wave_sync();
-  }
-  if (!ok) {
-    if (ln == 0) raise_error(p, -6 /*GTAP_E_CAPACITY*/, 2, p.cap, n, me, -1);
-    return false;
-  }
   uint32_t *ring = deque_ring(p, me, q);
   for (uint32_t i = ln; i < n; i += kWave) co_st32(ring + ((t + i) & (p.cap - 1)), id_of(i));
   wave_sync();
@@ -410,7 +460,7 @@ GTAP_DEV bool push_batch(const Params &p, WaveLds &L, uint32_t me, uint32_t q, u
     L.hint[q] = 1;
   }
   drain();  // slots (and the frames they name) complete before count rises
-  if (ln == 0) fetch_add_relaxed(&m->count, static_cast<int32_t>(n));
+  if (ln == 0) fetch_add_relaxed(&deque_meta(p, me, q)->count, static_cast<int32_t>(n));
   wave_sync();
   wc.add(ST_PUSHED, n);
   wc.add(ST_PUSH_BATCHES, 1);
@@ -465,29 +515,6 @@ GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
   write_frame(frame_ptr(p, id), kNone, j, state_word(kind, 0, 0), c);
 }
 
-// ---------------------------------------------------------------------------
-// Staging.  The task IDs made runnable in one iteration are ordered
-//   S = resumed parents (nres) ++ small-frame children (Fs) ++ big-frame children (Fb)
-// and the first `keep` = min(64, |S|) run on the lanes next iteration; the rest
-// are pushed.  A retained small-frame child gets no frame: its image goes to
-// LDS and it runs as a frameless task.  Frames are allocated only for
-// children that are pushed, for big-frame children (their buffer is written
-// while they run) and for a frameless task that forks (its join counter and
-// resume point must live somewhere other wavefronts can reach).
-struct Staged {
-  uint32_t nres, Fs, Fb, keep, gs0, nself;
-  AllocResult as, ab;
-};
-
-// Frame ID of staged entry i (kNone for a retained frameless child).
-GTAP_DEV uint32_t staged_id(const WaveLds &L, const PoolView &PS, const PoolView &PB,
-                            const Staged &S, uint32_t i) {
-  if (i < S.nres) return L.res[i];
-  const uint32_t g = i - S.nres;
-  if (g < S.Fs) return g < S.gs0 ? kNone : alloc_id(PS, S.as, S.nself + g - S.gs0);
-  return alloc_id(PB, S.ab, g - S.Fs);
-}
-
 template <int WPB>
 __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   __shared__ WaveLds lds_all[WPB];
@@ -515,8 +542,8 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
 
   uint32_t cnt = 0;
   uint32_t tid = kNone;
-  uint32_t npend = 0;  // parents resumed in the last iteration (IDs in L.res)
-  const uint32_t q = 0;  // single queue (DAQ classes select q when enabled)
+  uint32_t npend = 0;    // parents resumed in the last iteration (IDs in L.res)
+  uint32_t cur_q = 0;    // DAQ class of the batch on the lanes
 
   // Root admission: job j goes to wave j mod P (the paper's grid leader
   // enqueues the single root; with many jobs every wave seeds its share).
@@ -532,7 +559,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       const uint32_t keep = nroots < kWave ? nroots : kWave;
       if (ln < keep) tid = alloc_id(PS, ar, ln);
       cnt = keep;
-      push_batch(p, L, me, q, nroots - keep, [&](uint32_t i) { return alloc_id(PS, ar, keep + i); }, wc);
+      push_batch(p, L, me, 0, nroots - keep, [&](uint32_t i) { return alloc_id(PS, ar, keep + i); }, wc);
     }
   }
 
@@ -552,10 +579,24 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       cnt = npend;
       npend = 0;
     }
-    // popped and stolen tasks are children with frames (resume point 0)
+    // popped and stolen tasks are children with frames (resume point 0); a
+    // batch is topped up from the queue of its class, an empty wavefront
+    // starts from its fullest queue
     const uint32_t cnt0 = cnt;
-    if (cnt < kWave) cnt += pop_batch(p, L, me, q, cnt, tid, wc);
-    if (cnt < p.steal_below && p.nwaves > 1) cnt += steal_batch(p, me, rng, q, cnt, tid, wc);
+    if (cnt < kWave) {
+      uint32_t qp = cur_q;
+      if (cnt == 0 && p.Q > 1) {
+        qp = fullest_own_queue(p, L, me);
+        if (qp != kNone) cur_q = qp;
+      }
+      if (qp != kNone) cnt += pop_batch(p, L, me, qp, cnt, tid, wc);
+    }
+    if (cnt < p.steal_below && p.nwaves > 1) {
+      uint32_t qs = cur_q;
+      const uint32_t got = steal_batch(p, me, rng, cnt, tid, qs, wc);
+      if (got > 0 && cnt == 0) cur_q = qs;
+      cnt += got;
+    }
     if (ln >= cnt0) tcont = false;
     if (cnt == 0) {
       ++idle;
@@ -672,73 +713,155 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     }
     const bool fork = (o.type == OUT_FORK);
     const bool need_self = fork && tid == kNone;  // a frameless task suspends: give it a frame
-    const uint32_t fs = (fork && !o.big) ? o.nchild : 0u;
-    const uint32_t fb = (fork && o.big) ? o.nchild : 0u;
-    Staged S;
-    const uint32_t offs = wave_exclusive_scan(fs, &S.Fs);
-    const uint32_t offb = wave_exclusive_scan(fb, &S.Fb);
+    uint32_t F = 0;
+    const uint32_t off = wave_exclusive_scan(fork ? o.nchild : 0u, &F);
     const uint64_t m_self = ballot(need_self);
-    S.nself = __popcll(m_self);
-    S.nres = npend;
-    const uint32_t total = S.nres + S.Fs + S.Fb;
-    S.keep = total < kWave ? total : kWave;
-    S.gs0 = (S.keep - S.nres) < S.Fs ? (S.keep - S.nres) : S.Fs;
-    L.offs_s[ln] = offs;
-    L.offs_b[ln] = offb;
-    if (ln == 0) {
-      L.offs_s[kWave] = S.Fs;
-      L.offs_b[kWave] = S.Fb;
-    }
-    bool ok = alloc_frames(p, PS, me, S.nself + (S.Fs - S.gs0), S.as, wc);
-    ok = ok && alloc_frames(p, PB, me, S.Fb, S.ab, wc);
-    if (!ok) break;
+    const uint32_t nres = npend;
+    L.offs[ln] = off;
+    if (ln == 0) L.offs[kWave] = F;
+    AllocResult aself;
+    if (!alloc_frames(p, PS, me, __popcll(m_self), aself, wc)) break;
     wave_sync();
-    wc.add(ST_SPAWNS, S.Fs + S.Fb);
+    wc.add(ST_SPAWNS, F);
     if (fork) {
       // suspend at the join: resume point 1, count = #children, sums 0
-      const uint32_t self = need_self ? alloc_id(PS, S.as, rank_below(m_self)) : tid;
+      const uint32_t self = need_self ? alloc_id(PS, aself, rank_below(m_self)) : tid;
       uint32_t *f = frame_ptr(p, self);
       if (need_self) co_st64(frame64(f), pack(o.parent, o.job));
       co_st32(f + FW_STATE, state_word(o.kind, 1, 0));
       st_relaxed(bigacc_ptr(f), static_cast<int64_t>(0));
       st_relaxed(join_ptr(f), static_cast<int64_t>(o.nchild));
-      L.desc[ln] = ForkDesc{self, o.job, o.ckind | (o.d[5] << 8), o.d[0], o.d[1], o.d[2], o.d[3], o.d[4]};
+      L.desc[ln] = ForkDesc{self, o.job, o.ckind | (o.big << 7) | (o.d[5] << 8),
+                            o.d[0], o.d[1], o.d[2], o.d[3], o.d[4]};
     }
+    if (ln < kMaxQueues) L.qn[ln] = (ln == 0) ? F : 0u;
     wave_sync();
-    // children, built by the whole wavefront
-    for (uint32_t g = ln; g < S.Fs + S.Fb; g += kWave) {
-      const bool isbig = g >= S.Fs;
-      const uint32_t gg = isbig ? g - S.Fs : g;
-      const uint32_t *offs_arr = isbig ? L.offs_b : L.offs_s;
-      const uint32_t own = owner_of(offs_arr, gg);
-      const uint32_t j = gg - offs_arr[own];
-      const ForkDesc dsc = L.desc[own];
-      const uint32_t ckind = dsc.ckind_d5 & 0xFFu;
-      const uint32_t d[6] = {dsc.d0, dsc.d1, dsc.d2, dsc.d3, dsc.d4, dsc.ckind_d5 >> 8};
-      ChildInit c;
-      make_child(ckind, d, j, c);
-      const uint32_t st = state_word(ckind, 0, 0);
-      if (!isbig && gg < S.gs0) {
-        uint4 *v = L.vdesc + 2 * (S.nres + gg);
-        v[0] = make_uint4(dsc.self, dsc.job, st, c.p[0]);
-        v[1] = make_uint4(c.p[1], c.p[2], c.p[3], c.p[4]);
-      } else {
-        const uint32_t cid = isbig ? alloc_id(PB, S.ab, gg) : alloc_id(PS, S.as, S.nself + gg - S.gs0);
-        write_frame(frame_ptr(p, cid), dsc.self, dsc.job, st, c);
+
+    // ---- DAQ counting pass: children per class; the fullest class is kept ----
+    uint32_t R = 0;
+    if (p.Q > 1 && F > 0) {
+      if (ln < kMaxQueues) L.qn[ln] = 0;
+      wave_sync();
+      for (uint32_t g0 = 0; g0 < F; g0 += kWave) {
+        const uint32_t g = g0 + ln;
+        uint32_t c = kNone;
+        if (g < F) {
+          const uint32_t own = owner_of(L.offs, g);
+          const ForkDesc dsc = L.desc[own];
+          const uint32_t d[6] = {dsc.d0, dsc.d1, dsc.d2, dsc.d3, dsc.d4, dsc.ckind_big_d5 >> 8};
+          ChildInit ci;
+          make_child(dsc.ckind_big_d5 & 0x7Fu, d, g - L.offs[own], ci);
+          c = child_class(p, dsc.job, dsc.ckind_big_d5 & 0x7Fu, ci);
+          if (g < kClassCache) L.cls[g] = static_cast<uint8_t>(c);
+        }
+        for (uint32_t qq = 0; qq < p.Q; ++qq) {
+          const uint32_t k = __popcll(ballot(c == qq));
+          if (ln == 0) L.qn[qq] += k;
+        }
+      }
+      wave_sync();
+      uint32_t best = 0;
+      for (uint32_t qq = 1; qq < p.Q; ++qq)
+        if (L.qn[qq] > L.qn[best]) best = qq;
+      R = uniform(best);
+    }
+    const uint32_t nR = L.qn[R];
+    const uint32_t keep = (kWave - nres) < nR ? (kWave - nres) : nR;
+    bool room = true;
+    for (uint32_t qq = 0; qq < p.Q; ++qq) {
+      const uint32_t n = L.qn[qq] - (qq == R ? keep : 0u);
+      if (n > 0) room = room && ensure_room(p, L, me, qq, n);
+    }
+    if (!room) break;
+
+    // ---- build pass: children are retained (class R, first `keep` of them)
+    // or written to a frame and placed in their class's deque ----
+    if (ln < kMaxQueues) L.qbase[ln] = 0;
+    wave_sync();
+    bool alloc_ok = true;
+    for (uint32_t g0 = 0; g0 < F; g0 += kWave) {
+      const uint32_t g = g0 + ln;
+      const bool act = g < F;
+      uint32_t own = 0, j = 0, c = 0;
+      ForkDesc dsc{};
+      ChildInit ci;
+      if (act) {
+        own = owner_of(L.offs, g);
+        j = g - L.offs[own];
+        dsc = L.desc[own];
+        const uint32_t d[6] = {dsc.d0, dsc.d1, dsc.d2, dsc.d3, dsc.d4, dsc.ckind_big_d5 >> 8};
+        make_child(dsc.ckind_big_d5 & 0x7Fu, d, j, ci);
+        if (p.Q > 1) c = g < kClassCache ? L.cls[g] : child_class(p, dsc.job, dsc.ckind_big_d5 & 0x7Fu, ci);
+      }
+      const bool big = act && (dsc.ckind_big_d5 & 0x80u);
+      // rank of this child within its class
+      uint32_t rank = g;
+      if (p.Q > 1) {
+        for (uint32_t qq = 0; qq < p.Q; ++qq) {
+          const uint64_t m = ballot(act && c == qq);
+          if (act && c == qq) rank = L.qbase[qq] + rank_below(m);
+          wave_sync();
+          if (ln == 0) L.qbase[qq] += __popcll(m);
+          wave_sync();
+        }
+      }
+      const bool keep_me = act && c == R && rank < keep;
+      const bool frameless = keep_me && !big;
+      const uint64_t m_s = ballot(act && !big && !keep_me);
+      const uint64_t m_b = ballot(big);
+      AllocResult as_, ab_;
+      alloc_ok = alloc_frames(p, PS, me, __popcll(m_s), as_, wc) && alloc_frames(p, PB, me, __popcll(m_b), ab_, wc);
+      if (!alloc_ok) break;
+      wave_sync();
+      if (act) {
+        const uint32_t ck = dsc.ckind_big_d5 & 0x7Fu;
+        const uint32_t st = state_word(ck, 0, c);
+        uint32_t cid = kNone;
+        if (frameless) {
+          uint4 *v = L.vdesc + 2 * (nres + rank);
+          v[0] = make_uint4(dsc.self, dsc.job, st, ci.p[0]);
+          v[1] = make_uint4(ci.p[1], ci.p[2], ci.p[3], ci.p[4]);
+        } else {
+          cid = big ? alloc_id(PB, ab_, rank_below(m_b)) : alloc_id(PS, as_, rank_below(m_s));
+          write_frame(frame_ptr(p, cid), dsc.self, dsc.job, st, ci);
+        }
+        if (keep_me) {
+          L.next_tid[nres + rank] = cid;
+        } else {
+          const uint32_t pos = rank - (c == R ? keep : 0u);
+          co_st32(deque_ring(p, me, c) + ((L.tail[c] + pos) & (p.cap - 1)), cid);
+        }
+      }
+    }
+    if (!alloc_ok) break;
+    // frames and ring slots written this iteration are complete before any
+    // of them is published or run, and this iteration's join RMWs returned
+    drain();
+    {
+      const uint32_t qq = ln;
+      const uint32_t n = (qq < p.Q) ? L.qn[qq] - (qq == R ? keep : 0u) : 0u;
+      if (n > 0) fetch_add_relaxed(&deque_meta(p, me, qq)->count, static_cast<int32_t>(n));
+      wave_sync();
+      if (n > 0) {
+        L.tail[qq] += n;
+        L.hint[qq] = 1;
+      }
+      const uint32_t npushed = uniform(static_cast<uint32_t>(__builtin_amdgcn_readlane(
+          static_cast<int>(wave_inclusive_sum(n)), 63)));
+      if (npushed > 0) {
+        wc.add(ST_PUSHED, npushed);
+        wc.add(ST_PUSH_BATCHES, 1);
       }
     }
     wave_sync();
 
-    // ---- stage: retain the first `keep`, publish the rest ----
-    tid = (ln < S.keep) ? staged_id(L, PS, PB, S, ln) : kNone;
-    tcont = ln < S.nres;
-    cnt = S.keep;
-    const uint32_t npush = total - S.keep;
-    if (!push_batch(p, L, me, q, npush, [&](uint32_t i) { return staged_id(L, PS, PB, S, S.keep + i); }, wc))
-      break;
-    // frames written this iteration are complete before they run, and the
-    // join RMWs have returned
-    if (npush == 0) drain();
+    // ---- next batch: resumed parents, then the retained children ----
+    if (ln < nres) tid = L.res[ln];
+    else if (ln < nres + keep) tid = L.next_tid[ln];
+    else tid = kNone;
+    tcont = ln < nres;
+    cnt = nres + keep;
+    if (keep > 0) cur_q = R;
     const bool resumed = tail && (static_cast<uint64_t>(join_old) & kJoinMask) == run_len;
     const uint64_t m_res = ballot(resumed);
     wave_sync();

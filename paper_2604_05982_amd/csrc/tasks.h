@@ -294,6 +294,40 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
   }
 }
 
+// ---------------------------------------------------------------------------
+// Divergence-Aware Queueing (Sec. 4.2, "The queue Clause"): the class of a new
+// child selects the deque it waits in, and every wavefront batch is filled
+// from one class.  Continuations (resumed parents) are not queued: they are
+// always retained with the batch being formed.
+GTAP_DEV uint32_t bucket_of(const Params &p, uint32_t x) {
+  uint32_t c = 0;
+  while (c + 1 < p.Q && x > static_cast<uint32_t>(p.daq_bounds[c])) ++c;
+  return c;
+}
+
+// Class of child payload c of kind ckind.  GTAP_DAQ_KCLIQUE: a candidate task
+// is classed by min(|C_parent|, outdeg(u)), the spawn-time bound on the size
+// of its intersection and thus on its cost.
+GTAP_DEV uint32_t child_class(const Params &p, uint32_t job, uint32_t ckind, const ChildInit &c) {
+  if (p.Q <= 1) return 0;
+  switch (p.daq_policy) {
+    case 1: {  // by kind
+      const uint32_t k = ckind == TK_FIB ? 0u : ckind == TK_NQ ? 1u : ckind == TK_UTS ? 2u : 3u;
+      return k % p.Q;
+    }
+    case 2: {  // k-clique candidate-set bound
+      if (ckind != TK_KC_CAND) return 0;
+      const uint64_t *a = job_args(p, job);
+      const int32_t *rp = reinterpret_cast<const int32_t *>(a[0]);
+      const uint32_t u = c.p[0], nC = c.p[4];
+      const uint32_t deg = static_cast<uint32_t>(rp[u + 1] - rp[u]);
+      return bucket_of(p, deg < nC ? deg : nC);
+    }
+    default:
+      return 0;
+  }
+}
+
 GTAP_DEV uint32_t nth_set_bit(uint32_t m, uint32_t j) {
   for (uint32_t i = 0; i < j; ++i) m &= m - 1;
   return m & (0u - m);

@@ -237,3 +237,30 @@ def test_submit_validation(gtap, rt):
         rt.submit_nqueens(0)
     with pytest.raises(gtap.GtapError):
         rt.submit_uts(1, THR4, 300)
+
+
+# ---- DAQ: the queue configuration changes the schedule, never the result ----
+@pytest.mark.parametrize("opts", [
+    dict(num_queues=4, daq_policy=2, daq_bounds=[8, 32, 128]),
+    dict(num_queues=2, daq_policy=2, daq_bounds=[4]),
+    dict(num_queues=3, daq_policy=1),
+    dict(num_queues=8, daq_policy=1, num_waves=2, waves_per_group=1),
+])
+def test_daq_configs(gtap, opts):
+    say(f"daq config {opts}")
+    g = graphs.chung_lu(2000, 16, 2.5, 1.0, 1)
+    with make_rt(gtap, **opts) as r:
+        for k in (3, 4, 5):
+            got, st = run_single(r, r.submit_kclique, g.row_ptr32, g.col, k)
+            check(got, st, oracle.kclique(g.row_ptr, g.col, k))
+        for sub, arg, want in ((r.submit_fib, (18,), oracle.fib(18)),
+                               (r.submit_uts, (9, THR4, 7), oracle.uts(9, THR4, 7))):
+            got, st = run_single(r, sub, *arg)
+            check(got, st, want)
+        # a mixed batch spreads over the classes
+        jobs = [(r.submit_fib(15), oracle.fib(15).value), (r.submit_nqueens(8), oracle.nqueens(8).value),
+                (r.submit_uts(4, THR4, 6), oracle.uts(4, THR4, 6).value),
+                (r.submit_kclique(g.row_ptr32, g.col, 4), oracle.kclique(g.row_ptr, g.col, 4).value)]
+        r.run()
+        for jid, want in jobs:
+            assert r.result(jid) == want
