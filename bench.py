@@ -113,6 +113,227 @@ def cpu_baseline(min_seconds: float = 10.0, max_seconds: float = 30.0) -> dict:
                       f"{el:.1f} s on one host thread"}
 
 
+def bench_kclique7(args, gtap) -> int:
+    """7-cliques of the seeded n=10^6, mean degree 40, exponent 2.1 Chung-Lu graph
+    (thread mode; DAQ with 4 candidate-size buckets when --queues 4)."""
+    import torch
+    from synth import graphs
+    g = graphs.chung_lu(1000000, 40, 2.1, 0.6, 2)
+    want = None
+    with open(os.path.join(ROOT, "tests", "golden", "kclique_chung_lu.txt")) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) == 6 and f[0] == "n1000000_d40_g2.1_cap0.6_s2" and f[2] == "7":
+                want = (f[1], int(f[3]))
+    opts = dict(num_waves=args.num_waves, waves_per_group=args.waves_per_group, deque_capacity=1 << 17,
+                small_frames=1 << 25, big_frames=1 << 23, big_frame_ints=max(320, g.max_outdeg),
+                timeout_ms=60000, steal_below=args.steal_below)
+    if args.queues > 1:
+        opts.update(num_queues=args.queues, daq_policy=2, daq_bounds=[8, 32, 128][: args.queues - 1])
+    rt = gtap.Runtime(**opts)
+    rp = torch.as_tensor(g.row_ptr32).cuda()
+    col = torch.as_tensor(g.col).cuda()
+    for _ in range(args.warmup):
+        j = rt.submit_kclique(rp, col, 7, max_outdeg=g.max_outdeg)
+        rt.run()
+    torch.cuda.synchronize()
+    tot, kms = {}, []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        j = rt.submit_kclique(rp, col, 7, max_outdeg=g.max_outdeg)
+        rt.run()
+        st = rt.stats()
+        kms.append(st["kernel_ms"])
+        for k, v in st.items():
+            if isinstance(v, int):
+                tot[k] = tot.get(k, 0) + v
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    count = rt.result(j)
+    ok = want is not None and want == (g.checksum(), count)
+    out = {"metric": METRIC, "value": count * args.steps / el, "unit": "k-cliques/s",
+           "tasks_per_s": tot["tasks"] / el, "kernel_ms": sum(kms) / len(kms), "count": count,
+           "matches_oracle": ok, "queues": args.queues, "waves": st["num_waves"],
+           "steps": args.steps, "warmup": args.warmup, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "7-cliques, Chung-Lu n=1e6, mean degree 40, exponent 2.1, cap 0.6, seed 2",
+                      "graph_edges": g.m_undirected, "max_outdeg": g.max_outdeg},
+           "runtime_counters_per_step": {k: v // args.steps for k, v in tot.items()}}
+    rt.close()
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
+
+
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def _latency_summary(res, arrivals, classes) -> dict:
+    """p50/p99 of host-observed completion minus scheduled arrival (ms)."""
+    lat = [1e3 * (r.done_s - a) for r, a in zip(res, arrivals)]
+    out = {"p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "max_ms": max(lat) if lat else None}
+    for c in sorted(set(classes)):
+        lc = [x for x, cc in zip(lat, classes) if cc == c]
+        out[c] = {"p50_ms": _pct(lc, 50), "p99_ms": _pct(lc, 99), "jobs": len(lc)}
+    return out
+
+
+def serving_trace(gtap, rt, g, n_jobs, seed, torch):
+    """The batched/serving job mix: k-clique jobs on induced subgraphs of g
+    (their CSR staged on the device up front) and UTS jobs."""
+    import numpy as np
+    from synth import graphs, serving
+    specs = serving.serving_mix(n_jobs, seed)
+    kc = [sp for sp in specs if sp.kind == "kclique"]
+    subs = graphs.induced_many(g, [(sp.s, sp.sub_seed) for sp in kc], threads=min(16, os.cpu_count() or 1))
+    rp_off = np.cumsum([0] + [h.n + 1 for h in subs])
+    col_off = np.cumsum([0] + [h.col.size for h in subs])
+    rp_dev = torch.as_tensor(np.concatenate([h.row_ptr.astype(np.int32) for h in subs] or
+                                            [np.zeros(1, np.int32)])).cuda()
+    col_dev = torch.as_tensor(np.concatenate([h.col for h in subs] + [np.zeros(1, np.int32)])).cuda()
+    entries, classes, it = [], [], 0
+    for sp in specs:
+        if sp.kind == "kclique":
+            h = subs[it]
+            a = gtap.gtap_kclique_args(rp_dev.data_ptr() + 4 * int(rp_off[it]),
+                                       col_dev.data_ptr() + 4 * int(col_off[it]), h.n, sp.k, 64, h.max_outdeg)
+            entries.append((gtap.GTAP_KIND_KCLIQUE, a))
+            classes.append("kclique")
+            it += 1
+        else:
+            entries.append(rt.uts_args(sp.seed, gtap.uts_threshold(sp.m), sp.depth))
+            classes.append("uts")
+    staged = {"kclique_jobs": len(kc), "uts_jobs": len(specs) - len(kc),
+              "staged_csr_bytes": int(4 * (rp_dev.numel() + col_dev.numel())),
+              "subgraph_vertices": int(sum(h.n for h in subs)), "subgraph_edges": int(col_off[-1])}
+    return specs, entries, classes, (rp_dev, col_dev), subs, staged
+
+
+def bench_serving(args, gtap) -> int:
+    """Batched and served job mixes against one launch per job (plain)."""
+    import numpy as np
+    import torch
+    from synth import graphs, serving
+    say = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    t0 = time.perf_counter()
+    g = graphs.chung_lu(1000000, 40, 2.1, 0.6, 2)
+    say(f"graph ready {time.perf_counter() - t0:.1f}s max_outdeg={g.max_outdeg}")
+    rt = gtap.Runtime(num_waves=args.num_waves, waves_per_group=args.waves_per_group, max_jobs=1 << 15,
+                      small_frames=1 << 26, big_frames=1 << 21, big_frame_ints=max(320, g.max_outdeg),
+                      deque_capacity=1 << 16, timeout_ms=300000)
+    headroom = 1 << 25
+    specs, entries, classes, keep, subs, staged = serving_trace(gtap, rt, g, args.jobs, 5, torch)
+    n = len(entries)
+    say(f"trace ready {time.perf_counter() - t0:.1f}s {staged}")
+
+    def served(arrivals):
+        jobs = rt.trace([(t, e) for t, e in zip(arrivals, entries)])
+        rt.serve_start(max_inflight=args.inflight, headroom_small=headroom)
+        res = rt.trace_run(jobs, timeout_ms=280000)
+        rt.serve_stop()
+        return res, rt.stats()
+
+    # (i) saturated: every job at t = 0
+    zeros = np.zeros(n)
+    tb = time.perf_counter()
+    ids = []
+    for kind, a in entries:
+        ids.append(gtap.gtap_submit(rt.ctx, kind, a))
+    rt.run()
+    batch_s = time.perf_counter() - tb
+    res_batch = [rt.result(j) for j in ids]
+    st_batch = rt.stats()
+    say(f"batch launch {batch_s:.2f}s")
+    res_sat, st_sat = served(zeros)
+    served_s = max(r.done_s for r in res_sat)
+    say(f"served saturated {served_s:.2f}s")
+    plain_sat = rt.trace_run_plain(rt.trace([(0.0, e) for e in entries]))
+    plain_s = max(r.done_s for r in plain_sat)
+    say(f"plain saturated {plain_s:.2f}s")
+    r_b, r_s, r_p = res_batch, [r.result for r in res_sat], [r.result for r in plain_sat]
+    alone_eq_mix = r_b == r_p and r_s == r_p
+
+    # calibration on another trace seed: saturated served throughput
+    cal_specs, cal_entries, _, cal_keep, _, _ = serving_trace(gtap, rt, g, max(1, args.jobs // 4), 6, torch)
+    cal_jobs = rt.trace([(0.0, e) for e in cal_entries])
+    rt.serve_start(max_inflight=args.inflight, headroom_small=headroom)
+    cal_res = rt.trace_run(cal_jobs, timeout_ms=280000)
+    rt.serve_stop()
+    cal_rate = len(cal_entries) / max(r.done_s for r in cal_res)
+    del cal_keep
+    say(f"calibrated saturated rate {cal_rate:.1f} jobs/s")
+
+    # (ii) open loop at 0.8 x the calibrated saturated rate (and a sweep)
+    rhos = [0.8] + ([0.3, 0.5, 0.7, 0.9] if args.sweep else [])
+    open_loop = {}
+    for rho in rhos:
+        arr = serving.poisson_arrivals(n, rho * cal_rate, 55)
+        res_o, _ = served(arr)
+        ok = [r.result for r in res_o] == r_p
+        entry = {"rate_jobs_per_s": rho * cal_rate, "served": _latency_summary(res_o, arr, classes),
+                 "served_exact": ok}
+        alone_eq_mix = alone_eq_mix and ok
+        if rho == 0.8:
+            res_po = rt.trace_run_plain(rt.trace([(t, e) for t, e in zip(arr, entries)]))
+            entry["plain"] = _latency_summary(res_po, arr, classes)
+            alone_eq_mix = alone_eq_mix and [r.result for r in res_po] == r_p
+        open_loop[f"rho_{rho}"] = entry
+        say(f"open loop rho={rho}: {json.dumps(entry)[:300]}")
+
+    out = {"metric": METRIC, "value": n / batch_s, "unit": "jobs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+           "data": "synthetic",
+           "config": {"workload": f"{n} jobs, trace seed 5: 60% k-clique (k 4..8, induced subgraphs of "
+                                  "log-uniform 1e3..2e5 vertices of the n=1e6 Chung-Lu graph), 40% UTS "
+                                  "(m 2..4, depth 8..14)", **staged, "max_inflight": args.inflight,
+                      "waves": st_batch["num_waves"]},
+           "saturated_jobs_per_s": {"batch_launch": n / batch_s, "served": n / served_s, "plain": n / plain_s},
+           "saturated_tasks_per_s_batch": st_batch["tasks"] / batch_s,
+           "batch_kernel_ms": st_batch["kernel_ms"], "tasks_total": st_batch["tasks"],
+           "open_loop": open_loop, "all_results_equal_alone_vs_mix": alone_eq_mix,
+           "served_admitted": st_sat["admitted"]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = serving_cpu_baseline(specs, subs, res_batch)
+        alone_eq_mix = alone_eq_mix and out["cpu_baseline"]["sample_matches"]
+    del keep
+    rt.close()
+    print(json.dumps(out), flush=True)
+    return 0 if alone_eq_mix else 1
+
+
+def serving_cpu_baseline(specs, subs, gpu_results, budget_s: float = 15.0) -> dict:
+    """The oracle over the trace's jobs in order, smallest first, until the
+    time budget: jobs/s on one host core, and the sampled results checked."""
+    import oracle
+    order = []
+    it = 0
+    for i, sp in enumerate(specs):
+        if sp.kind == "kclique":
+            order.append((subs[it].col.size, i, it))
+            it += 1
+        else:
+            order.append((sp.m ** sp.depth, i, -1))
+    order.sort()
+    done, match = 0, True
+    t0 = time.perf_counter()
+    for _, i, it in order:
+        sp = specs[i]
+        if sp.kind == "kclique":
+            h = subs[it]
+            v = oracle.kclique(h.row_ptr, h.col, sp.k).value
+        else:
+            v = oracle.uts(sp.seed, oracle.uts_threshold(sp.m), sp.depth).value
+        match = match and v == gpu_results[i]
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "jobs/s", "cores": 1, "kind": "oracle",
+            "sample": f"the {done} smallest of {len(specs)} trace jobs, {el:.1f} s on one host thread "
+                      "(a lower bound on the oracle's time for the whole trace)",
+            "sample_matches": match}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +345,13 @@ def main() -> int:
     ap.add_argument("--steal-below", type=int, default=64)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run only a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--workload", default="microbench", choices=("microbench", "kclique7", "serving"),
+                    help="kclique7: 7-cliques of the n=10^6 Chung-Lu graph (DAQ comparison); "
+                         "serving: batched / served job mix against one launch per job")
+    ap.add_argument("--jobs", type=int, default=20000, help="serving: jobs in the trace")
+    ap.add_argument("--inflight", type=int, default=1024, help="serving: admission limit")
+    ap.add_argument("--sweep", action="store_true", help="serving: also rho 0.3/0.5/0.7/0.9")
+    ap.add_argument("--queues", type=int, default=1, help="kclique7: DAQ queues (1 = off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -136,6 +364,10 @@ def main() -> int:
         copy_probe(args.copy_probe)
         return 0
     from paper_2604_05982_amd import gtap
+    if args.workload == "kclique7":
+        return bench_kclique7(args, gtap)
+    if args.workload == "serving":
+        return bench_serving(args, gtap)
 
     rt = gtap.Runtime(waves_per_group=args.waves_per_group, num_waves=args.num_waves,
                       steal_below=args.steal_below, small_frames=1 << 25, timeout_ms=60000)

@@ -185,6 +185,7 @@ typedef struct gtap_stats {
     uint64_t depot_refills;
     uint64_t busy_cycles;    /* shader-clock cycles in iterations that ran tasks */
     uint64_t idle_cycles;    /* shader-clock cycles in iterations that found none */
+    uint64_t admitted;       /* serving: jobs admitted from the ring           */
     double kernel_ms;        /* device time of the last run's persistent kernel */
     int32_t num_waves;
     int32_t waves_per_group;
@@ -200,6 +201,72 @@ typedef struct gtap_error_report {
     int32_t wave;       /* wavefront that detected it                          */
     int32_t job;        /* job slot being served, -1 if unknown                */
 } gtap_error_report;
+
+/* ---- serving: continuous admission into a running kernel ------------------ */
+/* Not in the paper (its launch runs one root to completion); this is the
+ * serving extension of the same runtime.  The host appends jobs to an
+ * admission ring in pinned host memory while the persistent kernel runs; a
+ * few wavefronts poll the ring and admit jobs while fewer than max_inflight
+ * are in flight and the frame pools keep headroom_small / headroom_big
+ * frames free after admission (admission by free frame-pool memory).
+ * Results are written to pinned host memory as roots complete.  Job slots
+ * (max_jobs of them) are reused: ticket t uses slot t mod max_jobs, and a
+ * slot is free again once its previous ticket completed.  k-clique CSR
+ * buffers are borrowed until the job completes. */
+
+/* Reset the scheduler state and launch the persistent kernel in serving mode
+ * on cfg->stream (asynchronous).  cfg->timeout_ms bounds the whole serving
+ * session.  Errors: GTAP_E_STATE (jobs pending or already serving),
+ * GTAP_E_NOMEM (pinned memory), GTAP_E_HIP. */
+int gtap_serve_start(gtap_ctx *ctx, uint32_t max_inflight, uint32_t headroom_small,
+                     uint32_t headroom_big);
+
+/* Append one job to the admission ring; *ticket identifies it.  Arguments as
+ * for gtap_submit.  GTAP_E_FULL when the job's slot still holds an
+ * unfinished job. */
+int gtap_serve_submit(gtap_ctx *ctx, int32_t kind, const void *args, size_t args_bytes,
+                      uint64_t *ticket);
+
+/* Non-blocking: GTAP_OK and *result once ticket completed, else
+ * GTAP_E_PENDING.  *done_ticks (optional) receives the device wall clock at
+ * completion. */
+int gtap_serve_poll(gtap_ctx *ctx, uint64_t ticket, int64_t *result, uint64_t *done_ticks);
+
+/* Wait (up to wait_ms) for every submitted job, then stop the kernel and
+ * wait for it.  Returns the device's abort code if it aborted, GTAP_E_TIMEOUT
+ * if jobs were still pending after wait_ms (the kernel is stopped anyway once
+ * they drain or its watchdog fires). */
+int gtap_serve_stop(gtap_ctx *ctx, uint32_t wait_ms);
+
+/* One job of a request trace: kind, argument struct (as for gtap_submit,
+ * args_bytes <= 32) and its arrival time in seconds from the trace start. */
+typedef struct gtap_trace_job {
+    int32_t kind;
+    uint32_t args_bytes;
+    double arrival_s;
+    uint64_t args[4];
+} gtap_trace_job;
+
+typedef struct gtap_trace_result {
+    int64_t result;
+    double submit_s;   /* host time the job entered the system               */
+    double done_s;     /* host time its completion was observed              */
+    int32_t status;    /* GTAP_OK, or the error that stopped the trace       */
+    int32_t reserved;
+} gtap_trace_result;
+
+/* Host request loop against a serving kernel (gtap_serve_start first): submit
+ * each job at its arrival time (open loop; a full ring delays it), poll
+ * completions, record host times.  Returns when every job completed, on a
+ * device error, or after timeout_ms. */
+int gtap_trace_run(gtap_ctx *ctx, const gtap_trace_job *jobs, size_t n, gtap_trace_result *out,
+                   uint32_t timeout_ms);
+
+/* Baseline for the same trace: one persistent launch per job, in arrival
+ * order on the context's stream (a job that arrives while another runs
+ * waits).  Not valid while serving. */
+int gtap_trace_run_plain(gtap_ctx *ctx, const gtap_trace_job *jobs, size_t n,
+                         gtap_trace_result *out);
 
 int gtap_stats_get(gtap_ctx *ctx, gtap_stats *out);
 int gtap_last_error(gtap_ctx *ctx, gtap_error_report *out);

@@ -85,15 +85,29 @@ struct alignas(128) JobSlot {
   int64_t result;      // root task's return value
   uint64_t a[8];       // kind arguments (see runtime.hip: pack_args)
   uint64_t t_done;     // device wall clock at completion
-  uint64_t pad[4];
+  uint64_t ticket;     // serving: the job's ticket (set by the admitting wave)
+  uint64_t pad[3];
 };
 static_assert(sizeof(JobSlot) == 128, "job slot is one 128-byte line");
 
 enum StatIdx : uint32_t {
   ST_TASKS = 0, ST_CONTS, ST_SPAWNS, ST_PUSHED, ST_PUSH_BATCHES, ST_POPPED,
   ST_POP_BATCHES, ST_STOLEN, ST_STEAL_BATCHES, ST_STEAL_ATTEMPTS, ST_ITERS,
-  ST_IDLE, ST_SPILLS, ST_REFILLS, ST_BUSY_CYCLES, ST_IDLE_CYCLES, ST_COUNT
+  ST_IDLE, ST_SPILLS, ST_REFILLS, ST_BUSY_CYCLES, ST_IDLE_CYCLES, ST_ADMITTED,
+  ST_COUNT
 };
+
+// Serving: the host appends jobs to a ring in pinned host memory and the
+// running kernel admits them.  Slot t % ring_cap holds ticket t once
+// ring_seq[t % ring_cap] == t + 1.
+struct alignas(16) HostCompletion {
+  int64_t result;
+  uint64_t done;      // ticket + 1 once the job's root completed
+  uint64_t t_done;    // device wall clock at completion
+  uint64_t pad;
+};
+static_assert(sizeof(HostCompletion) == 32, "completion record");
+constexpr uint32_t kAdmitWaves = 8;       // waves that poll the admission ring
 
 // Control block: first 4 KB of the workspace.
 struct alignas(128) Control {
@@ -110,6 +124,11 @@ struct alignas(128) Control {
   uint64_t pad2[15];
   uint64_t bump_big;
   uint64_t pad3[15];
+  uint64_t admitted;        // serving: next ticket to admit (128-byte aligned)
+  uint64_t pad4[15];
+  int64_t live_small;       // serving: frames handed out and not yet returned
+  int64_t live_big;
+  uint64_t pad5[14];
   uint64_t stats[ST_COUNT];
 };
 
@@ -141,6 +160,16 @@ struct Params {
   uint32_t daq_policy;
   int32_t daq_bounds[kMaxQueues - 1];
   uint64_t timeout_ticks;   // watchdog, device wall-clock ticks
+  // serving mode (serving == 0: a batch run over jobs[0, njobs))
+  uint32_t serving;
+  uint32_t ring_cap;        // admission ring slots == job table slots
+  const JobSlot *ring;      // pinned host memory
+  const uint64_t *ring_seq; // pinned host memory
+  HostCompletion *done_host;  // pinned host memory, [ring_cap]
+  const int32_t *stop_host;   // pinned host memory
+  uint32_t max_inflight;    // admitted and not completed
+  uint32_t admit_headroom_small;  // frames that must stay free after admitting a job
+  uint32_t admit_headroom_big;
 };
 
 }  // namespace gtap

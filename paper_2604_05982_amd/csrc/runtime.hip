@@ -8,9 +8,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/gtap.h"
@@ -126,6 +128,9 @@ __global__ void reset_kernel(Params p, uint32_t ndeques) {
     c->err_requested = 0;
     c->bump_small = 0;
     c->bump_big = 0;
+    c->admitted = 0;
+    c->live_small = 0;
+    c->live_big = 0;
     for (int s = 0; s < static_cast<int>(ST_COUNT); ++s) c->stats[s] = 0;
   }
 }
@@ -148,6 +153,13 @@ struct gtap_ctx {
   bool have_done = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   uint32_t clock_khz = 100000;
+  // serving
+  bool serving = false;
+  JobSlot *ring = nullptr;          // pinned host memory
+  uint64_t *ring_seq = nullptr;     // pinned host memory
+  HostCompletion *done_host = nullptr;
+  int32_t *stop_host = nullptr;
+  uint64_t next_ticket = 0;
   gtap_stats stats{};
   gtap_error_report err{};
 };
@@ -261,10 +273,11 @@ int gtap_init(const gtap_config *cfg, gtap_ctx **out) {
   return GTAP_OK;
 }
 
-int gtap_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, uint64_t *job_id) {
-  if (!c || !args) return GTAP_E_INVAL;
-  if (c->pending.size() >= c->cfg.max_jobs) return GTAP_E_FULL;
-  JobSlot J;
+}  // extern "C"
+
+// Validate a root task's arguments and pack them into a job slot.
+static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, JobSlot &J) {
+  if (!args) return GTAP_E_INVAL;
   std::memset(&J, 0, sizeof(J));
   J.kind = static_cast<uint32_t>(kind);
   switch (kind) {
@@ -274,7 +287,7 @@ int gtap_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, 
       std::memcpy(&a, args, sizeof(a));
       if (a.n < 0 || a.n > 92) return GTAP_E_INVAL;
       J.a[0] = static_cast<uint64_t>(a.n);
-      break;
+      return GTAP_OK;
     }
     case GTAP_KIND_NQUEENS: {
       if (args_bytes != sizeof(gtap_nqueens_args)) return GTAP_E_INVAL;
@@ -283,7 +296,7 @@ int gtap_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, 
       if (a.n < 1 || a.n > 31) return GTAP_E_INVAL;
       J.a[0] = static_cast<uint64_t>(a.n);
       J.a[1] = (1ull << a.n) - 1ull;
-      break;
+      return GTAP_OK;
     }
     case GTAP_KIND_UTS: {
       if (args_bytes != sizeof(gtap_uts_args)) return GTAP_E_INVAL;
@@ -293,7 +306,7 @@ int gtap_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, 
       J.a[0] = a.seed;
       J.a[1] = a.threshold;
       J.a[2] = static_cast<uint64_t>(a.max_depth);
-      break;
+      return GTAP_OK;
     }
     case GTAP_KIND_KCLIQUE: {
       if (args_bytes != sizeof(gtap_kclique_args)) return GTAP_E_INVAL;
@@ -313,15 +326,61 @@ int gtap_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, 
       J.a[3] = static_cast<uint64_t>(a.k);
       J.a[4] = static_cast<uint64_t>(a.range_leaf);
       J.a[5] = static_cast<uint64_t>(a.max_outdeg);
-      break;
+      return GTAP_OK;
     }
     default:
       return GTAP_E_INVAL;
   }
+}
+
+extern "C" int gtap_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, uint64_t *job_id) {
+  if (!c || !args) return GTAP_E_INVAL;
+  if (c->serving) return GTAP_E_STATE;
+  if (c->pending.size() >= c->cfg.max_jobs) return GTAP_E_FULL;
+  JobSlot J;
+  const int rc = pack_job(c, kind, args, args_bytes, J);
+  if (rc) return rc;
   if (c->pending.empty()) c->pending_first = c->next_job_id;
   c->pending.push_back(J);
   if (job_id) *job_id = c->next_job_id;
   c->next_job_id++;
+  return GTAP_OK;
+}
+
+extern "C" {
+
+// Copy a finished run's statistics and error report into the context.
+static int record_run(gtap_ctx *c, const Control &ctl, float ms) {
+  gtap_stats &s = c->stats;
+  s.tasks = ctl.stats[ST_TASKS];
+  s.conts = ctl.stats[ST_CONTS];
+  s.spawns = ctl.stats[ST_SPAWNS];
+  s.pushed = ctl.stats[ST_PUSHED];
+  s.push_batches = ctl.stats[ST_PUSH_BATCHES];
+  s.popped = ctl.stats[ST_POPPED];
+  s.pop_batches = ctl.stats[ST_POP_BATCHES];
+  s.stolen = ctl.stats[ST_STOLEN];
+  s.steal_batches = ctl.stats[ST_STEAL_BATCHES];
+  s.steal_attempts = ctl.stats[ST_STEAL_ATTEMPTS];
+  s.iterations = ctl.stats[ST_ITERS];
+  s.idle_iterations = ctl.stats[ST_IDLE];
+  s.small_frames_touched = ctl.bump_small;
+  s.big_frames_touched = ctl.bump_big;
+  s.depot_spills = ctl.stats[ST_SPILLS];
+  s.depot_refills = ctl.stats[ST_REFILLS];
+  s.busy_cycles = ctl.stats[ST_BUSY_CYCLES];
+  s.idle_cycles = ctl.stats[ST_IDLE_CYCLES];
+  s.admitted = ctl.stats[ST_ADMITTED];
+  s.kernel_ms = ms;
+  if (ctl.error != 0) {
+    c->err.code = ctl.error;
+    c->err.pool = ctl.err_pool;
+    c->err.capacity = ctl.err_capacity;
+    c->err.requested = ctl.err_requested;
+    c->err.wave = ctl.err_wave;
+    c->err.job = ctl.err_job;
+    return ctl.error;
+  }
   return GTAP_OK;
 }
 
@@ -340,11 +399,13 @@ static int launch_sched(gtap_ctx *c) {
 
 int gtap_run(gtap_ctx *c) {
   if (!c) return GTAP_E_INVAL;
+  if (c->serving) return GTAP_E_STATE;
   const size_t nj = c->pending.size();
   c->err = gtap_error_report{};
   if (nj == 0) return GTAP_OK;
   Params &p = c->params;
   p.njobs = static_cast<uint32_t>(nj);
+  p.serving = 0;
   if (hipMemcpyAsync(p.jobs, c->pending.data(), nj * sizeof(JobSlot), hipMemcpyHostToDevice, c->stream) !=
       hipSuccess)
     return GTAP_E_HIP;
@@ -370,42 +431,217 @@ int gtap_run(gtap_ctx *c) {
   c->pending.clear();
   c->have_done = true;
 
-  gtap_stats &s = c->stats;
-  s.tasks = ctl.stats[ST_TASKS];
-  s.conts = ctl.stats[ST_CONTS];
-  s.spawns = ctl.stats[ST_SPAWNS];
-  s.pushed = ctl.stats[ST_PUSHED];
-  s.push_batches = ctl.stats[ST_PUSH_BATCHES];
-  s.popped = ctl.stats[ST_POPPED];
-  s.pop_batches = ctl.stats[ST_POP_BATCHES];
-  s.stolen = ctl.stats[ST_STOLEN];
-  s.steal_batches = ctl.stats[ST_STEAL_BATCHES];
-  s.steal_attempts = ctl.stats[ST_STEAL_ATTEMPTS];
-  s.iterations = ctl.stats[ST_ITERS];
-  s.idle_iterations = ctl.stats[ST_IDLE];
-  s.small_frames_touched = ctl.bump_small;
-  s.big_frames_touched = ctl.bump_big;
-  s.depot_spills = ctl.stats[ST_SPILLS];
-  s.depot_refills = ctl.stats[ST_REFILLS];
-  s.busy_cycles = ctl.stats[ST_BUSY_CYCLES];
-  s.idle_cycles = ctl.stats[ST_IDLE_CYCLES];
-  s.kernel_ms = ms;
-
-  if (ctl.error != 0) {
-    c->err.code = ctl.error;
-    c->err.pool = ctl.err_pool;
-    c->err.capacity = ctl.err_capacity;
-    c->err.requested = ctl.err_requested;
-    c->err.wave = ctl.err_wave;
-    c->err.job = ctl.err_job;
+  const int rc_run = record_run(c, ctl, ms);
+  if (rc_run != GTAP_OK) {
     c->have_done = false;
-    return ctl.error;
+    return rc_run;
   }
   for (size_t j = 0; j < nj; ++j)
     if (c->done_jobs[j].done != 1) {
       c->have_done = false;
       return GTAP_E_STATE;
     }
+  return GTAP_OK;
+}
+
+// ---- serving -------------------------------------------------------------
+static double host_seconds() {
+  using clk = std::chrono::steady_clock;
+  return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+int gtap_serve_start(gtap_ctx *c, uint32_t max_inflight, uint32_t headroom_small, uint32_t headroom_big) {
+  if (!c) return GTAP_E_INVAL;
+  if (c->serving || !c->pending.empty()) return GTAP_E_STATE;
+  if (max_inflight == 0 || max_inflight > c->cfg.max_jobs) return GTAP_E_INVAL;
+  const size_t R = c->cfg.max_jobs;
+  if (!c->ring) {
+    const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->ring), R * sizeof(JobSlot), fl) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&c->ring_seq), R * sizeof(uint64_t), fl) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&c->done_host), R * sizeof(HostCompletion), fl) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&c->stop_host), 64, fl) != hipSuccess)
+      return GTAP_E_NOMEM;
+  }
+  std::memset(c->ring, 0, R * sizeof(JobSlot));
+  std::memset(c->ring_seq, 0, R * sizeof(uint64_t));
+  std::memset(c->done_host, 0, R * sizeof(HostCompletion));
+  __atomic_store_n(c->stop_host, 0, __ATOMIC_RELEASE);
+  c->next_ticket = 0;
+  c->err = gtap_error_report{};
+  Params &p = c->params;
+  p.njobs = 0;
+  p.serving = 1;
+  p.ring_cap = static_cast<uint32_t>(R);
+  p.ring = c->ring;
+  p.ring_seq = c->ring_seq;
+  p.done_host = c->done_host;
+  p.stop_host = c->stop_host;
+  p.max_inflight = max_inflight;
+  p.admit_headroom_small = headroom_small;
+  p.admit_headroom_big = headroom_big;
+  const uint32_t ndq = c->nwaves * p.Q;
+  hipLaunchKernelGGL(reset_kernel, dim3(std::max<uint32_t>((ndq + 255) / 256, 1)), dim3(256), 0, c->stream, p,
+                     ndq);
+  if (hipGetLastError() != hipSuccess) return GTAP_E_HIP;
+  if (hipEventRecord(c->ev0, c->stream) != hipSuccess) return GTAP_E_HIP;
+  const int rc = launch_sched(c);
+  if (rc) return rc;
+  if (hipEventRecord(c->ev1, c->stream) != hipSuccess) return GTAP_E_HIP;
+  c->serving = true;
+  c->have_done = false;
+  return GTAP_OK;
+}
+
+int gtap_serve_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, uint64_t *ticket) {
+  if (!c || !ticket) return GTAP_E_INVAL;
+  if (!c->serving) return GTAP_E_STATE;
+  JobSlot J;
+  const int rc = pack_job(c, kind, args, args_bytes, J);
+  if (rc) return rc;
+  const uint64_t t = c->next_ticket;
+  const uint64_t R = c->params.ring_cap;
+  const uint64_t slot = t % R;
+  // the slot's previous job (ticket t - R) must have completed
+  if (t >= R && __atomic_load_n(&c->done_host[slot].done, __ATOMIC_ACQUIRE) != t - R + 1) return GTAP_E_FULL;
+  std::memcpy(&c->ring[slot], &J, sizeof(J));
+  __atomic_store_n(&c->ring_seq[slot], t + 1, __ATOMIC_RELEASE);
+  c->next_ticket = t + 1;
+  *ticket = t;
+  return GTAP_OK;
+}
+
+int gtap_serve_poll(gtap_ctx *c, uint64_t ticket, int64_t *result, uint64_t *done_ticks) {
+  if (!c || !c->done_host) return GTAP_E_INVAL;
+  if (ticket >= c->next_ticket) return GTAP_E_NOJOB;
+  const HostCompletion &h = c->done_host[ticket % c->params.ring_cap];
+  if (__atomic_load_n(&h.done, __ATOMIC_ACQUIRE) != ticket + 1) return GTAP_E_PENDING;
+  if (result) *result = __atomic_load_n(&h.result, __ATOMIC_RELAXED);
+  if (done_ticks) *done_ticks = __atomic_load_n(&h.t_done, __ATOMIC_RELAXED);
+  return GTAP_OK;
+}
+
+// True once the serving kernel has exited (it only exits early on an abort).
+static bool serving_kernel_ended(gtap_ctx *c) { return hipStreamQuery(c->stream) == hipSuccess; }
+
+int gtap_serve_stop(gtap_ctx *c, uint32_t wait_ms) {
+  if (!c) return GTAP_E_INVAL;
+  if (!c->serving) return GTAP_E_STATE;
+  int rc = GTAP_OK;
+  const double deadline = host_seconds() + wait_ms / 1000.0;
+  double next_query = host_seconds() + 1e-3;
+  const uint64_t R = c->params.ring_cap;
+  bool ended = false;
+  for (uint64_t t = (c->next_ticket > R ? c->next_ticket - R : 0); t < c->next_ticket && !ended; ++t) {
+    while (__atomic_load_n(&c->done_host[t % R].done, __ATOMIC_ACQUIRE) != t + 1) {
+      const double now = host_seconds();
+      if (now > deadline) {
+        rc = GTAP_E_TIMEOUT;
+        break;
+      }
+      if (now > next_query) {
+        next_query = now + 1e-3;
+        if (serving_kernel_ended(c)) {
+          ended = true;  // aborted: the device's error code is returned below
+          break;
+        }
+      }
+      std::this_thread::yield();
+    }
+    if (rc) break;
+  }
+  __atomic_store_n(c->stop_host, 1, __ATOMIC_RELEASE);
+  Control ctl;
+  if (hipMemcpyAsync(&ctl, c->params.ctl, sizeof(Control), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    c->serving = false;
+    return GTAP_E_HIP;
+  }
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+  c->serving = false;
+  c->params.serving = 0;
+  const int rr = record_run(c, ctl, ms);
+  return rr != GTAP_OK ? rr : rc;
+}
+
+int gtap_trace_run(gtap_ctx *c, const gtap_trace_job *jobs, size_t n, gtap_trace_result *out, uint32_t timeout_ms) {
+  if (!c || (n && (!jobs || !out))) return GTAP_E_INVAL;
+  if (!c->serving) return GTAP_E_STATE;
+  std::vector<uint64_t> ticket(n, 0);
+  std::vector<size_t> open;
+  open.reserve(n);
+  const double t0 = host_seconds();
+  const double deadline = t0 + timeout_ms / 1000.0;
+  size_t next = 0, done = 0;
+  double next_query = 1e-3;
+  for (size_t i = 0; i < n; ++i) out[i] = gtap_trace_result{0, -1.0, -1.0, GTAP_E_PENDING, 0};
+  while (done < n) {
+    double now = host_seconds() - t0;
+    if (now > next_query) {
+      next_query = now + 1e-3;
+      // the kernel exited early: it aborted; end the session and report why
+      if (serving_kernel_ended(c)) {
+        const int rc = gtap_serve_stop(c, 0);
+        return rc != GTAP_OK ? rc : GTAP_E_STATE;
+      }
+    }
+    while (next < n && jobs[next].arrival_s <= now) {
+      const gtap_trace_job &J = jobs[next];
+      if (J.args_bytes > sizeof(J.args)) return GTAP_E_INVAL;
+      const int rc = gtap_serve_submit(c, J.kind, J.args, J.args_bytes, &ticket[next]);
+      if (rc == GTAP_E_FULL) break;  // retry once a slot frees up
+      if (rc != GTAP_OK) {
+        out[next].status = rc;
+        return rc;
+      }
+      out[next].submit_s = now;
+      open.push_back(next);
+      ++next;
+    }
+    size_t w = 0;
+    for (size_t k = 0; k < open.size(); ++k) {
+      const size_t i = open[k];
+      int64_t r = 0;
+      if (gtap_serve_poll(c, ticket[i], &r, nullptr) == GTAP_OK) {
+        out[i].result = r;
+        out[i].done_s = host_seconds() - t0;
+        out[i].status = GTAP_OK;
+        ++done;
+      } else {
+        open[w++] = i;
+      }
+    }
+    open.resize(w);
+    if (host_seconds() > deadline) return GTAP_E_TIMEOUT;
+    if (open.empty() && next < n) {
+      // nothing in flight: sleep until shortly before the next arrival
+      const double gap = jobs[next].arrival_s - (host_seconds() - t0);
+      if (gap > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(gap - 1e-4));
+    }
+  }
+  return GTAP_OK;
+}
+
+int gtap_trace_run_plain(gtap_ctx *c, const gtap_trace_job *jobs, size_t n, gtap_trace_result *out) {
+  if (!c || (n && (!jobs || !out))) return GTAP_E_INVAL;
+  if (c->serving || !c->pending.empty()) return GTAP_E_STATE;
+  const double t0 = host_seconds();
+  for (size_t i = 0; i < n; ++i) {
+    const gtap_trace_job &J = jobs[i];
+    while (host_seconds() - t0 < J.arrival_s) {
+    }
+    out[i].submit_s = host_seconds() - t0;
+    uint64_t id = 0;
+    int rc = gtap_submit(c, J.kind, J.args, J.args_bytes, &id);
+    if (rc == GTAP_OK) rc = gtap_run(c);
+    int64_t r = 0;
+    if (rc == GTAP_OK) rc = gtap_result(c, id, &r, sizeof(r));
+    out[i].result = r;
+    out[i].done_s = host_seconds() - t0;
+    out[i].status = rc;
+    if (rc != GTAP_OK) return rc;
+  }
   return GTAP_OK;
 }
 
@@ -424,11 +660,18 @@ int gtap_result(gtap_ctx *c, uint64_t job_id, void *out, size_t out_bytes) {
 
 int gtap_finalize(gtap_ctx *c) {
   if (!c) return GTAP_E_INVAL;
+  // a serving kernel still running stops once its admitted jobs drain (or
+  // its watchdog fires); the pinned buffers it reads are freed only after
+  if (c->serving && c->stop_host) __atomic_store_n(c->stop_host, 1, __ATOMIC_RELEASE);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->owns_ws && c->ws) (void)hipFree(c->ws);
+  if (c->ring) (void)hipHostFree(c->ring);
+  if (c->ring_seq) (void)hipHostFree(c->ring_seq);
+  if (c->done_host) (void)hipHostFree(c->done_host);
+  if (c->stop_host) (void)hipHostFree(c->stop_host);
   delete c;
   return GTAP_OK;
 }

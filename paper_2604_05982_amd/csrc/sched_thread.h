@@ -79,6 +79,7 @@ struct PoolView {
   uint32_t *stk;        // LDS free stack
   int32_t sz;           // stack size (wave-uniform register)
   uint32_t skip;        // allocations left before the depot is probed again
+  int32_t net;          // frames handed out minus frames returned (serving accounting)
   uint32_t stk_cap;
   uint32_t chunk;
   DepotBin *bins;
@@ -91,11 +92,11 @@ struct PoolView {
 };
 
 GTAP_DEV PoolView small_pool(const Params &p, WaveLds &L) {
-  return PoolView{L.stk_s, 0, 0, kStackSmall, kChunkSmall, p.bins_s, p.store_s,
+  return PoolView{L.stk_s, 0, 0, 0, kStackSmall, kChunkSmall, p.bins_s, p.store_s,
                   p.bincap_s, &p.ctl->bump_small, p.nframes_s, 0u, 0};
 }
 GTAP_DEV PoolView big_pool(const Params &p, WaveLds &L) {
-  return PoolView{L.stk_b, 0, 0, kStackBig, kChunkBig, p.bins_b, p.store_b,
+  return PoolView{L.stk_b, 0, 0, 0, kStackBig, kChunkBig, p.bins_b, p.store_b,
                   p.bincap_b, &p.ctl->bump_big, p.nframes_b, kBigBit, 1};
 }
 
@@ -209,6 +210,7 @@ struct AllocResult {
 // earlier calls' IDs were taken from.
 GTAP_DEV bool alloc_frames(const Params &p, PoolView &P, uint32_t me, uint32_t F,
                            AllocResult &r, WaveCounters &wc) {
+  P.net += static_cast<int32_t>(F);
   if (static_cast<uint32_t>(P.sz) < F) {
     // Short: recycled frames from nearby depot bins first, unless the last
     // probe found none.
@@ -270,6 +272,7 @@ GTAP_DEV void free_frames(PoolView &P, uint32_t me, bool mine, uint32_t id, Wave
   const uint64_t m = ballot(mine);
   const uint32_t n = __popcll(m);
   if (n == 0) return;
+  P.net -= static_cast<int32_t>(n);
   if (P.sz + static_cast<int32_t>(n) > static_cast<int32_t>(P.stk_cap)) {
     if (!depot_spill(P, me, wc)) return;  // no bin took a chunk: these frames are not reused
   }
@@ -479,40 +482,97 @@ GTAP_DEV uint32_t owner_of(const uint32_t *offs, uint32_t g) {
   return lo;
 }
 
-// Root frame of job j (payload from the job's arguments).
+// Root frame of job slot j (payload from the job's arguments).
 GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
-  const JobSlot &J = p.jobs[j];
+  const uint32_t jkind = static_cast<uint32_t>(co_ld64(reinterpret_cast<const uint64_t *>(p.jobs + j)));
   ChildInit c;
   for (uint32_t i = 0; i < kPayloadWords; ++i) c.p[i] = 0;
   uint32_t kind = TK_FIB;
-  switch (J.kind) {
+  switch (jkind) {
     case 1:  // fib
       kind = TK_FIB;
-      c.p[0] = static_cast<uint32_t>(J.a[0]);
+      c.p[0] = static_cast<uint32_t>(job_arg(p, j, 0));
       break;
     case 2:  // n-queens: empty board of size n
       kind = TK_NQ;
-      c.p[4] = static_cast<uint32_t>(J.a[0]);
+      c.p[4] = static_cast<uint32_t>(job_arg(p, j, 0));
       break;
     case 3: {  // uts: root id = mix64(seed), depth 0
       kind = TK_UTS;
-      const uint64_t rid = mix64(J.a[0]);
+      const uint64_t rid = mix64(job_arg(p, j, 0));
+      const uint64_t thr = job_arg(p, j, 1);
       c.p[0] = static_cast<uint32_t>(rid);
       c.p[1] = static_cast<uint32_t>(rid >> 32);
-      c.p[2] = static_cast<uint32_t>(J.a[2]) << 16;
-      c.p[3] = static_cast<uint32_t>(J.a[1]);
-      c.p[4] = static_cast<uint32_t>(J.a[1] >> 32);
+      c.p[2] = static_cast<uint32_t>(job_arg(p, j, 2)) << 16;
+      c.p[3] = static_cast<uint32_t>(thr);
+      c.p[4] = static_cast<uint32_t>(thr >> 32);
       break;
     }
     case 4:  // k-clique: the whole vertex range
       kind = TK_KC_RANGE;
       c.p[0] = 0;
-      c.p[1] = static_cast<uint32_t>(J.a[2]);
+      c.p[1] = static_cast<uint32_t>(job_arg(p, j, 2));
       break;
     default:
       break;
   }
   write_frame(frame_ptr(p, id), kNone, j, state_word(kind, 0, 0), c);
+}
+
+// Serving: admit up to 64 jobs the host appended to the admission ring, if the
+// in-flight limit and the frame-pool headroom allow.  Admitted roots get
+// frames and are pushed to this wave's queue 0.  Returns the number admitted.
+GTAP_DEV uint32_t admit_jobs(const Params &p, WaveLds &L, uint32_t me, PoolView &PS, WaveCounters &wc) {
+  const uint32_t ln = lane_id();
+  uint64_t t = 0;
+  int32_t inflight = 0;
+  int64_t live = 0, live_b = 0;
+  if (ln == 0) {
+    t = ld_relaxed(&p.ctl->admitted);
+    inflight = ld_relaxed(&p.ctl->jobs_remaining);
+    live = ld_relaxed(&p.ctl->live_small);
+    live_b = ld_relaxed(&p.ctl->live_big);
+  }
+  t = uniform64(t);
+  inflight = uniform(inflight);
+  const uint64_t tk = t + ln;
+  const bool ready = sys_ld64(p.ring_seq + (tk % p.ring_cap)) == tk + 1;
+  const uint64_t m = ballot(ready);
+  uint32_t n = (~m == 0ull) ? kWave : static_cast<uint32_t>(__builtin_ctzll(~m));
+  const int32_t allowed = static_cast<int32_t>(p.max_inflight) - inflight;
+  if (allowed <= 0) return 0;
+  if (n > static_cast<uint32_t>(allowed)) n = static_cast<uint32_t>(allowed);
+  // admit by free frame-pool memory: keep the headroom free after admitting
+  const int64_t ls = static_cast<int64_t>(uniform64(static_cast<uint64_t>(live)));
+  const int64_t lb = static_cast<int64_t>(uniform64(static_cast<uint64_t>(live_b)));
+  const bool room = ls + static_cast<int64_t>(p.admit_headroom_small) <= static_cast<int64_t>(p.nframes_s) &&
+                    (p.nframes_b == 0 || lb + static_cast<int64_t>(p.admit_headroom_big) <= static_cast<int64_t>(p.nframes_b));
+  if (n == 0 || !room) return 0;
+  uint32_t won = 0;
+  if (ln == 0) {
+    uint64_t exp = t;
+    won = cas_relaxed(&p.ctl->admitted, &exp, t + n) ? 1u : 0u;
+  }
+  if (!uniform(won)) return 0;
+  // copy the job records into the device job table (slot = ticket mod ring_cap)
+  for (uint32_t i = ln; i < n; i += kWave) {
+    const uint32_t slot = static_cast<uint32_t>((t + i) % p.ring_cap);
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(p.ring + slot);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(p.jobs + slot);
+    for (int w = 0; w < 16; ++w) co_st64(dst + w, sys_ld64(src + w));
+    co_st64(&p.jobs[slot].ticket, t + i);
+  }
+  if (ln == 0) fetch_add_relaxed(&p.ctl->jobs_remaining, static_cast<int32_t>(n));
+  AllocResult ar;
+  if (!alloc_frames(p, PS, me, n, ar, wc)) return 0;
+  wave_sync();
+  drain();
+  for (uint32_t i = ln; i < n; i += kWave)
+    write_root(p, alloc_id(PS, ar, i), static_cast<uint32_t>((t + i) % p.ring_cap));
+  drain();
+  push_batch(p, L, me, 0, n, [&](uint32_t i) { return alloc_id(PS, ar, i); }, wc);
+  wc.add(ST_ADMITTED, n);
+  return n;
 }
 
 template <int WPB>
@@ -568,6 +628,8 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   bool tcont = false;  // this lane's task is a resumed parent (runs its continuation)
   uint64_t t_loop = clock64();
   for (;;) {
+    // ---- serving: a few waves admit newly submitted jobs ----
+    if (p.serving && me < kAdmitWaves && (cnt == 0 || (iter & 15u) == 0)) admit_jobs(p, L, me, PS, wc);
     // ---- acquire work ----
     // Parents resumed in the last iteration are normally staged with this
     // iteration's children; with no lanes busy they run right away.
@@ -605,13 +667,22 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       // end makes a root the last task of its job), an error, or the watchdog
       uint32_t stop = 0;
       if ((idle & 3u) == 1u && ln == 0) {
-        if (ld_relaxed(&p.ctl->jobs_remaining) <= 0 || ld_relaxed(&p.ctl->error) != 0) stop = 1;
+        // batch: every root completed; serving: stop requested and nothing in flight
+        const bool drained_jobs = ld_relaxed(&p.ctl->jobs_remaining) <= 0 &&
+                                  (!p.serving || ((idle & 15u) == 1u && sys_ld32i(p.stop_host) != 0));
+        if (drained_jobs || ld_relaxed(&p.ctl->error) != 0) stop = 1;
         else if (wall_ticks() > deadline) {
           raise_error(p, -8 /*GTAP_E_TIMEOUT*/, 3, p.timeout_ticks, 0, me, -1);
           stop = 1;
         }
       }
       if (uniform(stop)) break;
+      if (p.serving && ln == 0) {
+        if (PS.net) fetch_add_relaxed(&p.ctl->live_small, static_cast<int64_t>(PS.net));
+        if (PB.net) fetch_add_relaxed(&p.ctl->live_big, static_cast<int64_t>(PB.net));
+      }
+      PS.net = 0;
+      PB.net = 0;
       backoff_sleep(idle);
       const uint64_t now = clock64();
       idle_cycles += now - t_loop;
@@ -669,9 +740,15 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     const bool root_done = done && o.parent == kNone;
     if (root_done) {
       JobSlot &J = p.jobs[o.job];
+      const uint64_t now = wall_ticks();
       st_relaxed(&J.result, o.value);
-      st_relaxed(&J.t_done, wall_ticks());
+      st_relaxed(&J.t_done, now);
       st_relaxed(&J.done, 1u);
+      if (p.serving) {
+        HostCompletion *h = p.done_host + o.job;
+        sys_st64(reinterpret_cast<uint64_t *>(&h->result), static_cast<uint64_t>(o.value));
+        sys_st64(&h->t_done, now);
+      }
     }
     const uint32_t par = to_parent ? o.parent : kNone;
     const uint32_t prev_par = wave_from_below(par, kNone);
@@ -698,9 +775,10 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
                             static_cast<int64_t>(run_len);
       join_old = fetch_add_relaxed(join_ptr(frame_ptr(p, o.parent)), delta);
     }
-    if (root_done) {
-      drain();  // the job's result is in place before the run can end
-      fetch_add_relaxed(&p.ctl->jobs_remaining, -1);
+    if (ballot(root_done)) {
+      drain();  // the job's result is in place before the run can end or the host sees it
+      if (root_done && p.serving) sys_st64(&p.done_host[o.job].done, co_ld64(&p.jobs[o.job].ticket) + 1);
+      if (root_done) fetch_add_relaxed(&p.ctl->jobs_remaining, -1);
     }
     // completed tasks that had frames release them
     free_frames(PS, me, done && tid != kNone && !(tid & kBigBit), tid, wc);
@@ -868,6 +946,12 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     if (resumed) L.res[rank_below(m_res)] = o.parent;
     npend = __popcll(m_res);
     wave_sync();
+    if (p.serving && ln == 0) {
+      if (PS.net) fetch_add_relaxed(&p.ctl->live_small, static_cast<int64_t>(PS.net));
+      if (PB.net) fetch_add_relaxed(&p.ctl->live_big, static_cast<int64_t>(PB.net));
+    }
+    PS.net = 0;
+    PB.net = 0;
     const uint64_t now = clock64();
     busy_cycles += now - t_loop;
     t_loop = now;

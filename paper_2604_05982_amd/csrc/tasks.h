@@ -115,7 +115,9 @@ GTAP_DEV uint32_t intersect_sorted(const int32_t *C, uint32_t nc, const int32_t 
   return o;
 }
 
-GTAP_DEV const uint64_t *job_args(const Params &p, uint32_t job) { return p.jobs[job].a; }
+// Job arguments.  Read coherently: while serving, a job slot is rewritten by
+// the wave that admits the next job using it.
+GTAP_DEV uint64_t job_arg(const Params &p, uint32_t job, uint32_t i) { return co_ld64(&p.jobs[job].a[i]); }
 
 // Words 0..7 of a task: its frame's first half, or the LDS descriptor of a
 // task that has no frame (a child retained by the wavefront that spawned it).
@@ -219,9 +221,8 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
     case TK_KC_RANGE: {
       // Vertex range [lo,hi): halve while larger than range_leaf, else one
       // vertex task per vertex.
-      const uint64_t *a = job_args(p, o.job);
       const uint32_t lo = p0, hi = p1;
-      const uint32_t leaf = static_cast<uint32_t>(a[4]);
+      const uint32_t leaf = static_cast<uint32_t>(job_arg(p, o.job, 4));
       if (hi <= lo) return;
       o.type = OUT_FORK;
       o.d[0] = lo; o.d[1] = hi;
@@ -237,10 +238,9 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
     case TK_KC_VERTEX: {
       // K(N+(v), k-1): k = 1 counts the vertex, k = 2 its out-degree, else one
       // candidate task per out-neighbour with C = N+(v).
-      const uint64_t *a = job_args(p, o.job);
-      const int32_t *rp = reinterpret_cast<const int32_t *>(a[0]);
-      const int32_t *col = reinterpret_cast<const int32_t *>(a[1]);
-      const uint32_t k = static_cast<uint32_t>(a[3]);
+      const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 0));
+      const int32_t *col = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 1));
+      const uint32_t k = static_cast<uint32_t>(job_arg(p, o.job, 3));
       const uint32_t v = p0;
       if (k == 1) {
         o.value = 1;
@@ -265,9 +265,8 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
     case TK_KC_CAND: {
       // K(C /\ N+(u), l): l = 1 counts the intersection, else stores it in this
       // frame's buffer and forks one child per element.
-      const uint64_t *a = job_args(p, o.job);
-      const int32_t *rp = reinterpret_cast<const int32_t *>(a[0]);
-      const int32_t *col = reinterpret_cast<const int32_t *>(a[1]);
+      const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 0));
+      const int32_t *col = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 1));
       const uint32_t u = p0, l = p1;
       const int32_t *C = reinterpret_cast<const int32_t *>(pack(p2, p3));
       const uint32_t nC = p4;
@@ -317,8 +316,7 @@ GTAP_DEV uint32_t child_class(const Params &p, uint32_t job, uint32_t ckind, con
     }
     case 2: {  // k-clique candidate-set bound
       if (ckind != TK_KC_CAND) return 0;
-      const uint64_t *a = job_args(p, job);
-      const int32_t *rp = reinterpret_cast<const int32_t *>(a[0]);
+      const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, job, 0));
       const uint32_t u = c.p[0], nC = c.p[4];
       const uint32_t deg = static_cast<uint32_t>(rp[u + 1] - rp[u]);
       return bucket_of(p, deg < nC ? deg : nC);

@@ -154,6 +154,17 @@ GTAP_DEV uint64_t co_ld64(const uint64_t *p) {
   return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ---- system-scope accesses (pinned host memory shared with the host) ------
+GTAP_DEV uint64_t sys_ld64(const uint64_t *p) {
+  return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+GTAP_DEV int32_t sys_ld32i(const int32_t *p) {
+  return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+GTAP_DEV void sys_st64(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Wait until every memory operation this wavefront has issued is complete
 // (stores and RMWs performed at their coherence point, loads returned).  The
 // wavefront-scope fences keep the compiler from moving memory accesses across

@@ -92,7 +92,7 @@ class gtap_stats(ctypes.Structure):
         "tasks", "conts", "spawns", "pushed", "push_batches", "popped", "pop_batches",
         "stolen", "steal_batches", "steal_attempts", "iterations", "idle_iterations",
         "small_frames_touched", "big_frames_touched", "depot_spills", "depot_refills",
-        "busy_cycles", "idle_cycles")] + [
+        "busy_cycles", "idle_cycles", "admitted")] + [
         ("kernel_ms", ctypes.c_double),
         ("num_waves", ctypes.c_int32),
         ("waves_per_group", ctypes.c_int32),
@@ -102,6 +102,16 @@ class gtap_stats(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class gtap_trace_job(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("args_bytes", ctypes.c_uint32),
+                ("arrival_s", ctypes.c_double), ("args", ctypes.c_uint64 * 4)]
+
+
+class gtap_trace_result(ctypes.Structure):
+    _fields_ = [("result", ctypes.c_int64), ("submit_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class gtap_error_report(ctypes.Structure):
@@ -134,8 +144,17 @@ def _load() -> ctypes.CDLL:
     lib.gtap_last_error.argtypes = [vp, P(gtap_error_report)]
     lib.gtap_status_string.argtypes = [ctypes.c_int32]
     lib.gtap_status_string.restype = ctypes.c_char_p
+    u32, u64 = ctypes.c_uint32, ctypes.c_uint64
+    lib.gtap_serve_start.argtypes = [vp, u32, u32, u32]
+    lib.gtap_serve_submit.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_size_t, P(u64)]
+    lib.gtap_serve_poll.argtypes = [vp, u64, P(ctypes.c_int64), P(u64)]
+    lib.gtap_serve_stop.argtypes = [vp, u32]
+    lib.gtap_trace_run.argtypes = [vp, P(gtap_trace_job), ctypes.c_size_t, P(gtap_trace_result), u32]
+    lib.gtap_trace_run_plain.argtypes = [vp, P(gtap_trace_job), ctypes.c_size_t, P(gtap_trace_result)]
     for fn in ("gtap_workspace_size", "gtap_init", "gtap_submit", "gtap_run", "gtap_result",
-               "gtap_finalize", "gtap_stats_get", "gtap_last_error"):
+               "gtap_finalize", "gtap_stats_get", "gtap_last_error", "gtap_serve_start",
+               "gtap_serve_submit", "gtap_serve_poll", "gtap_serve_stop", "gtap_trace_run",
+               "gtap_trace_run_plain"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -145,7 +164,8 @@ _lib = _load()
 # Names every test checks the library exports (the declarations of gtap.h).
 EXPORTED = ("gtap_config_default", "gtap_workspace_size", "gtap_init", "gtap_submit", "gtap_run",
             "gtap_result", "gtap_finalize", "gtap_stats_get", "gtap_last_error",
-            "gtap_status_string")
+            "gtap_status_string", "gtap_serve_start", "gtap_serve_submit", "gtap_serve_poll",
+            "gtap_serve_stop", "gtap_trace_run", "gtap_trace_run_plain")
 
 
 class GtapError(RuntimeError):
@@ -226,6 +246,49 @@ def gtap_finalize(ctx) -> None:
         raise GtapError(rc, "gtap_finalize")
 
 
+def gtap_serve_start(ctx, max_inflight: int, headroom_small: int, headroom_big: int) -> None:
+    rc = _lib.gtap_serve_start(ctx, int(max_inflight), int(headroom_small), int(headroom_big))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_serve_start")
+
+
+def gtap_serve_submit(ctx, kind: int, args: ctypes.Structure) -> int:
+    t = ctypes.c_uint64(0)
+    rc = _lib.gtap_serve_submit(ctx, int(kind), ctypes.byref(args), ctypes.sizeof(args), ctypes.byref(t))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_serve_submit")
+    return int(t.value)
+
+
+def gtap_serve_poll(ctx, ticket: int):
+    """(result, done_ticks) once the job completed, else None."""
+    r, d = ctypes.c_int64(0), ctypes.c_uint64(0)
+    rc = _lib.gtap_serve_poll(ctx, int(ticket), ctypes.byref(r), ctypes.byref(d))
+    if rc == GTAP_E_PENDING:
+        return None
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_serve_poll")
+    return int(r.value), int(d.value)
+
+
+def gtap_serve_stop(ctx, wait_ms: int = 60000) -> None:
+    rc = _lib.gtap_serve_stop(ctx, int(wait_ms))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_serve_stop", gtap_last_error(ctx))
+
+
+def gtap_trace_run(ctx, jobs, results, timeout_ms: int) -> None:
+    rc = _lib.gtap_trace_run(ctx, jobs, len(jobs), results, int(timeout_ms))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_trace_run", gtap_last_error(ctx))
+
+
+def gtap_trace_run_plain(ctx, jobs, results) -> None:
+    rc = _lib.gtap_trace_run_plain(ctx, jobs, len(jobs), results)
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_trace_run_plain", gtap_last_error(ctx))
+
+
 def uts_threshold(m: float) -> int:
     """floor(2^64 * m / (m+1)): continue-threshold of a geometric law with mean m."""
     from fractions import Fraction
@@ -287,6 +350,61 @@ class Runtime:
         return gtap_submit(self.ctx, GTAP_KIND_KCLIQUE,
                            gtap_kclique_args(rp.data_ptr(), cl.data_ptr(), n, int(k),
                                              int(range_leaf), int(max_outdeg)))
+
+    # -- argument structs (for traces and serving) ----------------------------
+    @staticmethod
+    def fib_args(n):
+        return GTAP_KIND_FIB, gtap_fib_args(int(n), 0)
+
+    @staticmethod
+    def nqueens_args(n):
+        return GTAP_KIND_NQUEENS, gtap_nqueens_args(int(n), 0)
+
+    @staticmethod
+    def uts_args(seed, threshold, max_depth):
+        return GTAP_KIND_UTS, gtap_uts_args(int(seed) & (2**64 - 1), int(threshold), int(max_depth), 0)
+
+    def kclique_args(self, row_ptr, col, k, range_leaf=64, max_outdeg=None):
+        """row_ptr/col must be int32 CUDA tensors kept alive by the caller."""
+        n = row_ptr.numel() - 1
+        if max_outdeg is None:
+            max_outdeg = int((row_ptr[1:] - row_ptr[:-1]).max().item()) if n > 0 else 0
+        return GTAP_KIND_KCLIQUE, gtap_kclique_args(row_ptr.data_ptr(), col.data_ptr(), n, int(k),
+                                                    int(range_leaf), int(max_outdeg))
+
+    @staticmethod
+    def trace(entries):
+        """entries: [(arrival_s, (kind, args_struct)), ...] -> ctypes array of gtap_trace_job."""
+        arr = (gtap_trace_job * len(entries))()
+        for i, (t, (kind, a)) in enumerate(entries):
+            arr[i].kind = kind
+            arr[i].args_bytes = ctypes.sizeof(a)
+            arr[i].arrival_s = float(t)
+            ctypes.memmove(ctypes.addressof(arr[i].args), ctypes.addressof(a), ctypes.sizeof(a))
+        return arr
+
+    # -- serving --------------------------------------------------------------
+    def serve_start(self, max_inflight=1024, headroom_small=1 << 16, headroom_big=0):
+        gtap_serve_start(self.ctx, max_inflight, headroom_small, headroom_big)
+
+    def serve_submit(self, kind, args) -> int:
+        return gtap_serve_submit(self.ctx, kind, args)
+
+    def serve_poll(self, ticket):
+        return gtap_serve_poll(self.ctx, ticket)
+
+    def serve_stop(self, wait_ms=60000):
+        gtap_serve_stop(self.ctx, wait_ms)
+
+    def trace_run(self, jobs, timeout_ms=120000):
+        res = (gtap_trace_result * len(jobs))()
+        gtap_trace_run(self.ctx, jobs, res, timeout_ms)
+        return res
+
+    def trace_run_plain(self, jobs):
+        res = (gtap_trace_result * len(jobs))()
+        gtap_trace_run_plain(self.ctx, jobs, res)
+        return res
 
     # -- execution ------------------------------------------------------------
     def run(self) -> None:

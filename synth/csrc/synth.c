@@ -263,3 +263,56 @@ int64_t syn_orient(int64_t n, const int64_t *rp, const int32_t *col, const int64
     }
     return maxd;
 }
+
+/*
+ * Induced subgraph of an oriented graph on s of its n vertices, drawn
+ * uniformly without replacement with Floyd's algorithm (Bentley & Floyd,
+ * CACM 1987) from the splitmix64 stream `seed`.  The chosen vertices are
+ * renumbered 0..s-1 in increasing order; since the input orientation points
+ * from lower to higher ids, the renumbering keeps it acyclic and every
+ * out-list sorted.  Work buffers: mark (n/64 + 1 words, zero on entry and on
+ * return) and map (n entries).  Output: orp[s+1], ocol[cap].  Returns the
+ * number of edges, or -1 if they exceed cap.
+ */
+int64_t syn_induced(int64_t n, const int64_t *rp, const int32_t *col, int64_t s, uint64_t seed,
+                    uint64_t *mark, int32_t *map, int64_t *orp, int32_t *ocol, int64_t cap)
+{
+    if (s > n) s = n;
+    uint64_t e = 0;
+    for (int64_t j = n - s; j < n; j++) {
+        uint64_t t = mulhi64(syn_draw(seed, e++), (uint64_t)j + 1);
+        if (mark[t >> 6] & (1ull << (t & 63))) t = (uint64_t)j;
+        mark[t >> 6] |= 1ull << (t & 63);
+    }
+    int64_t k = 0;
+    for (int64_t w = 0; w <= (n - 1) / 64 && n > 0; w++) {
+        uint64_t b = mark[w];
+        while (b) {
+            int64_t v = w * 64 + __builtin_ctzll(b);
+            map[v] = (int32_t)k++;
+            b &= b - 1;
+        }
+    }
+    int64_t m = 0, u_sub = 0;
+    orp[0] = 0;
+    for (int64_t w = 0; w <= (n - 1) / 64 && n > 0; w++) {
+        uint64_t b = mark[w];
+        while (b) {
+            int64_t u = w * 64 + __builtin_ctzll(b);
+            b &= b - 1;
+            for (int64_t i = rp[u]; i < rp[u + 1]; i++) {
+                int32_t v = col[i];
+                if (mark[v >> 6] & (1ull << (v & 63))) {
+                    if (m >= cap) {
+                        memset(mark, 0, sizeof(uint64_t) * (size_t)(n / 64 + 1));
+                        return -1;
+                    }
+                    ocol[m++] = map[v];
+                }
+            }
+            orp[++u_sub] = m;
+        }
+    }
+    memset(mark, 0, sizeof(uint64_t) * (size_t)(n / 64 + 1));
+    return m;
+}

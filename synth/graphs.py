@@ -40,6 +40,8 @@ def _load():
     lib.syn_orient.restype = i64
     lib.syn_draw.argtypes = [u64, u64]
     lib.syn_draw.restype = u64
+    lib.syn_induced.argtypes = [i64, vp, vp, i64, u64, vp, vp, vp, vp, i64]
+    lib.syn_induced.restype = i64
     _lib = lib
     return lib
 
@@ -151,3 +153,45 @@ def chung_lu(n: int, mean_degree: float, gamma: float, cap_frac: float, seed: in
             "seed": seed, "scale_c": scale.value, "m_drawn": m_draw,
             "mean_degree_realised": 2.0 * m / n}
     return OrientedGraph(n, orp, ocol, int(m), maxdeg, degen, maxd, info)
+
+
+class _InducedWork:
+    """Per-thread work buffers for induced(): a vertex bitmap and an id map."""
+
+    def __init__(self, g: OrientedGraph):
+        self.mark = np.zeros(g.n // 64 + 1, dtype=np.uint64)
+        self.map = np.zeros(max(g.n, 1), dtype=np.int32)
+        self.col = np.zeros(max(int(g.row_ptr[-1]), 1), dtype=np.int32)
+
+
+def induced(g: OrientedGraph, s: int, seed: int, work: "_InducedWork | None" = None) -> OrientedGraph:
+    """Subgraph induced by s vertices of g drawn uniformly without replacement
+    (seeded), renumbered in increasing order: the orientation of g restricted
+    to them, still acyclic with sorted out-lists."""
+    lib = _load()
+    s = int(min(max(s, 0), g.n))
+    w = work if work is not None else _InducedWork(g)
+    rp = np.zeros(s + 1, dtype=np.int64)
+    m = lib.syn_induced(g.n, g.row_ptr.ctypes.data, g.col.ctypes.data, s, seed & (2**64 - 1),
+                        w.mark.ctypes.data, w.map.ctypes.data, rp.ctypes.data, w.col.ctypes.data,
+                        w.col.size)
+    if m < 0:
+        raise RuntimeError("induced: edge buffer too small")
+    col = w.col[:m].copy()
+    maxd = int(np.max(np.diff(rp))) if s > 0 else 0
+    return OrientedGraph(s, rp, col, int(m), -1, -1, maxd, {"parent_n": g.n, "seed": seed})
+
+
+def induced_many(g: OrientedGraph, specs, threads: int = 8) -> list:
+    """induced() for each (s, seed) in specs on a pool of threads."""
+    import concurrent.futures as cf
+    import threading
+    local = threading.local()
+
+    def one(spec):
+        if not hasattr(local, "w"):
+            local.w = _InducedWork(g)
+        return induced(g, spec[0], spec[1], local.w)
+
+    with cf.ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        return list(ex.map(one, specs))

@@ -264,3 +264,41 @@ def test_daq_configs(gtap, opts):
         r.run()
         for jid, want in jobs:
             assert r.result(jid) == want
+
+
+# ---- full-size k-clique: n = 10^6, mean degree 40, exponent 2.1 (cap 0.6, seed 2) ----
+def _golden_kclique():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "kclique_chung_lu.txt")
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, csum, k, count, tasks, conts = line.split()
+            out[(name, int(k))] = (csum, int(count), int(tasks), int(conts))
+    return out
+
+
+@pytest.fixture(scope="module")
+def big_graph():
+    return graphs.chung_lu(1000000, 40, 2.1, 0.6, 2)
+
+
+@pytest.mark.parametrize("queues", [1, 4])
+def test_kclique_1m_k7(gtap, big_graph, queues):
+    gold = _golden_kclique()
+    g = big_graph
+    name = "n1000000_d40_g2.1_cap0.6_s2"
+    opts = dict(num_waves=1024, deque_capacity=1 << 17, small_frames=1 << 25, big_frames=1 << 23,
+                big_frame_ints=max(320, g.max_outdeg), timeout_ms=60000)
+    if queues > 1:
+        opts.update(num_queues=4, daq_policy=2, daq_bounds=[8, 32, 128])
+    with make_rt(gtap, **opts) as r:
+        for k in (5, 7):
+            csum, count, tasks, conts = gold[(name, k)]
+            assert g.checksum() == csum
+            say(f"kclique n=1e6 k={k} queues={queues}")
+            got, st = run_single(r, r.submit_kclique, g.row_ptr32, g.col, k)
+            assert got == count
+            assert st["tasks"] == tasks and st["conts"] == conts

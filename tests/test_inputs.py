@@ -1,4 +1,5 @@
 """Seeded synthetic inputs: shape checks of the generated graphs."""
+import pytest
 import numpy as np
 
 from synth import graphs
@@ -41,3 +42,39 @@ def test_orientation_by_order():
     g = graphs.oriented_from_edges(5, edges, "degeneracy")
     _check_oriented(g)
     assert g.col.size == 5 and g.degeneracy == 2
+
+
+def _floyd_subset(n, s, seed):
+    """Floyd's sampling without replacement, from the same draw stream."""
+    chosen = set()
+    e = 0
+    for j in range(n - s, n):
+        t = (graphs.draw(seed, e) * (j + 1)) >> 64
+        e += 1
+        chosen.add(j if t in chosen else t)
+    return sorted(chosen)
+
+
+@pytest.mark.parametrize("s,seed", [(1, 3), (37, 4), (300, 5), (999, 6)])
+def test_induced_subgraph_matches_brute_force(s, seed):
+    g = graphs.chung_lu(1000, 12, 2.5, 1.0, 9)
+    h = graphs.induced(g, s, seed)
+    _check_oriented(h)
+    sub = _floyd_subset(g.n, s, seed)
+    assert h.n == len(sub) == s
+    idx = {v: i for i, v in enumerate(sub)}
+    want = set()
+    for u in sub:
+        for v in g.col[g.row_ptr[u]:g.row_ptr[u + 1]]:
+            if int(v) in idx:
+                want.add((idx[u], idx[int(v)]))
+    got = {(u, int(v)) for u in range(h.n) for v in h.col[h.row_ptr[u]:h.row_ptr[u + 1]]}
+    assert got == want
+
+
+def test_induced_whole_graph_and_threads():
+    g = graphs.chung_lu(2000, 16, 2.5, 1.0, 1)
+    assert graphs.induced(g, g.n, 3).checksum() == g.checksum()
+    assert graphs.induced(g, 0, 3).n == 0
+    hs = graphs.induced_many(g, [(700, i) for i in range(12)], threads=4)
+    assert [h.checksum() for h in hs] == [graphs.induced(g, 700, i).checksum() for i in range(12)]
