@@ -124,3 +124,107 @@ def kclique(row_ptr, col, k: int, range_leaf: int = 64) -> OracleResult:
     if v < 0:
         raise ValueError("oracle kclique: invalid arguments")
     return _res(v, c)
+
+
+# ---- FMM (GTaP Sec. 6.5.1) -------------------------------------------------
+class _FmmStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("n_cells", "n_leaves", "max_level", "m2l_pairs", "p2p_pairs")] + \
+               [("m2l_hash", ctypes.c_uint64), ("p2p_hash", ctypes.c_uint64),
+                ("p2p_interactions", ctypes.c_int64), ("coincident", ctypes.c_int64)]
+
+
+CELL_DTYPE = np.dtype([("level", np.int32), ("ax", np.int32), ("ay", np.int32), ("az", np.int32),
+                       ("begin", np.int32), ("end", np.int32), ("child0", np.int32), ("nchild", np.int32),
+                       ("parent", np.int32)])
+
+
+@dataclass
+class FmmResult:
+    phi: np.ndarray
+    stats: dict
+    m2l: np.ndarray = None   # (pairs, 2) int32: (target cell, source cell)
+    p2p: np.ndarray = None
+
+
+def _fmm_lib():
+    lib = _load()
+    if not getattr(lib, "_fmm_bound", False):
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        lib.orc_fmm_tree.argtypes = [i64, vp, vp, vp, ctypes.c_int, vp, vp, i64, vp]
+        lib.orc_fmm_tree.restype = i64
+        lib.orc_fmm.argtypes = [i64, vp, vp, vp, vp, ctypes.c_int, i64, i64, ctypes.c_int, vp, i64, vp,
+                                ctypes.POINTER(_FmmStats), vp, vp, i64]
+        lib.orc_fmm.restype = ctypes.c_int
+        lib.orc_direct.argtypes = [i64, vp, vp, vp, vp, vp, i64, vp]
+        lib.orc_direct.restype = None
+        lib._fmm_bound = True
+    return lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def fmm_tree(x, y, z, leaf_max: int = 64):
+    """Octree of the FMM reading in ``fmm.c``: (perm, cells, sorted keys)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.size
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    keys = np.zeros(max(n, 1), dtype=np.uint64)
+    cap = 2 * max(n, 1) + 64
+    cells = np.zeros(cap, dtype=CELL_DTYPE)
+    nc = _fmm_lib().orc_fmm_tree(n, x.ctypes.data, y.ctypes.data, z.ctypes.data, int(leaf_max),
+                                 perm.ctypes.data, cells.ctypes.data, cap, keys.ctypes.data)
+    if nc < 0:
+        raise ValueError("oracle fmm_tree: point outside the root cube" if nc == -1 else "too many cells")
+    return perm[:n], cells[:nc].copy(), keys[:n]
+
+
+def fmm(x, y, z, q, p: int = 6, theta=(1, 2), leaf_max: int = 64, targets=None,
+        lists: bool = False) -> FmmResult:
+    """Potentials of the FMM pipeline (all points, or the listed targets) with
+    pair counts and order-independent pair hashes."""
+    x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
+    n = x.size
+    st = _FmmStats()
+    if targets is None:
+        tg, nt, phi = None, 0, np.zeros(max(n, 1))
+    else:
+        tg = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+        nt = tg.size
+        phi = np.zeros(max(nt, 1))
+    cap = 0
+    m2l = p2p = None
+    lib = _fmm_lib()
+    if lists:
+        # a first pass learns the list sizes
+        rc = lib.orc_fmm(n, x.ctypes.data, y.ctypes.data, z.ctypes.data, q.ctypes.data, int(p), int(theta[0]),
+                         int(theta[1]), int(leaf_max), np.zeros(1, np.int64).ctypes.data, 0,
+                         np.zeros(1).ctypes.data, ctypes.byref(st), None, None, 0)
+        if rc != 0:
+            raise ValueError(f"oracle fmm: error {rc}")
+        cap = max(st.m2l_pairs, st.p2p_pairs, 1)
+        m2l = np.zeros((cap, 2), dtype=np.int32)
+        p2p = np.zeros((cap, 2), dtype=np.int32)
+    rc = lib.orc_fmm(n, x.ctypes.data, y.ctypes.data, z.ctypes.data, q.ctypes.data, int(p), int(theta[0]),
+                     int(theta[1]), int(leaf_max), tg.ctypes.data if tg is not None else None, nt,
+                     phi.ctypes.data, ctypes.byref(st), m2l.ctypes.data if lists else None,
+                     p2p.ctypes.data if lists else None, cap)
+    if rc != 0:
+        raise ValueError(f"oracle fmm: error {rc}")
+    stats = {f: getattr(st, f) for f, _ in _FmmStats._fields_}
+    out = FmmResult(phi[: (n if targets is None else nt)], stats)
+    if lists:
+        out.m2l = m2l[: st.m2l_pairs]
+        out.p2p = p2p[: st.p2p_pairs]
+    return out
+
+
+def direct(x, y, z, q, targets) -> np.ndarray:
+    """Direct summation sum_{j != i} q_j / |x_i - x_j| at the listed targets."""
+    x, y, z, q = _f64(x), _f64(y), _f64(z), _f64(q)
+    tg = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+    phi = np.zeros(max(tg.size, 1))
+    _fmm_lib().orc_direct(x.size, x.ctypes.data, y.ctypes.data, z.ctypes.data, q.ctypes.data, tg.ctypes.data,
+                          tg.size, phi.ctypes.data)
+    return phi[: tg.size]

@@ -316,3 +316,33 @@ int64_t syn_induced(int64_t n, const int64_t *rp, const int32_t *col, int64_t s,
     memset(mark, 0, sizeof(uint64_t) * (size_t)(n / 64 + 1));
     return m;
 }
+
+/*
+ * Plummer sphere (scale a = 1) of n points with charges, from the splitmix64
+ * stream `seed`: radius by inverting the enclosed-mass fraction
+ * M(r) = r^3 / (1 + r^2)^(3/2) at an open-interval uniform u, redrawn while
+ * r > 100; direction uniform on the sphere (cos theta uniform in [-1, 1),
+ * azimuth uniform in [0, 2 pi)); charge 2u - 1 with u open-interval uniform.
+ */
+static double syn_open01(uint64_t h) { return ((double)(h >> 11) + 0.5) * 0x1.0p-53; }
+static double syn_unit01(uint64_t h) { return (double)(h >> 11) * 0x1.0p-53; }
+
+void syn_plummer(int64_t n, uint64_t seed, double *x, double *y, double *z, double *q)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    uint64_t e = 0;
+    for (int64_t i = 0; i < n; i++) {
+        double r;
+        do {
+            double u = syn_open01(syn_draw(seed, e++));
+            r = 1.0 / sqrt(pow(u, -2.0 / 3.0) - 1.0);
+        } while (!(r <= 100.0));
+        double ct = 2.0 * syn_unit01(syn_draw(seed, e++)) - 1.0;
+        double ph = two_pi * syn_unit01(syn_draw(seed, e++));
+        double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+        x[i] = r * st * cos(ph);
+        y[i] = r * st * sin(ph);
+        z[i] = r * ct;
+        q[i] = 2.0 * syn_open01(syn_draw(seed, e++)) - 1.0;
+    }
+}
