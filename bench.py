@@ -219,8 +219,8 @@ def bench_serving(args, gtap) -> int:
     g = graphs.chung_lu(1000000, 40, 2.1, 0.6, 2)
     say(f"graph ready {time.perf_counter() - t0:.1f}s max_outdeg={g.max_outdeg}")
     rt = gtap.Runtime(num_waves=args.num_waves, waves_per_group=args.waves_per_group, max_jobs=1 << 15,
-                      small_frames=1 << 26, big_frames=1 << 21, big_frame_ints=max(320, g.max_outdeg),
-                      deque_capacity=1 << 16, timeout_ms=300000)
+                      small_frames=1 << 26, big_frames=1 << 22, big_frame_ints=max(320, g.max_outdeg),
+                      deque_capacity=1 << 18, timeout_ms=300000)
     headroom = 1 << 25
     specs, entries, classes, keep, subs, staged = serving_trace(gtap, rt, g, args.jobs, 5, torch)
     n = len(entries)
@@ -334,6 +334,68 @@ def serving_cpu_baseline(specs, subs, gpu_results, budget_s: float = 15.0) -> di
             "sample_matches": match}
 
 
+def bench_fmm(args, gtap) -> int:
+    """3D Laplace FMM in block mode on 10^6 Plummer points (leaf 64, theta 1/2,
+    order 6): traversal tasks with M2L and cooperative P2P inside."""
+    import numpy as np
+    import torch
+    from synth import points
+    n = args.fmm_points
+    x, y, z, q = points.plummer(n, 3)
+    tx, ty, tz, tq = (torch.as_tensor(a).cuda() for a in (x, y, z, q))
+    phi = torch.zeros_like(tx)
+    rt = gtap.Runtime(mode=gtap.GTAP_MODE_BLOCK, waves_per_group=args.fmm_wpg, small_frames=1 << 24,
+                      big_frames=0, timeout_ms=120000, num_waves=args.num_waves if args.num_waves != 1024 else 0)
+    for _ in range(args.warmup):
+        rt.submit_fmm(tx, ty, tz, tq, phi)
+        rt.run()
+    torch.cuda.synchronize()
+    res, wall = [], []
+    for _ in range(args.steps):
+        phi.zero_()
+        t0 = time.perf_counter()
+        j = rt.submit_fmm(tx, ty, tz, tq, phi)
+        rt.run()
+        wall.append(time.perf_counter() - t0)
+        res.append(rt.fmm_result(j))
+    st = rt.stats()
+    rt.close()
+    med = sorted(range(len(wall)), key=lambda i: wall[i])[len(wall) // 2]
+    r = res[med]
+    trav_s = r["traversal_ms"] * 1e-3
+    e2e = wall[med]
+    out = {"metric": METRIC, "value": r["p2p_interactions"] / trav_s, "unit": "P2P interactions/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"FMM dual-tree traversal, block mode: {n} Plummer points (seed 3), "
+                                  "leaf 64, theta 1/2, Cartesian order 6", "waves": st["num_waves"],
+                      "waves_per_group": st["waves_per_group"]},
+           "m2l_pairs_per_s": r["m2l_pairs"] / trav_s, "traversal_tasks_per_s": st["tasks"] / trav_s,
+           "end_to_end_ms_median": 1e3 * e2e, "end_to_end_ms_min": 1e3 * min(wall),
+           "end_to_end_ms_max": 1e3 * max(wall),
+           "phase_ms": {k: r[k] for k in ("tree_ms", "upward_ms", "traversal_ms", "downward_ms")},
+           "lists": {k: r[k] for k in ("n_cells", "n_leaves", "max_level", "m2l_pairs", "p2p_pairs",
+                                       "p2p_interactions", "coincident")},
+           "traversal_tasks": st["tasks"], "traversal_conts": st["conts"]}
+    if not args.no_cpu_baseline:
+        import oracle
+        tg = np.random.default_rng(17).choice(n, 256, replace=False)
+        t0 = time.perf_counter()
+        w = oracle.fmm(x, y, z, q, targets=tg)
+        el = time.perf_counter() - t0
+        got = phi.cpu().numpy()[tg]
+        err = np.linalg.norm(got - w.phi) / np.linalg.norm(w.phi)
+        out["cpu_baseline"] = {"value": w.stats["p2p_interactions"] / el, "unit": "P2P interactions/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"oracle FMM (tree, upward pass, full traversal) evaluated at 256 "
+                                         f"sampled targets, {el:.1f} s on one host thread"}
+        out["parity_sampled"] = {"targets": 256, "rel_l2": err,
+                                 "lists_equal": all(r[k] == w.stats[k] for k in
+                                                    ("m2l_pairs", "p2p_pairs", "m2l_hash", "p2p_hash"))}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,7 +407,9 @@ def main() -> int:
     ap.add_argument("--steal-below", type=int, default=64)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run only a plain device copy of this many bytes (counter calibration)")
-    ap.add_argument("--workload", default="microbench", choices=("microbench", "kclique7", "serving"),
+    ap.add_argument("--fmm-points", type=int, default=1000000, help="fmm: number of points")
+    ap.add_argument("--fmm-wpg", type=int, default=1, help="fmm: wavefronts per workgroup (1, 2, 4)")
+    ap.add_argument("--workload", default="microbench", choices=("microbench", "kclique7", "serving", "fmm"),
                     help="kclique7: 7-cliques of the n=10^6 Chung-Lu graph (DAQ comparison); "
                          "serving: batched / served job mix against one launch per job")
     ap.add_argument("--jobs", type=int, default=20000, help="serving: jobs in the trace")
@@ -368,6 +432,8 @@ def main() -> int:
         return bench_kclique7(args, gtap)
     if args.workload == "serving":
         return bench_serving(args, gtap)
+    if args.workload == "fmm":
+        return bench_fmm(args, gtap)
 
     rt = gtap.Runtime(waves_per_group=args.waves_per_group, num_waves=args.num_waves,
                       steal_below=args.steal_below, small_frames=1 << 25, timeout_ms=60000)

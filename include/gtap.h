@@ -58,7 +58,8 @@ enum gtap_kind {
     GTAP_KIND_FIB = 1,      /* gtap_fib_args                                   */
     GTAP_KIND_NQUEENS = 2,  /* gtap_nqueens_args                               */
     GTAP_KIND_UTS = 3,      /* gtap_uts_args                                   */
-    GTAP_KIND_KCLIQUE = 4   /* gtap_kclique_args                               */
+    GTAP_KIND_KCLIQUE = 4,  /* gtap_kclique_args                               */
+    GTAP_KIND_FMM = 5       /* gtap_fmm_args (block mode only)                 */
 };
 
 /* Fibonacci with a task at every call (Sec. 6.3, microbenchmarks): result is
@@ -91,6 +92,54 @@ typedef struct {
     int32_t max_outdeg;
 } gtap_kclique_args;
 
+/* 3D Laplace FMM whose interaction phase is a dual-tree traversal run as
+ * block-mode tasks (Sec. 6.5.1, "FMM Dual-Tree Traversal").  The library builds
+ * an octree over the n points (root cube [-128, 128)^3; a cell with more than
+ * leaf_max points below level 21 splits into its non-empty octants), computes
+ * multipole moments (P2M, M2M), runs the traversal from the (root, root) cell
+ * pair -- each task accepts its pair by the integer MAC with
+ * theta = theta_num / theta_den and adds an M2L contribution, runs a
+ * workgroup-wide P2P on a pair of leaves, or forks the child pairs of the
+ * wider cell -- and finishes with L2L and L2P.  Expansions are Cartesian
+ * Taylor series of total degree `order` (must be 6).  phi_dev[i] receives
+ * sum over j != i of q_j / |x_i - x_j| approximated by the FMM (coincident
+ * distinct points skipped).  All pointers are fp64 device arrays of n entries,
+ * borrowed until gtap_run returns.  Requires 1 <= n < 2^31, every coordinate
+ * in [-128, 128), 1 <= leaf_max <= 64, 0 <= theta_num and 1 <= theta_den <= 64
+ * with theta_num <= theta_den. */
+typedef struct {
+    const double *x_dev;
+    const double *y_dev;
+    const double *z_dev;
+    const double *q_dev;
+    double *phi_dev;
+    int32_t n;
+    int32_t leaf_max;
+    int32_t theta_num;
+    int32_t theta_den;
+    int32_t order;
+    int32_t reserved;
+} gtap_fmm_args;
+
+/* What gtap_result returns for an FMM job (out_bytes >= its size).  The pair
+ * hashes are wrapping sums of splitmix64((A << 32) | B) over the (target cell,
+ * source cell) pairs of each list, independent of the traversal's order. */
+typedef struct {
+    int64_t n_cells;
+    int64_t n_leaves;
+    int64_t max_level;
+    int64_t m2l_pairs;
+    int64_t p2p_pairs;
+    uint64_t m2l_hash;
+    uint64_t p2p_hash;
+    int64_t p2p_interactions;  /* (i, j != i) pairs evaluated by P2P          */
+    int64_t coincident;        /* of those, distinct points at the same place */
+    double tree_ms;            /* sort and octree construction               */
+    double upward_ms;          /* P2M and M2M                                */
+    double traversal_ms;       /* the block-mode launch (shared by the run's jobs) */
+    double downward_ms;        /* L2L, L2P and the scatter to phi_dev        */
+} gtap_fmm_result;
+
 /* ---- configuration -------------------------------------------------------- */
 enum gtap_daq_policy {
     GTAP_DAQ_NONE = 0,      /* every task in queue 0                            */
@@ -100,10 +149,14 @@ enum gtap_daq_policy {
 };
 
 typedef struct gtap_config {
-    int32_t mode;             /* gtap_mode; only GTAP_MODE_THREAD runs today   */
+    int32_t mode;             /* gtap_mode.  Thread mode runs every kind but
+                                 FMM; block mode runs FIB, UTS and FMM, one
+                                 task per workgroup, one Chase-Lev deque per
+                                 workgroup (num_queues must be 1)            */
     int32_t num_waves;        /* persistent wavefronts; 0 = every wavefront the
                                  device can keep resident                      */
-    int32_t waves_per_group;  /* wavefronts per workgroup: 1, 2, 4 or 8        */
+    int32_t waves_per_group;  /* wavefronts per workgroup: 1, 2, 4 or 8 (block
+                                 mode: 1, 2 or 4, i.e. 64..256 threads)       */
     int32_t num_queues;       /* DAQ deques per wavefront, 1..8 (1 = DAQ off)  */
     int32_t daq_policy;       /* gtap_daq_policy                               */
     int32_t daq_bounds[7];    /* ascending class boundaries (GTAP_DAQ_KCLIQUE) */
@@ -151,15 +204,20 @@ int gtap_submit(gtap_ctx *ctx, int32_t kind, const void *args, size_t args_bytes
                 uint64_t *job_id);
 
 /* Launch one persistent kernel for every pending job on cfg->stream and wait
- * for it.  Jobs' results become readable with gtap_result.  Returns
- * GTAP_E_CAPACITY or GTAP_E_TIMEOUT when the device aborted the run (results
- * of that run are then invalid; the context stays usable), GTAP_E_HIP on a
- * HIP failure. */
+ * for it.  Jobs' results become readable with gtap_result.  FMM jobs also run
+ * their tree construction and upward pass before, and their downward pass
+ * after, that launch (device memory for them is allocated and freed inside
+ * this call).  Returns GTAP_E_CAPACITY or GTAP_E_TIMEOUT when the device
+ * aborted the run (results of that run are then invalid; the context stays
+ * usable), GTAP_E_INVAL when an FMM job's points leave the root cube,
+ * GTAP_E_NOMEM, GTAP_E_HIP on a HIP failure. */
 int gtap_run(gtap_ctx *ctx);
 
-/* Copy job job_id's result (int64 count, out_bytes >= 8) into host memory
- * out.  Valid for the jobs of the most recent gtap_run.  Errors:
- * GTAP_E_NOJOB, GTAP_E_PENDING (not part of a completed run), GTAP_E_INVAL. */
+/* Copy job job_id's result into host memory out: an int64 count
+ * (out_bytes >= 8), or for an FMM job a gtap_fmm_result (out_bytes >= its
+ * size; the potentials are in the job's phi_dev).  Valid for the jobs of the
+ * most recent gtap_run.  Errors: GTAP_E_NOJOB, GTAP_E_PENDING (not part of a
+ * completed run), GTAP_E_INVAL. */
 int gtap_result(gtap_ctx *ctx, uint64_t job_id, void *out, size_t out_bytes);
 
 /* Release the context and any memory the library allocated for it. */

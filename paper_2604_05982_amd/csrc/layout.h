@@ -23,7 +23,7 @@ constexpr uint32_t kDepotBins = 256;           // depot bins per pool
 
 // Per-wave LDS free-stack capacities and depot chunk sizes (IDs).
 constexpr uint32_t kStackSmall = 1024;
-constexpr uint32_t kStackBig = 256;
+constexpr uint32_t kStackBig = 128;
 constexpr uint32_t kChunkSmall = 256;
 constexpr uint32_t kChunkBig = 64;
 
@@ -60,6 +60,7 @@ enum TaskKind : uint32_t {
   TK_KC_RANGE = 4,
   TK_KC_VERTEX = 5,
   TK_KC_CAND = 6,
+  TK_FMM = 7,       // block mode: FMM cell pair (A, B)
 };
 
 struct alignas(128) DequeMeta {

@@ -15,8 +15,12 @@
 #include <thread>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "../../include/gtap.h"
+#include "fmm.h"
 #include "layout.h"
+#include "sched_block.h"
 #include "sched_thread.h"
 
 using namespace gtap;
@@ -66,18 +70,34 @@ int occupancy_blocks(int *blocks_per_cu) {
              : -1;
 }
 
-int max_resident_waves(int wpb, uint32_t *out) {
+template <int NT>
+int occupancy_block_mode(int *blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, block_sched_kernel<NT>, NT, 0) == hipSuccess
+             ? 0
+             : -1;
+}
+
+int max_resident_waves(int mode, int wpb, uint32_t *out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return GTAP_E_HIP;
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return GTAP_E_HIP;
   int bpc = 0, rc = -1;
-  switch (wpb) {
-    case 1: rc = occupancy_blocks<1>(&bpc); break;
-    case 2: rc = occupancy_blocks<2>(&bpc); break;
-    case 4: rc = occupancy_blocks<4>(&bpc); break;
-    case 8: rc = occupancy_blocks<8>(&bpc); break;
-    default: return GTAP_E_INVAL;
+  if (mode == GTAP_MODE_BLOCK) {
+    switch (wpb) {
+      case 1: rc = occupancy_block_mode<64>(&bpc); break;
+      case 2: rc = occupancy_block_mode<128>(&bpc); break;
+      case 4: rc = occupancy_block_mode<256>(&bpc); break;
+      default: return GTAP_E_INVAL;
+    }
+  } else {
+    switch (wpb) {
+      case 1: rc = occupancy_blocks<1>(&bpc); break;
+      case 2: rc = occupancy_blocks<2>(&bpc); break;
+      case 4: rc = occupancy_blocks<4>(&bpc); break;
+      case 8: rc = occupancy_blocks<8>(&bpc); break;
+      default: return GTAP_E_INVAL;
+    }
   }
   if (rc != 0 || bpc <= 0 || ncu <= 0) return GTAP_E_HIP;
   *out = static_cast<uint32_t>(bpc) * static_cast<uint32_t>(ncu) * static_cast<uint32_t>(wpb);
@@ -87,9 +107,10 @@ int max_resident_waves(int wpb, uint32_t *out) {
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
 int validate(const gtap_config &c) {
-  if (c.mode != GTAP_MODE_THREAD) return GTAP_E_INVAL;
+  if (c.mode != GTAP_MODE_THREAD && c.mode != GTAP_MODE_BLOCK) return GTAP_E_INVAL;
   if (c.waves_per_group != 1 && c.waves_per_group != 2 && c.waves_per_group != 4 && c.waves_per_group != 8)
     return GTAP_E_INVAL;
+  if (c.mode == GTAP_MODE_BLOCK && (c.waves_per_group > 4 || c.num_queues != 1)) return GTAP_E_INVAL;
   if (c.num_waves < 0 || c.num_queues < 1 || c.num_queues > static_cast<int32_t>(kMaxQueues)) return GTAP_E_INVAL;
   if (c.daq_policy < GTAP_DAQ_NONE || c.daq_policy > GTAP_DAQ_KCLIQUE) return GTAP_E_INVAL;
   if (!is_pow2(c.deque_capacity) || c.deque_capacity < 128 || c.deque_capacity > (1u << 28)) return GTAP_E_INVAL;
@@ -110,6 +131,7 @@ __global__ void reset_kernel(Params p, uint32_t ndeques) {
     p.dq[d].count = 0;
     p.dq[d].head = 0;
     p.dq[d].lock = 0;
+    p.dq[d].pad[0] = 0;  // block mode reads the line as {int64 top, int64 bottom}
   }
   for (size_t b = i0; b < kDepotBins; b += stride) {
     p.bins_s[b].lock = 0;
@@ -160,6 +182,9 @@ struct gtap_ctx {
   HostCompletion *done_host = nullptr;
   int32_t *stop_host = nullptr;
   uint64_t next_ticket = 0;
+  // FMM jobs: arguments by pending position, results by run position
+  std::vector<gtap_fmm_args> pending_fmm;
+  std::vector<gtap_fmm_result> done_fmm;
   gtap_stats stats{};
   gtap_error_report err{};
 };
@@ -192,7 +217,7 @@ int gtap_workspace_size(const gtap_config *cfg, uint64_t *bytes) {
   int rc = validate(*cfg);
   if (rc) return rc;
   uint32_t maxw = 0;
-  rc = max_resident_waves(cfg->waves_per_group, &maxw);
+  rc = max_resident_waves(cfg->mode, cfg->waves_per_group, &maxw);
   if (rc) return rc;
   uint32_t nw = cfg->num_waves ? std::min<uint32_t>(cfg->num_waves, maxw) : maxw;
   nw = std::max<uint32_t>(nw / cfg->waves_per_group, 1) * cfg->waves_per_group;
@@ -206,7 +231,7 @@ int gtap_init(const gtap_config *cfg, gtap_ctx **out) {
   int rc = validate(*cfg);
   if (rc) return rc;
   uint32_t maxw = 0;
-  rc = max_resident_waves(cfg->waves_per_group, &maxw);
+  rc = max_resident_waves(cfg->mode, cfg->waves_per_group, &maxw);
   if (rc) return rc;
   gtap_ctx *c = new (std::nothrow) gtap_ctx();
   if (!c) return GTAP_E_NOMEM;
@@ -280,6 +305,9 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
   if (!args) return GTAP_E_INVAL;
   std::memset(&J, 0, sizeof(J));
   J.kind = static_cast<uint32_t>(kind);
+  const bool block = c->cfg.mode == GTAP_MODE_BLOCK;
+  if (block && kind != GTAP_KIND_FIB && kind != GTAP_KIND_UTS && kind != GTAP_KIND_FMM) return GTAP_E_INVAL;
+  if (!block && kind == GTAP_KIND_FMM) return GTAP_E_INVAL;
   switch (kind) {
     case GTAP_KIND_FIB: {
       if (args_bytes != sizeof(gtap_fib_args)) return GTAP_E_INVAL;
@@ -328,6 +356,15 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
       J.a[5] = static_cast<uint64_t>(a.max_outdeg);
       return GTAP_OK;
     }
+    case GTAP_KIND_FMM: {
+      if (args_bytes != sizeof(gtap_fmm_args)) return GTAP_E_INVAL;
+      gtap_fmm_args a;
+      std::memcpy(&a, args, sizeof(a));
+      if (a.n < 1 || !a.x_dev || !a.y_dev || !a.z_dev || !a.q_dev || !a.phi_dev) return GTAP_E_INVAL;
+      if (a.leaf_max < 1 || a.leaf_max > 64 || a.order != fmm::kP) return GTAP_E_INVAL;
+      if (a.theta_num < 0 || a.theta_den < 1 || a.theta_den > 64 || a.theta_num > a.theta_den) return GTAP_E_INVAL;
+      return GTAP_OK;  // the device descriptor is built by gtap_run
+    }
     default:
       return GTAP_E_INVAL;
   }
@@ -340,8 +377,14 @@ extern "C" int gtap_submit(gtap_ctx *c, int32_t kind, const void *args, size_t a
   JobSlot J;
   const int rc = pack_job(c, kind, args, args_bytes, J);
   if (rc) return rc;
-  if (c->pending.empty()) c->pending_first = c->next_job_id;
+  if (c->pending.empty()) {
+    c->pending_first = c->next_job_id;
+    c->pending_fmm.clear();
+  }
   c->pending.push_back(J);
+  gtap_fmm_args fa{};
+  if (kind == GTAP_KIND_FMM) std::memcpy(&fa, args, sizeof(fa));
+  c->pending_fmm.push_back(fa);
   if (job_id) *job_id = c->next_job_id;
   c->next_job_id++;
   return GTAP_OK;
@@ -387,6 +430,15 @@ static int record_run(gtap_ctx *c, const Control &ctl, float ms) {
 static int launch_sched(gtap_ctx *c) {
   const uint32_t wpb = static_cast<uint32_t>(c->cfg.waves_per_group);
   const dim3 grid(c->nwaves / wpb), block(64 * wpb);
+  if (c->cfg.mode == GTAP_MODE_BLOCK) {
+    switch (wpb) {
+      case 1: hipLaunchKernelGGL(block_sched_kernel<64>, grid, block, 0, c->stream, c->params); break;
+      case 2: hipLaunchKernelGGL(block_sched_kernel<128>, grid, block, 0, c->stream, c->params); break;
+      case 4: hipLaunchKernelGGL(block_sched_kernel<256>, grid, block, 0, c->stream, c->params); break;
+      default: return GTAP_E_INVAL;
+    }
+    return hipGetLastError() == hipSuccess ? GTAP_OK : GTAP_E_HIP;
+  }
   switch (wpb) {
     case 1: hipLaunchKernelGGL(thread_sched_kernel<1>, grid, block, 0, c->stream, c->params); break;
     case 2: hipLaunchKernelGGL(thread_sched_kernel<2>, grid, block, 0, c->stream, c->params); break;
@@ -397,6 +449,187 @@ static int launch_sched(gtap_ctx *c) {
   return hipGetLastError() == hipSuccess ? GTAP_OK : GTAP_E_HIP;
 }
 
+}  // extern "C"
+
+// ---- FMM jobs: passes around the block-mode traversal -----------------------
+namespace {
+
+struct FmmJobMem {
+  uint64_t *keys = nullptr, *keys_sorted = nullptr;
+  int32_t *idx = nullptr, *perm = nullptr;
+  void *sort_tmp = nullptr;
+  double *pts = nullptr;  // px | py | pz | pq | phi, n each
+  int32_t *cell = nullptr, *parent = nullptr;
+  int64_t cell_cap = 0;
+  int32_t *scratch = nullptr;  // nch | off | bnd | flags
+  double *Q = nullptr, *L = nullptr;
+  fmm::FmmDesc *desc = nullptr;
+  std::vector<std::pair<int32_t, int32_t>> levels;
+  int32_t ncells = 0;
+  hipEvent_t ev[6] = {};
+};
+
+void fmm_free(FmmJobMem &m) {
+  void *ptrs[] = {m.keys, m.keys_sorted, m.idx, m.perm, m.sort_tmp, m.pts, m.cell, m.parent, m.scratch,
+                  m.Q, m.L, m.desc};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+  for (hipEvent_t &e : m.ev)
+    if (e) (void)hipEventDestroy(e);
+  m = FmmJobMem{};
+}
+
+template <typename T>
+bool dev_alloc(T **p, size_t count) {
+  return hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * (count ? count : 1)) == hipSuccess;
+}
+
+unsigned nblk(int64_t n, unsigned b) { return static_cast<unsigned>(std::max<int64_t>((n + b - 1) / b, 1)); }
+
+// Sort, octree, P2M and M2M of one FMM job; fills the device descriptor.
+int fmm_prepare(gtap_ctx *c, const gtap_fmm_args &a, FmmJobMem &m) {
+  hipStream_t st = c->stream;
+  const int32_t n = a.n;
+  for (hipEvent_t &e : m.ev)
+    if (hipEventCreate(&e) != hipSuccess) return GTAP_E_HIP;
+  if (!dev_alloc(&m.keys, n) || !dev_alloc(&m.keys_sorted, n) || !dev_alloc(&m.idx, n) ||
+      !dev_alloc(&m.perm, n) || !dev_alloc(&m.pts, 5 * static_cast<size_t>(n)) ||
+      !dev_alloc(&m.scratch, 11 * (static_cast<size_t>(n) + 1) + 2))
+    return GTAP_E_NOMEM;
+  int32_t *nch = m.scratch, *off = nch + (n + 1), *bnd = off + (n + 1), *flags = bnd + 9 * (static_cast<size_t>(n) + 1);
+  double *px = m.pts, *py = px + n, *pz = py + n, *pq = pz + n, *phi = pq + n;
+  if (hipEventRecord(m.ev[0], st) != hipSuccess) return GTAP_E_HIP;
+  if (hipMemsetAsync(flags, 0, 2 * sizeof(int32_t), st) != hipSuccess) return GTAP_E_HIP;
+  hipLaunchKernelGGL(fmm::k_keys, dim3(nblk(n, 256)), dim3(256), 0, st, n, a.x_dev, a.y_dev, a.z_dev, m.keys,
+                     m.idx, flags + 1);
+  size_t tmp_bytes = 0;
+  if (rocprim::radix_sort_pairs(nullptr, tmp_bytes, m.keys, m.keys_sorted, m.idx, m.perm,
+                                static_cast<size_t>(n), 0, 63, st) != hipSuccess)
+    return GTAP_E_HIP;
+  if (hipMalloc(&m.sort_tmp, tmp_bytes ? tmp_bytes : 1) != hipSuccess) return GTAP_E_NOMEM;
+  if (rocprim::radix_sort_pairs(m.sort_tmp, tmp_bytes, m.keys, m.keys_sorted, m.idx, m.perm,
+                                static_cast<size_t>(n), 0, 63, st) != hipSuccess)
+    return GTAP_E_HIP;
+  hipLaunchKernelGGL(fmm::k_gather, dim3(nblk(n, 256)), dim3(256), 0, st, n, m.perm, a.x_dev, a.y_dev, a.z_dev,
+                     a.q_dev, px, py, pz, pq, phi);
+  // octree, one level at a time (the host learns each level's size)
+  m.cell_cap = 2 * static_cast<int64_t>(n) + 64;
+  if (!dev_alloc(&m.cell, static_cast<size_t>(m.cell_cap) * fmm::kCellInts) ||
+      !dev_alloc(&m.parent, static_cast<size_t>(m.cell_cap)))
+    return GTAP_E_NOMEM;
+  hipLaunchKernelGGL(fmm::k_root, dim3(1), dim3(64), 0, st, m.cell, m.parent, n);
+  int32_t lo = 0, hi = 1;
+  m.levels.clear();
+  m.levels.emplace_back(lo, hi);
+  for (;;) {
+    const int32_t w = hi - lo;
+    hipLaunchKernelGGL(fmm::k_level_count, dim3(nblk(w, 256)), dim3(256), 0, st, m.cell, lo, hi, m.keys_sorted,
+                       a.leaf_max, nch, bnd);
+    hipLaunchKernelGGL(fmm::k_scan, dim3(1), dim3(1024), 0, st, nch, off, w, flags);
+    int32_t hf[2] = {0, 0};
+    if (hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return GTAP_E_HIP;
+    if (hf[1] != 0) return GTAP_E_INVAL;  // a point outside the root cube
+    const int32_t total = hf[0];
+    if (total == 0) break;
+    if (hi + static_cast<int64_t>(total) > m.cell_cap) {
+      const int64_t cap2 = std::max<int64_t>(2 * m.cell_cap, hi + static_cast<int64_t>(total) + 64);
+      int32_t *c2 = nullptr, *p2 = nullptr;
+      if (!dev_alloc(&c2, static_cast<size_t>(cap2) * fmm::kCellInts) || !dev_alloc(&p2, static_cast<size_t>(cap2)))
+        return GTAP_E_NOMEM;
+      if (hipMemcpyAsync(c2, m.cell, sizeof(int32_t) * fmm::kCellInts * hi, hipMemcpyDeviceToDevice, st) !=
+              hipSuccess ||
+          hipMemcpyAsync(p2, m.parent, sizeof(int32_t) * hi, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return GTAP_E_HIP;
+      (void)hipFree(m.cell);
+      (void)hipFree(m.parent);
+      m.cell = c2;
+      m.parent = p2;
+      m.cell_cap = cap2;
+    }
+    hipLaunchKernelGGL(fmm::k_level_write, dim3(nblk(w, 256)), dim3(256), 0, st, m.cell, m.parent, lo, hi, nch,
+                       off, bnd);
+    lo = hi;
+    hi += total;
+    m.levels.emplace_back(lo, hi);
+  }
+  m.ncells = hi;
+  if (hipEventRecord(m.ev[1], st) != hipSuccess) return GTAP_E_HIP;
+  if (!dev_alloc(&m.Q, static_cast<size_t>(m.ncells) * fmm::kNc) ||
+      !dev_alloc(&m.L, static_cast<size_t>(m.ncells) * fmm::kNc))
+    return GTAP_E_NOMEM;
+  if (hipMemsetAsync(m.L, 0, sizeof(double) * fmm::kNc * m.ncells, st) != hipSuccess) return GTAP_E_HIP;
+  hipLaunchKernelGGL(fmm::k_p2m, dim3(m.ncells), dim3(128), 0, st, m.cell, 0, m.ncells, px, py, pz, pq, m.Q);
+  for (size_t l = m.levels.size(); l-- > 0;) {
+    const auto [l0, l1] = m.levels[l];
+    hipLaunchKernelGGL(fmm::k_m2m, dim3(l1 - l0), dim3(128), 0, st, m.cell, l0, l1, m.Q);
+  }
+  if (hipEventRecord(m.ev[2], st) != hipSuccess) return GTAP_E_HIP;
+  fmm::FmmDesc d{};
+  d.cell = m.cell;
+  d.Q = m.Q;
+  d.L = m.L;
+  d.px = px;
+  d.py = py;
+  d.pz = pz;
+  d.pq = pq;
+  d.phi = phi;
+  d.ta = a.theta_num;
+  d.tb = a.theta_den;
+  if (!dev_alloc(&m.desc, 1)) return GTAP_E_NOMEM;
+  if (hipMemcpyAsync(m.desc, &d, sizeof(d), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return GTAP_E_HIP;
+  return hipGetLastError() == hipSuccess ? GTAP_OK : GTAP_E_HIP;
+}
+
+// L2L, L2P and the scatter to the caller's order; statistics into r.
+int fmm_finish(gtap_ctx *c, const gtap_fmm_args &a, FmmJobMem &m, float traversal_ms, gtap_fmm_result &r) {
+  hipStream_t st = c->stream;
+  const int32_t n = a.n;
+  double *px = m.pts, *py = px + n, *pz = py + n, *phi = pz + 2 * static_cast<size_t>(n);
+  if (hipEventRecord(m.ev[3], st) != hipSuccess) return GTAP_E_HIP;
+  for (size_t l = 1; l < m.levels.size(); ++l) {
+    const auto [l0, l1] = m.levels[l];
+    hipLaunchKernelGGL(fmm::k_l2l, dim3(l1 - l0), dim3(128), 0, st, m.cell, m.parent, l0, l1, m.L);
+  }
+  hipLaunchKernelGGL(fmm::k_l2p, dim3(m.ncells), dim3(128), 0, st, m.cell, 0, m.ncells, m.L, px, py, pz, phi);
+  hipLaunchKernelGGL(fmm::k_scatter, dim3(nblk(n, 256)), dim3(256), 0, st, n, m.perm, phi, a.phi_dev);
+  if (hipEventRecord(m.ev[4], st) != hipSuccess) return GTAP_E_HIP;
+  fmm::FmmDesc d{};
+  std::vector<int32_t> cells(static_cast<size_t>(m.ncells) * fmm::kCellInts);
+  if (hipMemcpyAsync(&d, m.desc, sizeof(d), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(cells.data(), m.cell, sizeof(int32_t) * cells.size(), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return GTAP_E_HIP;
+  r = gtap_fmm_result{};
+  r.n_cells = m.ncells;
+  for (int32_t i = 0; i < m.ncells; ++i) r.n_leaves += cells[static_cast<size_t>(i) * fmm::kCellInts + 7] == 0;
+  r.max_level = static_cast<int64_t>(m.levels.size()) - 1;
+  r.m2l_pairs = static_cast<int64_t>(d.m2l_pairs);
+  r.p2p_pairs = static_cast<int64_t>(d.p2p_pairs);
+  r.m2l_hash = d.m2l_hash;
+  r.p2p_hash = d.p2p_hash;
+  r.p2p_interactions = static_cast<int64_t>(d.p2p_inter);
+  r.coincident = static_cast<int64_t>(d.coincident);
+  float t0 = 0.f, t1 = 0.f, t2 = 0.f;
+  (void)hipEventElapsedTime(&t0, m.ev[0], m.ev[1]);
+  (void)hipEventElapsedTime(&t1, m.ev[1], m.ev[2]);
+  (void)hipEventElapsedTime(&t2, m.ev[3], m.ev[4]);
+  r.tree_ms = t0;
+  r.upward_ms = t1;
+  r.traversal_ms = traversal_ms;
+  r.downward_ms = t2;
+  return hipGetLastError() == hipSuccess ? GTAP_OK : GTAP_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
 int gtap_run(gtap_ctx *c) {
   if (!c) return GTAP_E_INVAL;
   if (c->serving) return GTAP_E_STATE;
@@ -406,41 +639,71 @@ int gtap_run(gtap_ctx *c) {
   Params &p = c->params;
   p.njobs = static_cast<uint32_t>(nj);
   p.serving = 0;
+  // FMM jobs: tree and upward pass before the traversal launch
+  std::vector<FmmJobMem> fm;
+  bool any_fmm = false;
+  for (size_t j = 0; j < nj; ++j) any_fmm |= c->pending[j].kind == GTAP_KIND_FMM;
+  auto drop_pending = [&]() {
+    for (FmmJobMem &m : fm) fmm_free(m);
+    c->pending.clear();
+    c->pending_fmm.clear();
+  };
+  if (any_fmm) {
+    fm.resize(nj);
+    for (size_t j = 0; j < nj; ++j) {
+      if (c->pending[j].kind != GTAP_KIND_FMM) continue;
+      const int rc = fmm_prepare(c, c->pending_fmm[j], fm[j]);
+      if (rc != GTAP_OK) {
+        drop_pending();
+        return rc;
+      }
+      c->pending[j].a[0] = reinterpret_cast<uint64_t>(fm[j].desc);
+    }
+  }
   if (hipMemcpyAsync(p.jobs, c->pending.data(), nj * sizeof(JobSlot), hipMemcpyHostToDevice, c->stream) !=
-      hipSuccess)
+      hipSuccess) {
+    drop_pending();
     return GTAP_E_HIP;
+  }
   const uint32_t ndq = c->nwaves * p.Q;
   hipLaunchKernelGGL(reset_kernel, dim3(std::max<uint32_t>((ndq + 255) / 256, 1)), dim3(256), 0, c->stream, p,
                      ndq);
-  if (hipGetLastError() != hipSuccess) return GTAP_E_HIP;
-  if (hipEventRecord(c->ev0, c->stream) != hipSuccess) return GTAP_E_HIP;
-  int rc = launch_sched(c);
-  if (rc) return rc;
-  if (hipEventRecord(c->ev1, c->stream) != hipSuccess) return GTAP_E_HIP;
+  int rc = GTAP_OK;
+  if (hipGetLastError() != hipSuccess || hipEventRecord(c->ev0, c->stream) != hipSuccess) rc = GTAP_E_HIP;
+  if (rc == GTAP_OK) rc = launch_sched(c);
+  if (rc == GTAP_OK && hipEventRecord(c->ev1, c->stream) != hipSuccess) rc = GTAP_E_HIP;
+  if (rc != GTAP_OK) {
+    (void)hipStreamSynchronize(c->stream);
+    drop_pending();
+    return rc;
+  }
   c->done_jobs.resize(nj);
   Control ctl;
   if (hipMemcpyAsync(c->done_jobs.data(), p.jobs, nj * sizeof(JobSlot), hipMemcpyDeviceToHost, c->stream) !=
-      hipSuccess)
+          hipSuccess ||
+      hipMemcpyAsync(&ctl, p.ctl, sizeof(Control), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    drop_pending();
     return GTAP_E_HIP;
-  if (hipMemcpyAsync(&ctl, p.ctl, sizeof(Control), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
-    return GTAP_E_HIP;
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return GTAP_E_HIP;
+  }
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
   c->done_first = c->pending_first;
-  c->pending.clear();
   c->have_done = true;
 
   const int rc_run = record_run(c, ctl, ms);
-  if (rc_run != GTAP_OK) {
-    c->have_done = false;
-    return rc_run;
+  for (size_t j = 0; rc_run == GTAP_OK && j < nj; ++j)
+    if (c->done_jobs[j].done != 1) rc = GTAP_E_STATE;
+  if (rc_run == GTAP_OK && rc == GTAP_OK && any_fmm) {
+    c->done_fmm.assign(nj, gtap_fmm_result{});
+    for (size_t j = 0; j < nj && rc == GTAP_OK; ++j)
+      if (c->pending[j].kind == GTAP_KIND_FMM) rc = fmm_finish(c, c->pending_fmm[j], fm[j], ms, c->done_fmm[j]);
   }
-  for (size_t j = 0; j < nj; ++j)
-    if (c->done_jobs[j].done != 1) {
-      c->have_done = false;
-      return GTAP_E_STATE;
-    }
+  drop_pending();
+  if (rc_run != GTAP_OK || rc != GTAP_OK) {
+    c->have_done = false;
+    return rc_run != GTAP_OK ? rc_run : rc;
+  }
   return GTAP_OK;
 }
 
@@ -453,6 +716,7 @@ static double host_seconds() {
 int gtap_serve_start(gtap_ctx *c, uint32_t max_inflight, uint32_t headroom_small, uint32_t headroom_big) {
   if (!c) return GTAP_E_INVAL;
   if (c->serving || !c->pending.empty()) return GTAP_E_STATE;
+  if (c->cfg.mode != GTAP_MODE_THREAD) return GTAP_E_INVAL;
   if (max_inflight == 0 || max_inflight > c->cfg.max_jobs) return GTAP_E_INVAL;
   const size_t R = c->cfg.max_jobs;
   if (!c->ring) {
@@ -648,7 +912,13 @@ int gtap_trace_run_plain(gtap_ctx *c, const gtap_trace_job *jobs, size_t n, gtap
 int gtap_result(gtap_ctx *c, uint64_t job_id, void *out, size_t out_bytes) {
   if (!c || !out || out_bytes < sizeof(int64_t)) return GTAP_E_INVAL;
   if (c->have_done && job_id >= c->done_first && job_id < c->done_first + c->done_jobs.size()) {
-    const JobSlot &J = c->done_jobs[job_id - c->done_first];
+    const size_t j = job_id - c->done_first;
+    const JobSlot &J = c->done_jobs[j];
+    if (J.kind == GTAP_KIND_FMM) {
+      if (out_bytes < sizeof(gtap_fmm_result) || j >= c->done_fmm.size()) return GTAP_E_INVAL;
+      std::memcpy(out, &c->done_fmm[j], sizeof(gtap_fmm_result));
+      return GTAP_OK;
+    }
     std::memcpy(out, &J.result, sizeof(int64_t));
     return GTAP_OK;
   }

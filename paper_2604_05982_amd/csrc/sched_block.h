@@ -1,0 +1,585 @@
+// sched_block.h -- block-mode persistent scheduler: one task per workgroup.
+//
+// Block mode (GTaP Sec. 4.3, 5.1.3): every thread of a workgroup runs the same
+// task cooperatively.  Each workgroup owns one Chase-Lev deque (Chase and Lev,
+// SPAA 2005): the owner pushes and pops at the bottom, thieves take one task
+// at a time from the top with a CAS.  Thread 0 runs the queue operations and
+// broadcasts the task through LDS; wavefront 0 allocates and frees frames with
+// the same pools and depot as thread mode; the body runs on all threads.
+//
+// Frames, join words and the implicit join at task return are the ones of
+// thread mode.  A task whose continuation does nothing (an FMM cell pair)
+// never runs again after its join: the completion of its last child completes
+// it in place and the completion moves on to its parent.
+//
+// Memory ordering: every cross-workgroup word is accessed device-coherently
+// and drain() waits for completion.  The owner's bottom decrement is an atomic
+// exchange performed before top is read; a thief reads top, then bottom, then
+// the slot, each after the previous access completed, and claims the slot by
+// CAS on top.
+#pragma once
+#include "fmm.h"
+#include "sched_thread.h"
+#include "tasks.h"
+
+namespace gtap {
+
+struct alignas(128) ClDeque {
+  int64_t top;      // thieves' end: only grows, advanced by CAS
+  int64_t bottom;   // owner's end
+  int64_t pad[14];
+};
+static_assert(sizeof(ClDeque) == sizeof(DequeMeta), "block deques reuse the deque lines");
+
+constexpr uint32_t kMaxBlockThreads = 256;
+constexpr uint32_t kP2PTile = 64;
+
+struct BlockLds {
+  uint32_t stk_s[kStackSmall];
+  uint32_t stk_b[kStackBig];
+  uint32_t fw[kFrameWords];     // frame of the current task
+  uint32_t task, next, next_cont, stop;
+  uint32_t out_type, nchild, ckind, pad0;
+  int64_t value;
+  uint32_t child[8][2];         // FMM children (A, B)
+  int32_t ca[fmm::kCellInts], cb[fmm::kCellInts];
+  uint32_t branch;              // FMM: 0 split, 1 M2L, 2 P2P
+  uint32_t first_fail;          // UTS: first failed draw in a batch
+  int64_t bottom, top_seen;     // owner's view of its deque
+  double T[fmm::kNc];
+  double QB[fmm::kNc];
+  double sx[kP2PTile], sy[kP2PTile], sz[kP2PTile], sq[kP2PTile];
+  double red[kMaxBlockThreads];
+};
+
+GTAP_DEV ClDeque *cl_deque(const Params &p, uint32_t w) { return reinterpret_cast<ClDeque *>(p.dq) + w; }
+GTAP_DEV uint32_t *cl_buf(const Params &p, uint32_t w) { return p.rings + static_cast<size_t>(w) * p.cap; }
+
+// Owner pop (thread 0).  Returns kNone when the deque is empty.
+GTAP_DEV uint32_t cl_pop(const Params &p, BlockLds &S, uint32_t me) {
+  const int64_t b = S.bottom - 1;
+  if (b < S.top_seen) return kNone;  // top only grows: certainly empty
+  ClDeque *d = cl_deque(p, me);
+  __hip_atomic_exchange(&d->bottom, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  drain();
+  int64_t t = static_cast<int64_t>(co_ld64(reinterpret_cast<const uint64_t *>(&d->top)));
+  S.top_seen = t;
+  if (t > b) {
+    co_st64(reinterpret_cast<uint64_t *>(&d->bottom), static_cast<uint64_t>(b + 1));
+    return kNone;
+  }
+  const uint32_t x = co_ld32(cl_buf(p, me) + (static_cast<uint64_t>(b) & (p.cap - 1)));
+  if (t == b) {
+    int64_t e = t;
+    const bool won = cas_relaxed(&d->top, &e, t + 1);
+    co_st64(reinterpret_cast<uint64_t *>(&d->bottom), static_cast<uint64_t>(b + 1));
+    S.top_seen = t + 1;
+    return won ? x : kNone;
+  }
+  S.bottom = b;
+  return x;
+}
+
+// Thief (thread 0): one task from the top of worker v's deque, or kNone.
+GTAP_DEV uint32_t cl_steal(const Params &p, uint32_t v) {
+  ClDeque *d = cl_deque(p, v);
+  int64_t t = static_cast<int64_t>(co_ld64(reinterpret_cast<const uint64_t *>(&d->top)));
+  drain();
+  const int64_t b = static_cast<int64_t>(co_ld64(reinterpret_cast<const uint64_t *>(&d->bottom)));
+  drain();
+  if (t >= b) return kNone;
+  const uint32_t x = co_ld32(cl_buf(p, v) + (static_cast<uint64_t>(t) & (p.cap - 1)));
+  drain();
+  int64_t e = t;
+  return cas_relaxed(&d->top, &e, t + 1) ? x : kNone;
+}
+
+// Publish n IDs (already written to the slots by wavefront 0) at the bottom.
+GTAP_DEV bool cl_room(const Params &p, BlockLds &S, uint32_t me, uint32_t n) {
+  if (S.bottom + n - S.top_seen <= static_cast<int64_t>(p.cap)) return true;
+  S.top_seen = static_cast<int64_t>(co_ld64(reinterpret_cast<const uint64_t *>(&cl_deque(p, me)->top)));
+  return S.bottom + n - S.top_seen <= static_cast<int64_t>(p.cap);
+}
+
+GTAP_DEV void store_result(const Params &p, uint32_t job, int64_t v) {
+  JobSlot &J = p.jobs[job];
+  st_relaxed(&J.result, v);
+  st_relaxed(&J.t_done, wall_ticks());
+  st_relaxed(&J.done, 1u);
+}
+
+// ---- FMM cell-pair body (all threads) -------------------------------------------
+// Statistics of the FMM job a workgroup works on, flushed when the job changes.
+struct FmmCounters {
+  uint32_t job;
+  uint64_t m2l, p2p, m2l_hash, p2p_hash, inter;
+};
+
+GTAP_DEV void fmm_flush(const Params &p, FmmCounters &fc) {
+  if (fc.job == kNone) return;
+  if (threadIdx.x == 0) {
+    fmm::FmmDesc *D = reinterpret_cast<fmm::FmmDesc *>(co_ld64(&p.jobs[fc.job].a[0]));
+    if (fc.m2l) fetch_add_relaxed(&D->m2l_pairs, fc.m2l);
+    if (fc.p2p) fetch_add_relaxed(&D->p2p_pairs, fc.p2p);
+    if (fc.m2l_hash) fetch_add_relaxed(&D->m2l_hash, fc.m2l_hash);
+    if (fc.p2p_hash) fetch_add_relaxed(&D->p2p_hash, fc.p2p_hash);
+    if (fc.inter) fetch_add_relaxed(&D->p2p_inter, fc.inter);
+  }
+  fc = FmmCounters{kNone, 0, 0, 0, 0, 0};
+}
+
+template <int NT>
+GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &fc) {
+  const uint32_t tx = threadIdx.x;
+  const fmm::FmmDesc *D = reinterpret_cast<const fmm::FmmDesc *>(co_ld64(&p.jobs[job].a[0]));
+  const uint32_t a = S.fw[FW_P0], b = S.fw[FW_P0 + 1];
+  if (fc.job != job) {
+    fmm_flush(p, fc);
+    fc.job = job;
+  }
+  if (tx < fmm::kCellInts) {
+    S.ca[tx] = D->cell[static_cast<size_t>(a) * fmm::kCellInts + tx];
+    S.cb[tx] = D->cell[static_cast<size_t>(b) * fmm::kCellInts + tx];
+  }
+  __syncthreads();
+  if (tx == 0) {
+    uint32_t br = 0;
+    if (fmm::mac_accept(S.ca, S.cb, D->ta, D->tb)) br = 1;
+    else if (S.ca[7] == 0 && S.cb[7] == 0) br = 2;
+    S.branch = br;
+    if (br == 0) {
+      // split the wider cell; on a tie the target unless it is a leaf; never a leaf
+      bool split_a = S.ca[0] < S.cb[0] ? true : (S.ca[0] > S.cb[0] ? false : S.ca[7] != 0);
+      if (split_a && S.ca[7] == 0) split_a = false;
+      if (!split_a && S.cb[7] == 0) split_a = true;
+      const int32_t *Sp = split_a ? S.ca : S.cb;
+      const uint32_t k = static_cast<uint32_t>(Sp[7]);
+      for (uint32_t i = 0; i < k; ++i) {
+        const uint32_t ch = static_cast<uint32_t>(Sp[6]) + i;
+        S.child[i][0] = split_a ? ch : a;
+        S.child[i][1] = split_a ? b : ch;
+      }
+      S.nchild = k;
+    }
+  }
+  __syncthreads();
+  const uint32_t br = S.branch;
+  if (br == 0) return;
+  if (br == 1) {
+    // ---- M2L(A <- B): Taylor coefficients of 1/|d + h|, degree by degree ----
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, r2 = 0.0;
+    {
+      const int32_t *A = S.ca, *B = S.cb;
+      d0 = fmm::cell_centre(A[1], A[0]) - fmm::cell_centre(B[1], B[0]);
+      d1 = fmm::cell_centre(A[2], A[0]) - fmm::cell_centre(B[2], B[0]);
+      d2 = fmm::cell_centre(A[3], A[0]) - fmm::cell_centre(B[3], B[0]);
+      r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    }
+    for (uint32_t t = tx; t < static_cast<uint32_t>(fmm::kNc); t += NT) S.QB[t] = D->Q[static_cast<size_t>(b) * fmm::kNc + t];
+    if (tx == 0) S.T[0] = 1.0 / sqrt(r2);
+    __syncthreads();
+    for (int deg = 1; deg <= fmm::kP; ++deg) {
+      const int lo = fmm::ncoef(deg - 1), hi = fmm::ncoef(deg);
+      const int t = lo + static_cast<int>(tx);
+      if (t < hi) {
+        const double dd[3] = {d0, d1, d2};
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const uint8_t m1 = fmm::kTab.dm1[t][i], m2 = fmm::kTab.dm2[t][i];
+          if (m1 != 0xFF) s1 += dd[i] * S.T[m1];
+          if (m2 != 0xFF) s2 += S.T[m2];
+        }
+        S.T[t] = -((2.0 * deg - 1.0) * s1 + (deg - 1.0) * s2) / (deg * r2);
+      }
+      __syncthreads();
+    }
+    for (uint32_t t = tx; t < static_cast<uint32_t>(fmm::kNc); t += NT) {
+      double acc = 0.0;
+      for (int m = fmm::kTab.m2l_first[t]; m < fmm::kTab.m2l_first[t + 1]; ++m)
+        acc += fmm::kTab.m2l_c[m] * S.T[fmm::kTab.m2l_g[m]] * S.QB[fmm::kTab.m2l_b[m]];
+      unsafeAtomicAdd(D->L + static_cast<size_t>(a) * fmm::kNc + t, acc);
+    }
+    fc.m2l += 1;
+    fc.m2l_hash += fmm::pair_hash(a, b);
+    return;
+  }
+  // ---- P2P(A <- B), cooperative: target = tx mod 64, source group = tx / 64 ----
+  constexpr uint32_t G = NT / kP2PTile;
+  const int32_t ab = S.ca[4], ae = S.ca[5], bb = S.cb[4], be = S.cb[5];
+  uint32_t coinc = 0;
+  for (int32_t t0 = ab; t0 < ae; t0 += kP2PTile) {
+    const int32_t i = t0 + static_cast<int32_t>(tx % kP2PTile);
+    const bool live = i < ae;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    if (live) {
+      xi = D->px[i];
+      yi = D->py[i];
+      zi = D->pz[i];
+    }
+    double acc = 0.0;
+    for (int32_t s0 = bb; s0 < be; s0 += kP2PTile) {
+      const int32_t ns = min(static_cast<int32_t>(kP2PTile), be - s0);
+      __syncthreads();
+      if (tx < static_cast<uint32_t>(ns)) {
+        S.sx[tx] = D->px[s0 + tx];
+        S.sy[tx] = D->py[s0 + tx];
+        S.sz[tx] = D->pz[s0 + tx];
+        S.sq[tx] = D->pq[s0 + tx];
+      }
+      __syncthreads();
+      if (live)
+        for (int32_t j = static_cast<int32_t>(tx / kP2PTile); j < ns; j += G) {
+          if (s0 + j == i) continue;
+          const double dx = xi - S.sx[j], dy = yi - S.sy[j], dz = zi - S.sz[j];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0) {
+            ++coinc;
+            continue;
+          }
+          acc += S.sq[j] / sqrt(r2);
+        }
+    }
+    __syncthreads();
+    S.red[tx] = acc;
+    __syncthreads();
+    if (tx < kP2PTile && live) {
+      double s = 0.0;
+#pragma unroll
+      for (uint32_t g = 0; g < G; ++g) s += S.red[tx + g * kP2PTile];
+      unsafeAtomicAdd(D->phi + i, s);
+    }
+  }
+  if (coinc) atomicAdd(reinterpret_cast<unsigned long long *>(const_cast<uint64_t *>(&D->coincident)),
+                       static_cast<unsigned long long>(coinc));
+  if (tx == 0) {
+    const int64_t na = ae - ab, nb = be - bb;
+    fc.p2p += 1;
+    fc.p2p_hash += fmm::pair_hash(a, b);
+    fc.inter += static_cast<uint64_t>(na * nb - (a == b ? na : 0));
+  }
+}
+
+// Root frame of job j in block mode.
+GTAP_DEV void write_root_block(const Params &p, uint32_t id, uint32_t j) {
+  const uint32_t jkind = static_cast<uint32_t>(co_ld64(reinterpret_cast<const uint64_t *>(p.jobs + j)));
+  if (jkind == 5) {  // FMM: the (root, root) cell pair
+    ChildInit c{};
+    write_frame(frame_ptr(p, id), kNone, j, state_word(TK_FMM, 0, 0), c);
+  } else {
+    write_root(p, id, j);
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
+  static_assert(NT % kWave == 0 && NT <= static_cast<int>(kMaxBlockThreads), "workgroup shape");
+  __shared__ BlockLds S;
+  const uint32_t tx = threadIdx.x, ln = tx & 63u, wv = tx >> 6;
+  const uint32_t me = blockIdx.x;
+  const uint32_t nw = gridDim.x;
+  const uint64_t deadline = wall_ticks() + p.timeout_ticks;
+  PoolView PS{S.stk_s, 0, 0, 0, kStackSmall, kChunkSmall, p.bins_s, p.store_s,
+              p.bincap_s, &p.ctl->bump_small, p.nframes_s, 0u, 0};
+  PoolView PB{S.stk_b, 0, 0, 0, kStackBig, kChunkBig, p.bins_b, p.store_b,
+              p.bincap_b, &p.ctl->bump_big, p.nframes_b, kBigBit, 1};
+  WaveCounters wc;
+  for (int i = 0; i < static_cast<int>(ST_COUNT); ++i) wc.v[i] = 0;
+  FmmCounters fc{kNone, 0, 0, 0, 0, 0};
+  uint32_t rng = 0x9E3779B9u ^ (me * 0x85EBCA6Bu + 1u);
+  uint64_t t_loop = clock64(), busy_cycles = 0, idle_cycles = 0;
+  if (tx == 0) {
+    S.bottom = 0;
+    S.top_seen = 0;
+    S.stop = 0;
+  }
+  __syncthreads();
+
+  // roots: job j goes to worker j mod nw, onto its deque
+  if (wv == 0) {
+    const uint32_t nroots = me < p.njobs ? (p.njobs - me + nw - 1) / nw : 0u;
+    AllocResult ar{};
+    if (nroots > p.cap) {
+      if (ln == 0) raise_error(p, -6 /*GTAP_E_CAPACITY*/, 2, p.cap, nroots, me, -1);
+    } else if (nroots > 0 && alloc_frames(p, PS, me, nroots, ar, wc)) {
+      wave_sync();
+      for (uint32_t g = ln; g < nroots; g += kWave) {
+        const uint32_t id = alloc_id(PS, ar, g);
+        write_root_block(p, id, me + g * nw);
+        co_st32(cl_buf(p, me) + g, id);
+      }
+      drain();
+      if (ln == 0) {
+        co_st64(reinterpret_cast<uint64_t *>(&cl_deque(p, me)->bottom), nroots);
+        S.bottom = nroots;
+      }
+    }
+  }
+  __syncthreads();
+
+  uint32_t tid = kNone, cont = 0, idle = 0, iter = 0;
+  for (;;) {
+    // ---- acquire: own deque, then random victims ----
+    if (tid == kNone) {
+      if (tx == 0) {
+        uint32_t t = cl_pop(p, S, me);
+        if (t != kNone) {
+          wc.add(ST_POPPED, 1);
+        } else if (nw > 1) {
+          wc.add(ST_STEAL_ATTEMPTS, 1);
+          for (uint32_t k = 0; k < p.steal_probes && t == kNone; ++k) {
+            uint32_t v = xorshift32(rng) % (nw - 1);
+            if (v >= me) ++v;
+            t = cl_steal(p, v);
+          }
+          if (t != kNone) wc.add(ST_STOLEN, 1);
+        }
+        S.task = t;
+        S.next_cont = 0;
+        uint32_t stop = 0;
+        if (t == kNone && (idle & 3u) == 0u) {
+          if (ld_relaxed(&p.ctl->jobs_remaining) <= 0 || ld_relaxed(&p.ctl->error) != 0) stop = 1;
+          else if (wall_ticks() > deadline) {
+            raise_error(p, -8 /*GTAP_E_TIMEOUT*/, 3, p.timeout_ticks, 0, me, -1);
+            stop = 1;
+          }
+        }
+        S.stop = stop;
+      }
+      __syncthreads();
+      tid = S.task;
+      cont = 0;
+      if (S.stop) break;
+      if (tid == kNone) {
+        ++idle;
+        wc.add(ST_IDLE, 1);
+        backoff_sleep(idle);
+        const uint64_t now = clock64();
+        idle_cycles += now - t_loop;
+        t_loop = now;
+        __syncthreads();
+        continue;
+      }
+    }
+    idle = 0;
+    ++iter;
+    wc.add(ST_ITERS, 1);
+    if ((iter & 63u) == 0) {
+      if (tx == 0) {
+        uint32_t stop = 0;
+        if (ld_relaxed(&p.ctl->error) != 0) stop = 1;
+        else if (wall_ticks() > deadline) {
+          raise_error(p, -8 /*GTAP_E_TIMEOUT*/, 3, p.timeout_ticks, 0, me, -1);
+          stop = 1;
+        }
+        S.stop = stop;
+      }
+      __syncthreads();
+      if (S.stop) break;
+    }
+
+    // ---- load the frame ----
+    if (tx < kFrameWords) S.fw[tx] = co_ld32(frame_ptr(p, tid) + tx);
+    if (tx == 0) {
+      S.out_type = OUT_DONE;
+      S.nchild = 0;
+      S.value = 0;
+    }
+    __syncthreads();
+    const uint32_t kind = S.fw[FW_STATE] & 0xFFu;
+    const uint32_t job = S.fw[FW_JOB];
+    if (cont) wc.add(ST_CONTS, 1);
+    else wc.add(ST_TASKS, 1);
+
+    // ---- body ----
+    if (cont) {
+      if (tx == 0) {
+        const int64_t jw = static_cast<int64_t>(pack(S.fw[FW_JOIN], S.fw[FW_JOIN + 1]));
+        const int64_t big = static_cast<int64_t>(pack(S.fw[FW_BIGACC], S.fw[FW_BIGACC + 1]));
+        S.value = (jw >> kJoinBits) + big + (kind == TK_UTS ? 1 : 0);
+      }
+    } else if (kind == TK_FIB) {
+      if (tx == 0) {
+        const uint32_t n = S.fw[FW_P0];
+        if (n < 2) {
+          S.value = n;
+        } else {
+          S.out_type = OUT_FORK;
+          S.nchild = 2;
+        }
+      }
+    } else if (kind == TK_UTS) {
+      // cooperative geometric draw: the child count is the index of the first
+      // failed draw j = 1, 2, ...
+      const uint64_t id = pack(S.fw[FW_P0], S.fw[FW_P0 + 1]);
+      const uint32_t dm = S.fw[FW_P0 + 2];
+      const uint64_t thr = pack(S.fw[FW_P0 + 3], S.fw[FW_P0 + 4]);
+      if ((dm & 0xFFFFu) < (dm >> 16)) {
+        uint32_t base = 0;
+        for (;;) {
+          if (tx == 0) S.first_fail = kNone;
+          __syncthreads();
+          const uint64_t j = base + tx + 1;
+          if (!(mix64(id ^ (j * 0xD1B54A32D192ED03ull)) < thr)) atomicMin(&S.first_fail, base + tx);
+          __syncthreads();
+          const uint32_t ff = S.first_fail;
+          __syncthreads();
+          if (ff != kNone) {
+            if (tx == 0 && ff > 0) {
+              S.out_type = OUT_FORK;
+              S.nchild = ff;
+            }
+            break;
+          }
+          base += NT;
+        }
+      }
+      if (tx == 0 && S.out_type == OUT_DONE) S.value = 1;
+    } else if (kind == TK_FMM) {
+      fmm_pair<NT>(p, S, job, fc);
+      if (tx == 0 && S.branch == 0) {
+        S.out_type = OUT_FORK;
+        // nchild set by the body
+      }
+    }
+    __syncthreads();
+
+    // ---- fork or complete (wavefront 0) ----
+    if (wv == 0) {
+      const uint32_t out = S.out_type;
+      uint32_t next = kNone, next_cont = 0;
+      if (out == OUT_FORK) {
+        const uint32_t nc = S.nchild;
+        if (nc > kMaxChildren) {
+          if (ln == 0) raise_error(p, -6 /*GTAP_E_CAPACITY*/, 4, kMaxChildren, nc, me, static_cast<int32_t>(job));
+        } else {
+          uint32_t *f = frame_ptr(p, tid);
+          if (ln == 0) {
+            co_st64(reinterpret_cast<uint64_t *>(f + FW_JOIN), static_cast<uint64_t>(nc));
+            co_st64(reinterpret_cast<uint64_t *>(f + FW_BIGACC), 0ull);
+          }
+          // children 1..nc-1 go to the deque, child 0 runs next
+          bool ok = true;
+          if (ln == 0) ok = cl_room(p, S, me, nc - 1);
+          ok = uniform(static_cast<uint32_t>(ok)) != 0;
+          if (!ok) {
+            if (ln == 0) raise_error(p, -6 /*GTAP_E_CAPACITY*/, 2, p.cap, nc, me, static_cast<int32_t>(job));
+          } else {
+            const uint32_t ckind = kind;
+            const uint32_t state = state_word(ckind, 0, 0);
+            const int64_t bot = S.bottom;
+            uint32_t first = kNone;
+            for (uint32_t done = 0; done < nc && ok; done += kWave) {
+              const uint32_t chunk = (nc - done) < kWave ? (nc - done) : kWave;
+              AllocResult ar{};
+              if (!alloc_frames(p, PS, me, chunk, ar, wc)) {
+                ok = false;
+                break;
+              }
+              wave_sync();
+              uint32_t cid = kNone;
+              if (ln < chunk) {
+                const uint32_t g = done + ln;
+                cid = alloc_id(PS, ar, ln);
+                ChildInit ci{};
+                if (ckind == TK_FIB) {
+                  ci.p[0] = S.fw[FW_P0] - 1 - g;
+                } else if (ckind == TK_UTS) {
+                  const uint64_t cidv = split_id(pack(S.fw[FW_P0], S.fw[FW_P0 + 1]), g);
+                  ci.p[0] = static_cast<uint32_t>(cidv);
+                  ci.p[1] = static_cast<uint32_t>(cidv >> 32);
+                  ci.p[2] = S.fw[FW_P0 + 2] + 1;
+                  ci.p[3] = S.fw[FW_P0 + 3];
+                  ci.p[4] = S.fw[FW_P0 + 4];
+                } else {
+                  ci.p[0] = S.child[g][0];
+                  ci.p[1] = S.child[g][1];
+                }
+                write_frame(frame_ptr(p, cid), tid, job, state, ci);
+                // child 0 runs next on this workgroup, the others go to the deque
+                if (g > 0) co_st32(cl_buf(p, me) + (static_cast<uint64_t>(bot + g - 1) & (p.cap - 1)), cid);
+              }
+              if (done == 0) first = uniform(static_cast<uint32_t>(__shfl(static_cast<int>(cid), 0, 64)));
+            }
+            if (ok) {
+              drain();  // frames and slots complete before the deque grows
+              if (ln == 0 && nc > 1) {
+                co_st64(reinterpret_cast<uint64_t *>(&cl_deque(p, me)->bottom), static_cast<uint64_t>(bot + nc - 1));
+                S.bottom = bot + nc - 1;
+              }
+              next = first;
+              wc.add(ST_SPAWNS, nc);
+              wc.add(ST_PUSHED, nc - 1);
+            }
+          }
+        }
+      } else {
+        // completion; an empty continuation completes the parent in place
+        const bool empty_cont = (kind == TK_FMM);
+        uint32_t cur = tid;
+        uint32_t par = S.fw[FW_PARENT];
+        int64_t val = S.value;
+        for (;;) {
+          free_frames((cur & kBigBit) ? PB : PS, me, ln == 0, cur, wc);
+          if (par == kNone) {
+            if (ln == 0) {
+              store_result(p, job, val);
+              drain();
+              fetch_add_relaxed(&p.ctl->jobs_remaining, -1);
+            }
+            break;
+          }
+          uint32_t resumed = 0, gp = kNone;
+          if (ln == 0) {
+            uint32_t *pf = frame_ptr(p, par);
+            const int64_t lim = static_cast<int64_t>(1) << kSmallValueBits;
+            int64_t delta = -1;
+            if (val >= lim || val <= -lim) {
+              fetch_add_relaxed(bigacc_ptr(pf), val);
+              drain();
+            } else {
+              delta = val * (static_cast<int64_t>(1) << kJoinBits) - 1;
+            }
+            const int64_t old = fetch_add_relaxed(join_ptr(pf), delta);
+            if ((static_cast<uint64_t>(old) & kJoinMask) == 1u) {
+              resumed = 1;
+              if (empty_cont) gp = co_ld32(pf + FW_PARENT);
+            }
+          }
+          resumed = uniform(resumed);
+          if (!resumed) break;
+          if (!empty_cont) {
+            next = par;
+            next_cont = 1;
+            break;
+          }
+          gp = uniform(gp);
+          cur = par;
+          par = gp;
+          val = 0;
+          wc.add(ST_CONTS, 1);
+        }
+      }
+      if (ln == 0) {
+        S.next = next;
+        S.next_cont = next_cont;
+      }
+    }
+    __syncthreads();
+    tid = S.next;
+    cont = S.next_cont;
+    const uint64_t now = clock64();
+    busy_cycles += now - t_loop;
+    t_loop = now;
+  }
+
+  fmm_flush(p, fc);
+  if (tx == 0) {
+    for (int i = 0; i < static_cast<int>(ST_COUNT); ++i)
+      if (wc.v[i]) fetch_add_relaxed(&p.ctl->stats[i], static_cast<uint64_t>(wc.v[i]));
+    if (busy_cycles) fetch_add_relaxed(&p.ctl->stats[ST_BUSY_CYCLES], busy_cycles);
+    if (idle_cycles) fetch_add_relaxed(&p.ctl->stats[ST_IDLE_CYCLES], idle_cycles);
+  }
+}
+
+}  // namespace gtap

@@ -402,13 +402,19 @@ GTAP_DEV uint32_t steal_batch(const Params &p, uint32_t me, uint32_t &rng, uint3
   return static_cast<uint32_t>(claim);
 }
 
-// The owner's fullest deque (DAQ: a wavefront with no tasks starts a batch from
-// it); kNone if every hint says empty.
+// The own deque a wavefront with no tasks starts its next batch from (DAQ):
+// the lowest class that can fill a whole wavefront, else the fullest one;
+// kNone if every hint says empty.  Low classes hold the tasks nearest to the
+// leaves (k-clique: the smallest candidate sets), so draining them first
+// keeps the number of live frames close to that of a depth-first order.
 GTAP_DEV uint32_t fullest_own_queue(const Params &p, const WaveLds &L, uint32_t me) {
   const uint32_t ln = lane_id();
   int32_t c = 0;
   if (ln < p.Q && L.hint[ln]) c = ld_relaxed(&deque_meta(p, me, ln)->count);
-  uint32_t key = c > 0 ? ((static_cast<uint32_t>(c < (1 << 24) ? c : (1 << 24) - 1) << 6) | ln) : 0u;
+  uint32_t rank = 0;
+  if (c >= static_cast<int32_t>(kWave)) rank = (1u << 23) + (kMaxQueues - ln);
+  else if (c > 0) rank = static_cast<uint32_t>(c);
+  uint32_t key = rank ? ((rank << 6) | ln) : 0u;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
     const uint32_t other = __shfl_xor(key, d, 64);

@@ -38,6 +38,7 @@ GTAP_KIND_FIB = 1
 GTAP_KIND_NQUEENS = 2
 GTAP_KIND_UTS = 3
 GTAP_KIND_KCLIQUE = 4
+GTAP_KIND_FMM = 5
 
 GTAP_DAQ_NONE = 0
 GTAP_DAQ_BY_KIND = 1
@@ -85,6 +86,23 @@ class gtap_kclique_args(ctypes.Structure):
     _fields_ = [("row_ptr_dev", ctypes.c_void_p), ("col_dev", ctypes.c_void_p),
                 ("n", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("range_leaf", ctypes.c_int32), ("max_outdeg", ctypes.c_int32)]
+
+
+class gtap_fmm_args(ctypes.Structure):
+    _fields_ = [("x_dev", ctypes.c_void_p), ("y_dev", ctypes.c_void_p), ("z_dev", ctypes.c_void_p),
+                ("q_dev", ctypes.c_void_p), ("phi_dev", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("leaf_max", ctypes.c_int32), ("theta_num", ctypes.c_int32), ("theta_den", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class gtap_fmm_result(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("n_cells", "n_leaves", "max_level", "m2l_pairs", "p2p_pairs")] + \
+               [("m2l_hash", ctypes.c_uint64), ("p2p_hash", ctypes.c_uint64),
+                ("p2p_interactions", ctypes.c_int64), ("coincident", ctypes.c_int64)] + \
+               [(f, ctypes.c_double) for f in ("tree_ms", "upward_ms", "traversal_ms", "downward_ms")]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class gtap_stats(ctypes.Structure):
@@ -350,6 +368,27 @@ class Runtime:
         return gtap_submit(self.ctx, GTAP_KIND_KCLIQUE,
                            gtap_kclique_args(rp.data_ptr(), cl.data_ptr(), n, int(k),
                                              int(range_leaf), int(max_outdeg)))
+
+    def submit_fmm(self, x, y, z, q, phi, leaf_max: int = 64, theta=(1, 2), order: int = 6) -> int:
+        """FMM job (block mode): x, y, z, q, phi are float64 CUDA tensors of n
+        entries, kept alive until run() returns; phi receives the potentials."""
+        torch = self._torch
+        ts = [t.to(device="cuda", dtype=torch.float64).contiguous() for t in (x, y, z, q)]
+        if not (phi.is_cuda and phi.dtype == torch.float64 and phi.is_contiguous()):
+            raise ValueError("phi must be a contiguous float64 CUDA tensor")
+        n = ts[0].numel()
+        self._keep.append((*ts, phi))
+        return gtap_submit(self.ctx, GTAP_KIND_FMM,
+                           gtap_fmm_args(ts[0].data_ptr(), ts[1].data_ptr(), ts[2].data_ptr(), ts[3].data_ptr(),
+                                         phi.data_ptr(), n, int(leaf_max), int(theta[0]), int(theta[1]),
+                                         int(order), 0))
+
+    def fmm_result(self, job_id: int) -> dict:
+        r = gtap_fmm_result()
+        rc = _lib.gtap_result(self.ctx, job_id, ctypes.byref(r), ctypes.sizeof(r))
+        if rc != GTAP_OK:
+            raise GtapError(rc, "gtap_result")
+        return r.as_dict()
 
     # -- argument structs (for traces and serving) ----------------------------
     @staticmethod

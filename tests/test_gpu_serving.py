@@ -69,7 +69,7 @@ def mixed_entries(rt, gtap, graph, n, seed, spacing_s=0.0):
 def make_rt(gtap, **kw):
     kw.setdefault("timeout_ms", 60000)
     kw.setdefault("small_frames", 1 << 22)
-    kw.setdefault("big_frames", 1 << 18)
+    kw.setdefault("big_frames", 1 << 20)
     kw.setdefault("big_frame_ints", 512)
     kw.setdefault("max_jobs", 256)
     return gtap.Runtime(**kw)
