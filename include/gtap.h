@@ -93,7 +93,7 @@ typedef struct {
 } gtap_kclique_args;
 
 /* 3D Laplace FMM whose interaction phase is a dual-tree traversal run as
- * block-mode tasks (Sec. 6.5.1, "FMM Dual-Tree Traversal").  The library builds
+ * block-mode tasks (Sec. 6.4.1, "FMM Dual-Tree Traversal").  The library builds
  * an octree over the n points (root cube [-128, 128)^3; a cell with more than
  * leaf_max points below level 21 splits into its non-empty octants), computes
  * multipole moments (P2M, M2M), runs the traversal from the (root, root) cell

@@ -126,7 +126,7 @@ def kclique(row_ptr, col, k: int, range_leaf: int = 64) -> OracleResult:
     return _res(v, c)
 
 
-# ---- FMM (GTaP Sec. 6.5.1) -------------------------------------------------
+# ---- FMM (GTaP Sec. 6.4.1) -------------------------------------------------
 class _FmmStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("n_cells", "n_leaves", "max_level", "m2l_pairs", "p2p_pairs")] + \
                [("m2l_hash", ctypes.c_uint64), ("p2p_hash", ctypes.c_uint64),

@@ -1,6 +1,6 @@
 /*
  * fmm.c -- plain, sequential CPU oracle of the 3D Laplace FMM pipeline with a
- * dual-tree traversal (GTaP Sec. 6.5.1, "FMM Dual-Tree Traversal": adaptive
+ * dual-tree traversal (GTaP Sec. 6.4.1, "FMM Dual-Tree Traversal": adaptive
  * octree, upward pass, DTT over cell pairs with a multipole acceptance
  * criterion, M2L, P2P and L2P).
  *

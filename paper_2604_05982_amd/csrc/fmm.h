@@ -1,6 +1,6 @@
 // fmm.h -- 3D Laplace FMM for block mode: octree construction, upward and
 // downward passes as data-parallel kernels, and the cell-pair work that the
-// dual-tree traversal tasks run (GTaP Sec. 6.5.1).
+// dual-tree traversal tasks run (GTaP Sec. 6.4.1).
 //
 // Conventions (the paper names the phases only):
 //   * root cube [-2^7, 2^7)^3; grid coordinate floor((x + 2^7) * 2^13) in
