@@ -218,14 +218,21 @@ def bench_serving(args, gtap) -> int:
     t0 = time.perf_counter()
     g = graphs.chung_lu(1000000, 40, 2.1, 0.6, 2)
     say(f"graph ready {time.perf_counter() - t0:.1f}s max_outdeg={g.max_outdeg}")
-    rt = gtap.Runtime(num_waves=args.num_waves, waves_per_group=args.waves_per_group, max_jobs=1 << 15,
-                      small_frames=1 << 26, big_frames=1 << 22, big_frame_ints=max(320, g.max_outdeg),
-                      deque_capacity=1 << 18, timeout_ms=300000)
-    headroom = 1 << 25
+    common = dict(max_jobs=1 << 15, big_frame_ints=max(320, g.max_outdeg), deque_capacity=1 << 18,
+                  timeout_ms=300000)
+    base = gtap.Runtime(num_waves=args.num_waves, waves_per_group=args.waves_per_group, small_frames=1 << 26,
+                        big_frames=1 << 22, **common)
+    # calibration trace (its own seed): the autotuner's jobs and the open-loop rate
+    _, cal_entries, _, cal_keep, _, _ = serving_trace(gtap, base, g, max(1, args.jobs // 4), 6, torch)
+    tune_jobs = base.trace([(0.0, e) for e in cal_entries[: args.calib_jobs]])
+    space = gtap.tune_space(num_queues=(1, 2, 4), waves_per_group=(4,), num_waves=(1024, 0),
+                            daq_policy=gtap.GTAP_DAQ_BY_KIND, repeats=1)
+    tuned, tune_rep = base.autotune(tune_jobs, space)
+    base.close()
+    say(f"autotuned {tuned} {tune_rep}")
+    rt = gtap.Runtime(**tuned, **common)
+    headroom = int(tuned["small_frames"]) // 4
     specs, entries, classes, keep, subs, staged = serving_trace(gtap, rt, g, args.jobs, 5, torch)
-    n = len(entries)
-    say(f"trace ready {time.perf_counter() - t0:.1f}s {staged}")
-
     def served(arrivals):
         jobs = rt.trace([(t, e) for t, e in zip(arrivals, entries)])
         rt.serve_start(max_inflight=args.inflight, headroom_small=headroom)
@@ -254,7 +261,6 @@ def bench_serving(args, gtap) -> int:
     alone_eq_mix = r_b == r_p and r_s == r_p
 
     # calibration on another trace seed: saturated served throughput
-    cal_specs, cal_entries, _, cal_keep, _, _ = serving_trace(gtap, rt, g, max(1, args.jobs // 4), 6, torch)
     cal_jobs = rt.trace([(0.0, e) for e in cal_entries])
     rt.serve_start(max_inflight=args.inflight, headroom_small=headroom)
     cal_res = rt.trace_run(cal_jobs, timeout_ms=280000)
@@ -286,7 +292,7 @@ def bench_serving(args, gtap) -> int:
            "config": {"workload": f"{n} jobs, trace seed 5: 60% k-clique (k 4..8, induced subgraphs of "
                                   "log-uniform 1e3..2e5 vertices of the n=1e6 Chung-Lu graph), 40% UTS "
                                   "(m 2..4, depth 8..14)", **staged, "max_inflight": args.inflight,
-                      "waves": st_batch["num_waves"]},
+                      "waves": st_batch["num_waves"], "autotuned": tuned, "autotune_report": tune_rep},
            "saturated_jobs_per_s": {"batch_launch": n / batch_s, "served": n / served_s, "plain": n / plain_s},
            "saturated_tasks_per_s_batch": st_batch["tasks"] / batch_s,
            "batch_kernel_ms": st_batch["kernel_ms"], "tasks_total": st_batch["tasks"],
@@ -414,6 +420,7 @@ def main() -> int:
                          "serving: batched / served job mix against one launch per job")
     ap.add_argument("--jobs", type=int, default=20000, help="serving: jobs in the trace")
     ap.add_argument("--inflight", type=int, default=1024, help="serving: admission limit")
+    ap.add_argument("--calib-jobs", type=int, default=400, help="serving: autotuner calibration jobs")
     ap.add_argument("--sweep", action="store_true", help="serving: also rho 0.3/0.5/0.7/0.9")
     ap.add_argument("--queues", type=int, default=1, help="kclique7: DAQ queues (1 = off)")
     args = ap.parse_args()

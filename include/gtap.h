@@ -330,6 +330,44 @@ int gtap_stats_get(gtap_ctx *ctx, gtap_stats *out);
 int gtap_last_error(gtap_ctx *ctx, gtap_error_report *out);
 const char *gtap_status_string(int32_t status);
 
+/* ---- batching: configuration autotuner ---------------------------------------- */
+/* Not in the paper (its configuration is chosen by hand).  Candidate values,
+ * each list terminated by 0 (or by its length).  Every combination of
+ * num_queues x (daq_bounds sets, for num_queues > 1) x waves_per_group x
+ * num_waves is tried on the calibration jobs. */
+typedef struct {
+    int32_t num_queues[4];       /* 1 = DAQ off                                 */
+    int32_t daq_policy;          /* policy used when num_queues > 1             */
+    int32_t waves_per_group[4];
+    int32_t num_waves[4];        /* a negative entry means 0 (occupancy maximum) */
+    int32_t bounds_sets;         /* daq_bounds candidates in bounds[] (0..4)    */
+    int32_t bounds[4][7];
+    uint32_t repeats;            /* timed runs per candidate, the best counts (>= 1) */
+    uint32_t reserved;
+} gtap_tune_space;
+
+typedef struct {
+    int32_t candidates;          /* configurations tried                        */
+    int32_t failed;              /* of those, aborted after pool growth         */
+    double best_ms;              /* best wall time of the calibration batch     */
+    double base_ms;              /* the same for the base configuration         */
+    uint64_t small_frames_touched;  /* frame high-water of the best run        */
+    uint64_t big_frames_touched;
+} gtap_tune_report;
+
+/* Run the calibration jobs (one batch, one gtap_run per timed repeat after an
+ * untimed warm-up) under every candidate configuration derived from *base and
+ * write the fastest to *best.  A candidate that exhausts a frame pool is
+ * retried with that pool doubled, up to three times.  The chosen
+ * configuration's frame pools are then sized to max(4 x the frames the best
+ * run touched, 2^20), capped at the base sizes.  Contexts are created and
+ * finalized internally (library-owned workspaces; base->workspace_dev is
+ * ignored).  n <= base->max_jobs.  k-clique job buffers are borrowed for the
+ * duration of the call.  Errors: GTAP_E_INVAL, or the base configuration's
+ * own failure. */
+int gtap_autotune(const gtap_config *base, const gtap_trace_job *calib, size_t n,
+                  const gtap_tune_space *space, gtap_config *best, gtap_tune_report *report);
+
 #ifdef __cplusplus
 }
 #endif

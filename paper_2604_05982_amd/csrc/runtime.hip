@@ -909,6 +909,112 @@ int gtap_trace_run_plain(gtap_ctx *c, const gtap_trace_job *jobs, size_t n, gtap
   return GTAP_OK;
 }
 
+// ---- autotuner ------------------------------------------------------------------
+// Best wall time (ms) of `repeats` timed batches of the calibration jobs under
+// cfg; pools grow on exhaustion.  Returns GTAP_OK or the last failure.
+static int tune_candidate(gtap_config &cfg, const gtap_trace_job *jobs, size_t n, uint32_t repeats,
+                          double *best_ms, gtap_stats *st) {
+  int rc = GTAP_OK;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    gtap_ctx *c = nullptr;
+    rc = gtap_init(&cfg, &c);
+    if (rc != GTAP_OK) return rc;
+    double best = 1e300;
+    for (uint32_t r = 0; r <= repeats && rc == GTAP_OK; ++r) {
+      for (size_t i = 0; i < n && rc == GTAP_OK; ++i) {
+        uint64_t id = 0;
+        rc = gtap_submit(c, jobs[i].kind, jobs[i].args, jobs[i].args_bytes, &id);
+      }
+      if (rc != GTAP_OK) break;
+      const double t0 = host_seconds();
+      rc = gtap_run(c);
+      const double t1 = host_seconds();
+      if (rc == GTAP_OK && r > 0) best = std::min(best, 1e3 * (t1 - t0));
+    }
+    const gtap_error_report err = c->err;
+    if (st) *st = c->stats;
+    gtap_finalize(c);
+    if (rc == GTAP_OK) {
+      *best_ms = best;
+      return GTAP_OK;
+    }
+    if (rc != GTAP_E_CAPACITY || (err.pool != 0 && err.pool != 1)) return rc;
+    if (err.pool == 0) cfg.small_frames = std::min<uint64_t>(cfg.small_frames * 2, (1ull << 31) - 1);
+    else cfg.big_frames = std::min<uint64_t>(std::max<uint64_t>(cfg.big_frames * 2, 1024), (1ull << 31) - 1);
+  }
+  return rc;
+}
+
+int gtap_autotune(const gtap_config *base, const gtap_trace_job *calib, size_t n, const gtap_tune_space *space,
+                  gtap_config *best, gtap_tune_report *report) {
+  if (!base || !calib || !space || !best || n == 0 || n > base->max_jobs) return GTAP_E_INVAL;
+  for (size_t i = 0; i < n; ++i)
+    if (calib[i].args_bytes > sizeof(calib[i].args)) return GTAP_E_INVAL;
+  const uint32_t repeats = std::max<uint32_t>(space->repeats, 1);
+  gtap_tune_report rep{};
+  gtap_config b = *base;
+  b.workspace_dev = nullptr;
+  b.workspace_bytes = 0;
+  gtap_stats st{};
+  double base_ms = 0.0;
+  int rc = tune_candidate(b, calib, n, repeats, &base_ms, &st);
+  if (rc != GTAP_OK) return rc;
+  rep.candidates = 1;
+  rep.base_ms = base_ms;
+  gtap_config win = b;
+  double win_ms = base_ms;
+  gtap_stats win_st = st;
+  auto list = [](const int32_t *v, int32_t dflt) {
+    std::vector<int32_t> out;
+    for (int i = 0; i < 4 && v[i] != 0; ++i) out.push_back(v[i]);
+    if (out.empty()) out.push_back(dflt);
+    return out;
+  };
+  for (int32_t q : list(space->num_queues, b.num_queues)) {
+    const int nb = (q > 1 && space->bounds_sets > 0) ? std::min(space->bounds_sets, 4) : 1;
+    for (int bi = 0; bi < nb; ++bi)
+      for (int32_t wpg : list(space->waves_per_group, b.waves_per_group))
+        for (int32_t nw : list(space->num_waves, b.num_waves)) {
+          gtap_config cand = b;
+          cand.num_queues = q;
+          cand.daq_policy = q > 1 ? space->daq_policy : GTAP_DAQ_NONE;
+          if (q > 1 && space->bounds_sets > 0) std::memcpy(cand.daq_bounds, space->bounds[bi], sizeof(cand.daq_bounds));
+          cand.waves_per_group = wpg;
+          cand.num_waves = nw < 0 ? 0 : nw;
+          double ms = 0.0;
+          ++rep.candidates;
+          if (validate(cand) != GTAP_OK ||
+              tune_candidate(cand, calib, n, repeats, &ms, &st) != GTAP_OK) {
+            ++rep.failed;
+            continue;
+          }
+          if (ms < win_ms) {
+            win_ms = ms;
+            win = cand;
+            win_st = st;
+          }
+        }
+  }
+  // frame pools: four times what the best run touched, at least 2^20, at most the base sizes
+  auto size_pool = [](uint64_t touched, uint64_t cap) {
+    uint64_t v = std::max<uint64_t>(4 * touched, 1ull << 20);
+    uint64_t p2 = 1;
+    while (p2 < v) p2 <<= 1;
+    return std::min<uint64_t>(p2, cap);
+  };
+  win.small_frames = size_pool(win_st.small_frames_touched, std::max(win.small_frames, b.small_frames));
+  if (win.big_frames > 0) win.big_frames = size_pool(win_st.big_frames_touched, std::max(win.big_frames, b.big_frames));
+  win.workspace_dev = base->workspace_dev;
+  win.workspace_bytes = base->workspace_bytes;
+  win.stream = base->stream;
+  rep.best_ms = win_ms;
+  rep.small_frames_touched = win_st.small_frames_touched;
+  rep.big_frames_touched = win_st.big_frames_touched;
+  *best = win;
+  if (report) *report = rep;
+  return GTAP_OK;
+}
+
 int gtap_result(gtap_ctx *c, uint64_t job_id, void *out, size_t out_bytes) {
   if (!c || !out || out_bytes < sizeof(int64_t)) return GTAP_E_INVAL;
   if (c->have_done && job_id >= c->done_first && job_id < c->done_first + c->done_jobs.size()) {

@@ -132,6 +132,19 @@ class gtap_trace_result(ctypes.Structure):
                 ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class gtap_tune_space(ctypes.Structure):
+    _fields_ = [("num_queues", ctypes.c_int32 * 4), ("daq_policy", ctypes.c_int32),
+                ("waves_per_group", ctypes.c_int32 * 4), ("num_waves", ctypes.c_int32 * 4),
+                ("bounds_sets", ctypes.c_int32), ("bounds", (ctypes.c_int32 * 7) * 4),
+                ("repeats", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class gtap_tune_report(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("failed", ctypes.c_int32), ("best_ms", ctypes.c_double),
+                ("base_ms", ctypes.c_double), ("small_frames_touched", ctypes.c_uint64),
+                ("big_frames_touched", ctypes.c_uint64)]
+
+
 class gtap_error_report(ctypes.Structure):
     _fields_ = [("code", ctypes.c_int32), ("pool", ctypes.c_int32),
                 ("capacity", ctypes.c_uint64), ("requested", ctypes.c_uint64),
@@ -169,10 +182,12 @@ def _load() -> ctypes.CDLL:
     lib.gtap_serve_stop.argtypes = [vp, u32]
     lib.gtap_trace_run.argtypes = [vp, P(gtap_trace_job), ctypes.c_size_t, P(gtap_trace_result), u32]
     lib.gtap_trace_run_plain.argtypes = [vp, P(gtap_trace_job), ctypes.c_size_t, P(gtap_trace_result)]
+    lib.gtap_autotune.argtypes = [P(gtap_config), P(gtap_trace_job), ctypes.c_size_t, P(gtap_tune_space),
+                                  P(gtap_config), P(gtap_tune_report)]
     for fn in ("gtap_workspace_size", "gtap_init", "gtap_submit", "gtap_run", "gtap_result",
                "gtap_finalize", "gtap_stats_get", "gtap_last_error", "gtap_serve_start",
                "gtap_serve_submit", "gtap_serve_poll", "gtap_serve_stop", "gtap_trace_run",
-               "gtap_trace_run_plain"):
+               "gtap_trace_run_plain", "gtap_autotune"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -183,7 +198,7 @@ _lib = _load()
 EXPORTED = ("gtap_config_default", "gtap_workspace_size", "gtap_init", "gtap_submit", "gtap_run",
             "gtap_result", "gtap_finalize", "gtap_stats_get", "gtap_last_error",
             "gtap_status_string", "gtap_serve_start", "gtap_serve_submit", "gtap_serve_poll",
-            "gtap_serve_stop", "gtap_trace_run", "gtap_trace_run_plain")
+            "gtap_serve_stop", "gtap_trace_run", "gtap_trace_run_plain", "gtap_autotune")
 
 
 class GtapError(RuntimeError):
@@ -305,6 +320,37 @@ def gtap_trace_run_plain(ctx, jobs, results) -> None:
     rc = _lib.gtap_trace_run_plain(ctx, jobs, len(jobs), results)
     if rc != GTAP_OK:
         raise GtapError(rc, "gtap_trace_run_plain", gtap_last_error(ctx))
+
+
+def gtap_autotune(base: "gtap_config", jobs, space: "gtap_tune_space"):
+    """(best gtap_config, report dict) over the candidates of `space`."""
+    best = gtap_config()
+    rep = gtap_tune_report()
+    rc = _lib.gtap_autotune(ctypes.byref(base), jobs, len(jobs), ctypes.byref(space), ctypes.byref(best),
+                            ctypes.byref(rep))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_autotune")
+    return best, {f: getattr(rep, f) for f, _ in rep._fields_}
+
+
+def tune_space(num_queues=(1,), waves_per_group=(4,), num_waves=(0,), bounds=(), daq_policy=0,
+               repeats=2) -> "gtap_tune_space":
+    """Build a gtap_tune_space from Python lists (num_waves 0 = occupancy maximum)."""
+    sp = gtap_tune_space()
+    for i, v in enumerate(list(num_queues)[:4]):
+        sp.num_queues[i] = int(v)
+    for i, v in enumerate(list(waves_per_group)[:4]):
+        sp.waves_per_group[i] = int(v)
+    for i, v in enumerate(list(num_waves)[:4]):
+        sp.num_waves[i] = -1 if int(v) == 0 else int(v)
+    sp.daq_policy = int(daq_policy)
+    sp.bounds_sets = min(len(bounds), 4)
+    for i, bset in enumerate(list(bounds)[:4]):
+        full = list(bset) + [1 << 30] * (7 - len(bset))
+        for k in range(7):
+            sp.bounds[i][k] = int(full[k])
+    sp.repeats = int(repeats)
+    return sp
 
 
 def uts_threshold(m: float) -> int:
@@ -439,6 +485,15 @@ class Runtime:
         res = (gtap_trace_result * len(jobs))()
         gtap_trace_run(self.ctx, jobs, res, timeout_ms)
         return res
+
+    def autotune(self, jobs, space):
+        """Best configuration for the calibration jobs (see gtap_autotune): a
+        dict of the tuned gtap_config fields, and the report."""
+        best, rep = gtap_autotune(self.cfg, jobs, space)
+        keys = ("num_queues", "daq_policy", "waves_per_group", "num_waves", "small_frames", "big_frames")
+        out = {k: getattr(best, k) for k in keys}
+        out["daq_bounds"] = list(best.daq_bounds)
+        return out, rep
 
     def trace_run_plain(self, jobs):
         res = (gtap_trace_result * len(jobs))()

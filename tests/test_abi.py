@@ -39,7 +39,8 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_2604_05982_amd import gtap
     structs = [gtap.gtap_config, gtap.gtap_fib_args, gtap.gtap_nqueens_args, gtap.gtap_uts_args,
                gtap.gtap_kclique_args, gtap.gtap_fmm_args, gtap.gtap_fmm_result, gtap.gtap_stats,
-               gtap.gtap_error_report, gtap.gtap_trace_job, gtap.gtap_trace_result]
+               gtap.gtap_error_report, gtap.gtap_trace_job, gtap.gtap_trace_result, gtap.gtap_tune_space,
+               gtap.gtap_tune_report]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gtap.h"', "int main(void){"]
     for st in structs:
         lines.append(f'printf("{st.__name__} %zu\\n", sizeof({st.__name__}));')
