@@ -244,6 +244,7 @@ typedef struct gtap_stats {
     uint64_t busy_cycles;    /* shader-clock cycles in iterations that ran tasks */
     uint64_t idle_cycles;    /* shader-clock cycles in iterations that found none */
     uint64_t admitted;       /* serving: jobs admitted from the ring           */
+    uint64_t local_pushed;   /* children kept in a wavefront's LDS stack       */
     double kernel_ms;        /* device time of the last run's persistent kernel */
     int32_t num_waves;
     int32_t waves_per_group;

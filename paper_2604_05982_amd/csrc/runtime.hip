@@ -414,6 +414,7 @@ static int record_run(gtap_ctx *c, const Control &ctl, float ms) {
   s.busy_cycles = ctl.stats[ST_BUSY_CYCLES];
   s.idle_cycles = ctl.stats[ST_IDLE_CYCLES];
   s.admitted = ctl.stats[ST_ADMITTED];
+  s.local_pushed = ctl.stats[ST_LOCAL];
   s.kernel_ms = ms;
   if (ctl.error != 0) {
     c->err.code = ctl.error;

@@ -581,11 +581,26 @@ GTAP_DEV uint32_t admit_jobs(const Params &p, WaveLds &L, uint32_t me, PoolView 
   return n;
 }
 
+// Capacity of a wavefront's private LDS task stack (task images, 32 bytes
+// each): 16 KB per wavefront, 4 KB with eight wavefronts per workgroup.
+template <int WPB>
+struct LocalCap {
+  static constexpr uint32_t v = WPB >= 8 ? 128u : 512u;
+};
+
 template <int WPB>
 __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   __shared__ WaveLds lds_all[WPB];
+  // Private task stack: children a wavefront cannot run in its lanes this
+  // iteration stay here as frameless images and are popped (newest first)
+  // before the shared deque; only the oldest are exposed to thieves, with
+  // frames, when the stack overflows or the wavefront's deque runs dry.
+  constexpr uint32_t LC = LocalCap<WPB>::v;
+  __shared__ uint4 lstk_all[WPB][2 * LC];
   const uint32_t wv = threadIdx.x >> 6;
   WaveLds &L = lds_all[wv];
+  uint4 *lstk = lstk_all[wv];
+  uint32_t lbot = 0, ltop = 0;  // wave-uniform: entries [lbot, ltop) mod LC, newest at ltop - 1
   const uint32_t me = blockIdx.x * WPB + wv;
   const uint32_t ln = lane_id();
   const uint64_t deadline = wall_ticks() + p.timeout_ticks;
@@ -651,6 +666,19 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     // batch is topped up from the queue of its class, an empty wavefront
     // starts from its fullest queue
     const uint32_t cnt0 = cnt;
+    if (p.Q == 1 && cnt < kWave && ltop != lbot) {
+      const uint32_t have = ltop - lbot;
+      const uint32_t take = (kWave - cnt) < have ? (kWave - cnt) : have;
+      if (ln >= cnt && ln < cnt + take) {
+        const uint32_t e = (ltop - 1 - (ln - cnt)) & (LC - 1);
+        L.vdesc[2 * ln] = lstk[2 * e];
+        L.vdesc[2 * ln + 1] = lstk[2 * e + 1];
+        tid = kNone;
+      }
+      wave_sync();
+      ltop -= take;
+      cnt += take;
+    }
     if (cnt < kWave) {
       uint32_t qp = cur_q;
       if (cnt == 0 && p.Q > 1) {
@@ -851,12 +879,59 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     }
     const uint32_t nR = L.qn[R];
     const uint32_t keep = (kWave - nres) < nR ? (kWave - nres) : nR;
+    // ---- private stack (one queue): small children beyond the lanes stay in
+    // LDS; the oldest entries are exposed when it would overflow, or when the
+    // wavefront's own deque has run dry (thieves then find work) ----
+    const bool use_local = (p.Q == 1);
+    uint32_t E = 0, direct = 0, nsmall = 0;
+    if (use_local) {
+      for (uint32_t g0 = keep; g0 < F; g0 += kWave) {
+        const uint32_t g = g0 + ln;
+        bool sm = false;
+        if (g < F) sm = !(L.desc[owner_of(L.offs, g)].ckind_big_d5 & 0x80u);
+        nsmall += __popcll(ballot(sm));
+      }
+      const uint32_t have = ltop - lbot;
+      uint32_t ex = (have + nsmall > LC) ? (have + nsmall - LC) : 0u;
+      if (ex > have) ex = have;
+      if ((iter & 7u) == 0 && have >= 2 * kWave) {
+        int32_t c = 0;
+        if (ln == 0) c = ld_relaxed(&deque_meta(p, me, 0)->count);
+        if (uniform(c) < static_cast<int32_t>(kWave) && have / 2 > ex) ex = have / 2;
+      }
+      E = ex;
+      const uint32_t free_slots = LC - (have - E);
+      direct = nsmall > free_slots ? nsmall - free_slots : 0u;
+    }
+    const uint32_t nglob = use_local ? (F - keep) - (nsmall - direct) + E : 0u;
     bool room = true;
     for (uint32_t qq = 0; qq < p.Q; ++qq) {
-      const uint32_t n = L.qn[qq] - (qq == R ? keep : 0u);
+      const uint32_t n = use_local ? nglob : L.qn[qq] - (qq == R ? keep : 0u);
       if (n > 0) room = room && ensure_room(p, L, me, qq, n);
     }
     if (!room) break;
+    if (E > 0) {
+      // the oldest local entries get frames and the first ring slots
+      AllocResult ae;
+      if (!alloc_frames(p, PS, me, E, ae, wc)) break;
+      wave_sync();
+      for (uint32_t i = ln; i < E; i += kWave) {
+        const uint32_t e = (lbot + i) & (LC - 1);
+        const uint4 a = lstk[2 * e], b = lstk[2 * e + 1];
+        const uint32_t cid = alloc_id(PS, ae, i);
+        ChildInit ci;
+        ci.p[0] = a.w;
+        ci.p[1] = b.x;
+        ci.p[2] = b.y;
+        ci.p[3] = b.z;
+        ci.p[4] = b.w;
+        write_frame(frame_ptr(p, cid), a.x, a.y, a.z, ci);
+        co_st32(deque_ring(p, me, 0) + ((L.tail[0] + i) & (p.cap - 1)), cid);
+      }
+      wave_sync();
+      lbot += E;
+    }
+    uint32_t lbase = 0, gbase = E;
 
     // ---- build pass: children are retained (class R, first `keep` of them)
     // or written to a frame and placed in their class's deque ----
@@ -890,8 +965,18 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         }
       }
       const bool keep_me = act && c == R && rank < keep;
+      // small children beyond the lanes: the first `direct` go to the shared
+      // deque, the rest onto the private stack
+      const bool cand = use_local && act && !keep_me && !big;
+      const uint64_t m_c = ballot(cand);
+      const uint32_t lr = lbase + rank_below(m_c);
+      lbase += __popcll(m_c);
+      const bool to_local = cand && lr >= direct;
+      const uint64_t m_g = ballot(act && !keep_me && !to_local);
+      const uint32_t gpos = gbase + rank_below(m_g);
+      gbase += __popcll(m_g);
       const bool frameless = keep_me && !big;
-      const uint64_t m_s = ballot(act && !big && !keep_me);
+      const uint64_t m_s = ballot(act && !big && !keep_me && !to_local);
       const uint64_t m_b = ballot(big);
       AllocResult as_, ab_;
       alloc_ok = alloc_frames(p, PS, me, __popcll(m_s), as_, wc) && alloc_frames(p, PB, me, __popcll(m_b), ab_, wc);
@@ -901,7 +986,11 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         const uint32_t ck = dsc.ckind_big_d5 & 0x7Fu;
         const uint32_t st = state_word(ck, 0, c);
         uint32_t cid = kNone;
-        if (frameless) {
+        if (to_local) {
+          const uint32_t e = (ltop + lr - direct) & (LC - 1);
+          lstk[2 * e] = make_uint4(dsc.self, dsc.job, st, ci.p[0]);
+          lstk[2 * e + 1] = make_uint4(ci.p[1], ci.p[2], ci.p[3], ci.p[4]);
+        } else if (frameless) {
           uint4 *v = L.vdesc + 2 * (nres + rank);
           v[0] = make_uint4(dsc.self, dsc.job, st, ci.p[0]);
           v[1] = make_uint4(ci.p[1], ci.p[2], ci.p[3], ci.p[4]);
@@ -911,19 +1000,23 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         }
         if (keep_me) {
           L.next_tid[nres + rank] = cid;
-        } else {
-          const uint32_t pos = rank - (c == R ? keep : 0u);
+        } else if (!to_local) {
+          const uint32_t pos = use_local ? gpos : rank - (c == R ? keep : 0u);
           co_st32(deque_ring(p, me, c) + ((L.tail[c] + pos) & (p.cap - 1)), cid);
         }
       }
     }
     if (!alloc_ok) break;
+    if (use_local) {
+      ltop += nsmall - direct;
+      wc.add(ST_LOCAL, nsmall - direct);
+    }
     // frames and ring slots written this iteration are complete before any
     // of them is published or run, and this iteration's join RMWs returned
     drain();
     {
       const uint32_t qq = ln;
-      const uint32_t n = (qq < p.Q) ? L.qn[qq] - (qq == R ? keep : 0u) : 0u;
+      const uint32_t n = (qq < p.Q) ? (use_local ? nglob : L.qn[qq] - (qq == R ? keep : 0u)) : 0u;
       if (n > 0) fetch_add_relaxed(&deque_meta(p, me, qq)->count, static_cast<int32_t>(n));
       wave_sync();
       if (n > 0) {

@@ -110,7 +110,7 @@ class gtap_stats(ctypes.Structure):
         "tasks", "conts", "spawns", "pushed", "push_batches", "popped", "pop_batches",
         "stolen", "steal_batches", "steal_attempts", "iterations", "idle_iterations",
         "small_frames_touched", "big_frames_touched", "depot_spills", "depot_refills",
-        "busy_cycles", "idle_cycles", "admitted")] + [
+        "busy_cycles", "idle_cycles", "admitted", "local_pushed")] + [
         ("kernel_ms", ctypes.c_double),
         ("num_waves", ctypes.c_int32),
         ("waves_per_group", ctypes.c_int32),

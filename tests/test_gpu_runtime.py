@@ -197,9 +197,29 @@ def test_small_deques_wrap_around(gtap):
     they hold, so slots are reused after wrap-around."""
     say("small deques wrap around")
     with make_rt(gtap, num_waves=2, waves_per_group=2, deque_capacity=4096) as r:
-        got, st = run_single(r, r.submit_fib, 24)
-        check(got, st, oracle.fib(24))
+        got, st = run_single(r, r.submit_fib, 28)
+        check(got, st, oracle.fib(28))
         assert st["pushed"] > 2 * 4096
+        assert st["local_pushed"] > 0
+
+
+@pytest.mark.parametrize("job", ["fib", "uts", "nqueens"])
+def test_private_stack_single_wave(gtap, job):
+    """One wavefront: children beyond the lanes live on its LDS stack, the
+    oldest are exposed to its own deque when the stack overflows or the deque
+    is empty, and come back through PopBatch."""
+    say(f"private stack, one wave, {job}")
+    with make_rt(gtap, num_waves=1, waves_per_group=1) as r:
+        if job == "fib":
+            got, st = run_single(r, r.submit_fib, 23)
+            check(got, st, oracle.fib(23))
+        elif job == "uts":
+            got, st = run_single(r, r.submit_uts, 5, THR4, 8)
+            check(got, st, oracle.uts(5, THR4, 8))
+        else:
+            got, st = run_single(r, r.submit_nqueens, 10)
+            check(got, st, oracle.nqueens(10))
+        assert st["local_pushed"] > 0 and st["stolen"] == 0
 
 
 # ---- capacity exhaustion is a structured error, not a hang -----------------
