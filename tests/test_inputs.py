@@ -78,3 +78,28 @@ def test_induced_whole_graph_and_threads():
     assert graphs.induced(g, 0, 3).n == 0
     hs = graphs.induced_many(g, [(700, i) for i in range(12)], threads=4)
     assert [h.checksum() for h in hs] == [graphs.induced(g, 700, i).checksum() for i in range(12)]
+
+
+def test_serving_mix_recipe():
+    from synth import serving
+    specs = serving.serving_mix(20000, 5)
+    kc = [s for s in specs if s.kind == "kclique"]
+    ut = [s for s in specs if s.kind == "uts"]
+    assert abs(len(kc) / 20000 - 0.6) < 0.02
+    assert {s.k for s in kc} == {4, 5, 6, 7, 8}
+    sizes = np.array([s.s for s in kc], dtype=np.float64)
+    assert sizes.min() >= 1000 and sizes.max() <= 200000
+    # log-uniform: the log sizes are uniform, mean at the log midpoint
+    ls = np.log(sizes)
+    assert abs(ls.mean() - 0.5 * (np.log(1000) + np.log(200000))) < 0.05
+    ms = np.array([s.m for s in ut])
+    assert ms.min() >= 2.0 and ms.max() <= 4.0 and abs(ms.mean() - 3.0) < 0.05
+    assert {s.depth for s in ut} == set(range(8, 15))
+    assert serving.serving_mix(300, 5) == serving.serving_mix(300, 5)
+
+
+def test_poisson_arrivals_rate():
+    from synth import serving
+    t = serving.poisson_arrivals(100000, 250.0, 3)
+    assert t[0] == 0.0 and np.all(np.diff(t) >= 0)
+    assert abs(len(t) / t[-1] - 250.0) / 250.0 < 0.02
