@@ -129,7 +129,8 @@ def bench_kclique7(args, gtap) -> int:
                 small_frames=1 << 25, big_frames=1 << 23, big_frame_ints=max(320, g.max_outdeg),
                 timeout_ms=60000, steal_below=args.steal_below)
     if args.queues > 1:
-        opts.update(num_queues=args.queues, daq_policy=2, daq_bounds=[8, 32, 128][: args.queues - 1])
+        opts.update(num_queues=args.queues, daq_policy=2, daq_bounds=[8, 32, 128][: args.queues - 1],
+                    deque_capacity=1 << 19, big_frames=1 << 24)
     rt = gtap.Runtime(**opts)
     rp = torch.as_tensor(g.row_ptr32).cuda()
     col = torch.as_tensor(g.col).cuda()
@@ -233,6 +234,9 @@ def bench_serving(args, gtap) -> int:
     rt = gtap.Runtime(**tuned, **common)
     headroom = int(tuned["small_frames"]) // 4
     specs, entries, classes, keep, subs, staged = serving_trace(gtap, rt, g, args.jobs, 5, torch)
+    n = len(entries)
+    say(f"trace ready {time.perf_counter() - t0:.1f}s {staged}")
+
     def served(arrivals):
         jobs = rt.trace([(t, e) for t, e in zip(arrivals, entries)])
         rt.serve_start(max_inflight=args.inflight, headroom_small=headroom)

@@ -31,6 +31,8 @@ namespace gtap {
 constexpr uint32_t kPushSpinLimit = 1u << 16;
 
 constexpr uint32_t kClassCache = 1024;  // children whose DAQ class is kept from the counting pass
+constexpr uint32_t kDaqPressure = 2048;  // queued tasks per wavefront above which DAQ runs lowest class first
+constexpr uint32_t kLocalFramed = 0xFFFFFFFFu;  // private-stack entry that names a frame (never a job slot)
 
 // Fork descriptor a lane leaves in LDS for the wave-wide child builder:
 // {parent frame, job, child kind | big << 7 | d5 << 8, d0..d4}, 32 bytes.
@@ -407,12 +409,19 @@ GTAP_DEV uint32_t steal_batch(const Params &p, uint32_t me, uint32_t &rng, uint3
 // kNone if every hint says empty.  Low classes hold the tasks nearest to the
 // leaves (k-clique: the smallest candidate sets), so draining them first
 // keeps the number of live frames close to that of a depth-first order.
-GTAP_DEV uint32_t fullest_own_queue(const Params &p, const WaveLds &L, uint32_t me) {
+// Under queue pressure (the wavefront's class queues hold many tasks) the
+// lowest non-empty class is taken instead.
+GTAP_DEV uint32_t fullest_own_queue(const Params &p, WaveLds &L, uint32_t me, bool pressure) {
   const uint32_t ln = lane_id();
   int32_t c = 0;
   if (ln < p.Q && L.hint[ln]) c = ld_relaxed(&deque_meta(p, me, ln)->count);
+  // only the owner adds to its deques: one read as empty stays empty until it pushes
+  wave_sync();
+  if (ln < p.Q && L.hint[ln] && c <= 0) L.hint[ln] = 0;
+  wave_sync();
   uint32_t rank = 0;
-  if (c >= static_cast<int32_t>(kWave)) rank = (1u << 23) + (kMaxQueues - ln);
+  if (pressure && c > 0) rank = (1u << 23) + (kMaxQueues - ln);
+  else if (c >= static_cast<int32_t>(kWave)) rank = (1u << 23) + (kMaxQueues - ln);
   else if (c > 0) rank = static_cast<uint32_t>(c);
   uint32_t key = rank ? ((rank << 6) | ln) : 0u;
 #pragma unroll
@@ -625,6 +634,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   uint32_t tid = kNone;
   uint32_t npend = 0;    // parents resumed in the last iteration (IDs in L.res)
   uint32_t cur_q = 0;    // DAQ class of the batch on the lanes
+  bool daq_pressure = false;  // DAQ: own class queues hold more than kDaqPressure tasks
 
   // Root admission: job j goes to wave j mod P (the paper's grid leader
   // enqueues the single root; with many jobs every wave seeds its share).
@@ -671,9 +681,14 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       const uint32_t take = (kWave - cnt) < have ? (kWave - cnt) : have;
       if (ln >= cnt && ln < cnt + take) {
         const uint32_t e = (ltop - 1 - (ln - cnt)) & (LC - 1);
-        L.vdesc[2 * ln] = lstk[2 * e];
-        L.vdesc[2 * ln + 1] = lstk[2 * e + 1];
-        tid = kNone;
+        const uint4 a = lstk[2 * e];
+        if (a.y == kLocalFramed) {
+          tid = a.x;  // a task with a frame (it carries a buffer)
+        } else {
+          L.vdesc[2 * ln] = a;
+          L.vdesc[2 * ln + 1] = lstk[2 * e + 1];
+          tid = kNone;
+        }
       }
       wave_sync();
       ltop -= take;
@@ -682,12 +697,16 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     if (cnt < kWave) {
       uint32_t qp = cur_q;
       if (cnt == 0 && p.Q > 1) {
-        qp = fullest_own_queue(p, L, me);
+        qp = fullest_own_queue(p, L, me, daq_pressure);
         if (qp != kNone) cur_q = qp;
       }
       if (qp != kNone) cnt += pop_batch(p, L, me, qp, cnt, tid, wc);
     }
-    if (cnt < p.steal_below && p.nwaves > 1) {
+    // DAQ: a wavefront that still holds tasks in its own class queues runs a
+    // partial batch rather than stealing, so it finishes its own subtrees
+    // first (stealing new work instead grows the pending frontier breadth-first)
+    const bool own_left = p.Q > 1 && cnt > 0 && ballot(ln < p.Q && L.hint[ln] != 0) != 0ull;
+    if (cnt < p.steal_below && p.nwaves > 1 && !own_left) {
       uint32_t qs = cur_q;
       const uint32_t got = steal_batch(p, me, rng, cnt, tid, qs, wc);
       if (got > 0 && cnt == 0) cur_q = qs;
@@ -725,6 +744,14 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     }
     idle = 0;
     ++iter;
+    if (p.Q > 1 && (iter & 7u) == 0) {
+      // DAQ queue pressure: tasks waiting in this wavefront's class queues
+      int32_t c = 0;
+      if (ln < p.Q) c = ld_relaxed(&deque_meta(p, me, ln)->count);
+      const uint32_t tot = static_cast<uint32_t>(
+          __builtin_amdgcn_readlane(static_cast<int>(wave_inclusive_sum(c > 0 ? static_cast<uint32_t>(c) : 0u)), 63));
+      daq_pressure = tot > kDaqPressure;
+    }
     if ((iter & 63u) == 0) {
       uint32_t stop = 0;
       if (ln == 0) {
@@ -873,8 +900,13 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       }
       wave_sync();
       uint32_t best = 0;
-      for (uint32_t qq = 1; qq < p.Q; ++qq)
-        if (L.qn[qq] > L.qn[best]) best = qq;
+      if (daq_pressure) {
+        // queue pressure: keep the lowest class present (nearest the leaves)
+        while (best + 1 < p.Q && L.qn[best] == 0) ++best;
+      } else {
+        for (uint32_t qq = 1; qq < p.Q; ++qq)
+          if (L.qn[qq] > L.qn[best]) best = qq;
+      }
       R = uniform(best);
     }
     const uint32_t nR = L.qn[R];
@@ -885,12 +917,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     const bool use_local = (p.Q == 1);
     uint32_t E = 0, direct = 0, nsmall = 0;
     if (use_local) {
-      for (uint32_t g0 = keep; g0 < F; g0 += kWave) {
-        const uint32_t g = g0 + ln;
-        bool sm = false;
-        if (g < F) sm = !(L.desc[owner_of(L.offs, g)].ckind_big_d5 & 0x80u);
-        nsmall += __popcll(ballot(sm));
-      }
+      nsmall = F - keep;  // every child beyond the lanes is a candidate
       const uint32_t have = ltop - lbot;
       uint32_t ex = (have + nsmall > LC) ? (have + nsmall - LC) : 0u;
       if (ex > have) ex = have;
@@ -911,23 +938,40 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     }
     if (!room) break;
     if (E > 0) {
-      // the oldest local entries get frames and the first ring slots
-      AllocResult ae;
-      if (!alloc_frames(p, PS, me, E, ae, wc)) break;
-      wave_sync();
-      for (uint32_t i = ln; i < E; i += kWave) {
-        const uint32_t e = (lbot + i) & (LC - 1);
-        const uint4 a = lstk[2 * e], b = lstk[2 * e + 1];
-        const uint32_t cid = alloc_id(PS, ae, i);
-        ChildInit ci;
-        ci.p[0] = a.w;
-        ci.p[1] = b.x;
-        ci.p[2] = b.y;
-        ci.p[3] = b.z;
-        ci.p[4] = b.w;
-        write_frame(frame_ptr(p, cid), a.x, a.y, a.z, ci);
-        co_st32(deque_ring(p, me, 0) + ((L.tail[0] + i) & (p.cap - 1)), cid);
+      // the oldest local entries take the first ring slots; frameless ones
+      // get frames first
+      bool ok = true;
+      for (uint32_t i0 = 0; i0 < E && ok; i0 += kWave) {
+        const uint32_t i = i0 + ln;
+        const bool act = i < E;
+        uint4 a = make_uint4(0, 0, 0, 0), b = a;
+        if (act) {
+          const uint32_t e = (lbot + i) & (LC - 1);
+          a = lstk[2 * e];
+          b = lstk[2 * e + 1];
+        }
+        const bool framed = act && a.y == kLocalFramed;
+        const uint64_t m_f = ballot(act && !framed);
+        AllocResult ae;
+        ok = alloc_frames(p, PS, me, __popcll(m_f), ae, wc);
+        if (!ok) break;
+        wave_sync();
+        if (act) {
+          uint32_t cid = a.x;
+          if (!framed) {
+            cid = alloc_id(PS, ae, rank_below(m_f));
+            ChildInit ci;
+            ci.p[0] = a.w;
+            ci.p[1] = b.x;
+            ci.p[2] = b.y;
+            ci.p[3] = b.z;
+            ci.p[4] = b.w;
+            write_frame(frame_ptr(p, cid), a.x, a.y, a.z, ci);
+          }
+          co_st32(deque_ring(p, me, 0) + ((L.tail[0] + i) & (p.cap - 1)), cid);
+        }
       }
+      if (!ok) break;
       wave_sync();
       lbot += E;
     }
@@ -967,7 +1011,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       const bool keep_me = act && c == R && rank < keep;
       // small children beyond the lanes: the first `direct` go to the shared
       // deque, the rest onto the private stack
-      const bool cand = use_local && act && !keep_me && !big;
+      const bool cand = use_local && act && !keep_me;
       const uint64_t m_c = ballot(cand);
       const uint32_t lr = lbase + rank_below(m_c);
       lbase += __popcll(m_c);
@@ -977,6 +1021,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       gbase += __popcll(m_g);
       const bool frameless = keep_me && !big;
       const uint64_t m_s = ballot(act && !big && !keep_me && !to_local);
+      const bool local_framed = to_local && big;
       const uint64_t m_b = ballot(big);
       AllocResult as_, ab_;
       alloc_ok = alloc_frames(p, PS, me, __popcll(m_s), as_, wc) && alloc_frames(p, PB, me, __popcll(m_b), ab_, wc);
@@ -986,7 +1031,12 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         const uint32_t ck = dsc.ckind_big_d5 & 0x7Fu;
         const uint32_t st = state_word(ck, 0, c);
         uint32_t cid = kNone;
-        if (to_local) {
+        if (local_framed) {
+          cid = alloc_id(PB, ab_, rank_below(m_b));
+          write_frame(frame_ptr(p, cid), dsc.self, dsc.job, st, ci);
+          const uint32_t e = (ltop + lr - direct) & (LC - 1);
+          lstk[2 * e] = make_uint4(cid, kLocalFramed, 0, 0);
+        } else if (to_local) {
           const uint32_t e = (ltop + lr - direct) & (LC - 1);
           lstk[2 * e] = make_uint4(dsc.self, dsc.job, st, ci.p[0]);
           lstk[2 * e + 1] = make_uint4(ci.p[1], ci.p[2], ci.p[3], ci.p[4]);

@@ -306,7 +306,9 @@ GTAP_DEV uint32_t bucket_of(const Params &p, uint32_t x) {
 
 // Class of child payload c of kind ckind.  GTAP_DAQ_KCLIQUE: a candidate task
 // is classed by min(|C_parent|, outdeg(u)), the spawn-time bound on the size
-// of its intersection and thus on its cost.
+// of its intersection and thus on its cost; a vertex task by its out-degree
+// (its candidate set is N+(v)); a vertex-range task, whose subtree spans many
+// vertices, by the highest class.
 GTAP_DEV uint32_t child_class(const Params &p, uint32_t job, uint32_t ckind, const ChildInit &c) {
   if (p.Q <= 1) return 0;
   switch (p.daq_policy) {
@@ -315,8 +317,13 @@ GTAP_DEV uint32_t child_class(const Params &p, uint32_t job, uint32_t ckind, con
       return k % p.Q;
     }
     case 2: {  // k-clique candidate-set bound
-      if (ckind != TK_KC_CAND) return 0;
+      if (ckind == TK_KC_RANGE) return p.Q - 1;
       const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, job, 0));
+      if (ckind == TK_KC_VERTEX) {
+        const uint32_t v = c.p[0];
+        return bucket_of(p, static_cast<uint32_t>(rp[v + 1] - rp[v]));
+      }
+      if (ckind != TK_KC_CAND) return 0;
       const uint32_t u = c.p[0], nC = c.p[4];
       const uint32_t deg = static_cast<uint32_t>(rp[u + 1] - rp[u]);
       return bucket_of(p, deg < nC ? deg : nC);

@@ -197,8 +197,8 @@ def test_small_deques_wrap_around(gtap):
     they hold, so slots are reused after wrap-around."""
     say("small deques wrap around")
     with make_rt(gtap, num_waves=2, waves_per_group=2, deque_capacity=4096) as r:
-        got, st = run_single(r, r.submit_fib, 28)
-        check(got, st, oracle.fib(28))
+        got, st = run_single(r, r.submit_fib, 31)
+        check(got, st, oracle.fib(31))
         assert st["pushed"] > 2 * 4096
         assert st["local_pushed"] > 0
 
@@ -313,7 +313,9 @@ def test_kclique_1m_k7(gtap, big_graph, queues):
     opts = dict(num_waves=1024, deque_capacity=1 << 17, small_frames=1 << 25, big_frames=1 << 23,
                 big_frame_ints=max(320, g.max_outdeg), timeout_ms=60000)
     if queues > 1:
-        opts.update(num_queues=4, daq_policy=2, daq_bounds=[8, 32, 128])
+        # per-class deques hold the breadth that one LIFO deque keeps depth-first
+        opts.update(num_queues=4, daq_policy=2, daq_bounds=[8, 32, 128], deque_capacity=1 << 19,
+                    big_frames=1 << 24)
     with make_rt(gtap, **opts) as r:
         for k in (5, 7):
             csum, count, tasks, conts = gold[(name, k)]
