@@ -423,7 +423,7 @@ def main() -> int:
                     help="kclique7: 7-cliques of the n=10^6 Chung-Lu graph (DAQ comparison); "
                          "serving: batched / served job mix against one launch per job")
     ap.add_argument("--jobs", type=int, default=20000, help="serving: jobs in the trace")
-    ap.add_argument("--inflight", type=int, default=1024, help="serving: admission limit")
+    ap.add_argument("--inflight", type=int, default=4096, help="serving: admission limit")
     ap.add_argument("--calib-jobs", type=int, default=400, help="serving: autotuner calibration jobs")
     ap.add_argument("--sweep", action="store_true", help="serving: also rho 0.3/0.5/0.7/0.9")
     ap.add_argument("--queues", type=int, default=1, help="kclique7: DAQ queues (1 = off)")
