@@ -556,6 +556,17 @@ GTAP_DEV uint32_t admit_jobs(const Params &p, WaveLds &L, uint32_t me, PoolView 
   uint32_t n = (~m == 0ull) ? kWave : static_cast<uint32_t>(__builtin_ctzll(~m));
   const int32_t allowed = static_cast<int32_t>(p.max_inflight) - inflight;
   if (allowed <= 0) return 0;
+  // backpressure: admitted roots go onto this wavefront's deque (and are
+  // popped newest first), so admit only while that deque is short
+  if (L.tail[0] - L.head_seen[0] > p.cap / 4) {
+    uint32_t h = 0;
+    if (ln == 0) h = ld_relaxed(&deque_meta(p, me, 0)->head);
+    h = uniform(h);
+    wave_sync();
+    if (ln == 0) L.head_seen[0] = h;
+    wave_sync();
+    if (L.tail[0] - h > p.cap / 4) return 0;
+  }
   if (n > static_cast<uint32_t>(allowed)) n = static_cast<uint32_t>(allowed);
   // admit by free frame-pool memory: keep the headroom free after admitting
   const int64_t ls = static_cast<int64_t>(uniform64(static_cast<uint64_t>(live)));
@@ -660,7 +671,10 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   uint64_t t_loop = clock64();
   for (;;) {
     // ---- serving: a few waves admit newly submitted jobs ----
-    if (p.serving && me < kAdmitWaves && (cnt == 0 || (iter & 15u) == 0)) admit_jobs(p, L, me, PS, wc);
+    // (any other wavefront also admits when it has been idle for a while, so
+    // a burst of arrivals spreads over the grid instead of over eight deques)
+    if (p.serving && (me < kAdmitWaves ? (cnt == 0 || (iter & 15u) == 0) : (cnt == 0 && (idle & 7u) == 4u)))
+      admit_jobs(p, L, me, PS, wc);
     // ---- acquire work ----
     // Parents resumed in the last iteration are normally staged with this
     // iteration's children; with no lanes busy they run right away.
@@ -1095,12 +1109,16 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     if (resumed) L.res[rank_below(m_res)] = o.parent;
     npend = __popcll(m_res);
     wave_sync();
-    if (p.serving && ln == 0) {
-      if (PS.net) fetch_add_relaxed(&p.ctl->live_small, static_cast<int64_t>(PS.net));
-      if (PB.net) fetch_add_relaxed(&p.ctl->live_big, static_cast<int64_t>(PB.net));
+    // serving: live-frame deltas reach the shared counters in batches (two
+    // same-address atomics per wavefront per iteration would serialise)
+    if (p.serving && ((iter & 63u) == 0 || PS.net > 1024 || PS.net < -1024 || PB.net > 256 || PB.net < -256)) {
+      if (ln == 0) {
+        if (PS.net) fetch_add_relaxed(&p.ctl->live_small, static_cast<int64_t>(PS.net));
+        if (PB.net) fetch_add_relaxed(&p.ctl->live_big, static_cast<int64_t>(PB.net));
+      }
+      PS.net = 0;
+      PB.net = 0;
     }
-    PS.net = 0;
-    PB.net = 0;
     const uint64_t now = clock64();
     busy_cycles += now - t_loop;
     t_loop = now;
