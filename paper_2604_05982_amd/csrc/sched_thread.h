@@ -669,6 +669,26 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   uint32_t iter = 0;
   bool tcont = false;  // this lane's task is a resumed parent (runs its continuation)
   uint64_t t_loop = clock64();
+  // Join RMWs of the last busy iteration.  Their old values are examined in
+  // the next iteration, after its tasks ran, so the RMW latency overlaps that
+  // work; an iteration that publishes nothing to a shared deque ends without
+  // a drain, and the drain in examine() orders its writes before the next
+  // completion RMWs.
+  bool pend_any = false;
+  bool pend_tail = false;
+  int64_t pend_old = 0;
+  uint32_t pend_len = 0, pend_par = kNone;
+  auto examine = [&]() {
+    drain();
+    const bool resumed = pend_tail && (static_cast<uint64_t>(pend_old) & kJoinMask) == pend_len;
+    const uint64_t m_res = ballot(resumed);
+    wave_sync();
+    if (resumed) L.res[rank_below(m_res)] = pend_par;
+    npend = __popcll(m_res);
+    wave_sync();
+    pend_any = false;
+    pend_tail = false;
+  };
   for (;;) {
     // ---- serving: a few waves admit newly submitted jobs ----
     // (any other wavefront also admits when it has been idle for a while, so
@@ -676,8 +696,9 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     if (p.serving && (me < kAdmitWaves ? (cnt == 0 || (iter & 15u) == 0) : (cnt == 0 && (idle & 7u) == 4u)))
       admit_jobs(p, L, me, PS, wc);
     // ---- acquire work ----
-    // Parents resumed in the last iteration are normally staged with this
-    // iteration's children; with no lanes busy they run right away.
+    // Parents resumed by the last iteration's RMWs are normally staged with
+    // this iteration's children; with no lanes busy they run right away.
+    if (cnt == 0 && pend_any) examine();
     if (cnt == 0 && npend > 0) {
       if (ln < npend) {
         tid = L.res[ln];
@@ -780,6 +801,10 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     wc.add(ST_ITERS, 1);
 
     // ---- execute one task per lane ----
+    // (a lane about to load a frame this wavefront may have written in the
+    // last iteration -- a retained or privately stacked child with a frame --
+    // waits for those writes)
+    if (pend_any && ballot(ln < cnt && tid != kNone && !tcont) != 0ull) drain();
     Outcome o;
     o.type = OUT_NONE;
     o.nchild = 0;
@@ -808,8 +833,9 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     // brings the count to zero resumes the parent (Sec. 5.1.2).  Siblings that
     // completed on adjacent lanes are summed first (a prefix sum over the wave
     // minus the prefix before the run's first lane), so each parent receives
-    // one RMW per wavefront.  The RMW's old value is examined after this
-    // iteration's final drain and the resumed parents are staged next iteration.
+    // one RMW per wavefront.  The RMW's old value is examined in the next
+    // iteration, and the parents it resumed are staged with that iteration's
+    // children.
     const bool done = (o.type == OUT_DONE);
     const bool to_parent = done && o.parent != kNone;
     const bool root_done = done && o.parent == kNone;
@@ -838,6 +864,8 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     const uint64_t before = hidx > 0 ? (pre_lo | (pre_hi << 32)) : 0ull;
     const int64_t run_val = static_cast<int64_t>(pre - before);
     const uint32_t run_len = ln - hidx + 1;
+    // the previous iteration's RMW results (its writes complete before these RMWs)
+    if (pend_any) examine();
     const int64_t lim = static_cast<int64_t>(1) << kSmallValueBits;
     const bool big_val = tail && (run_val >= lim || run_val <= -lim);
     if (ballot(big_val)) {
@@ -850,6 +878,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
                             static_cast<int64_t>(run_len);
       join_old = fetch_add_relaxed(join_ptr(frame_ptr(p, o.parent)), delta);
     }
+    const uint32_t pend_par_next = o.parent;
     if (ballot(root_done)) {
       drain();  // the job's result is in place before the run can end or the host sees it
       if (root_done && p.serving) sys_st64(&p.done_host[o.job].done, co_ld64(&p.jobs[o.job].ticket) + 1);
@@ -1075,12 +1104,12 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       ltop += nsmall - direct;
       wc.add(ST_LOCAL, nsmall - direct);
     }
-    // frames and ring slots written this iteration are complete before any
-    // of them is published or run, and this iteration's join RMWs returned
-    drain();
     {
       const uint32_t qq = ln;
       const uint32_t n = (qq < p.Q) ? (use_local ? nglob : L.qn[qq] - (qq == R ? keep : 0u)) : 0u;
+      // frames and ring slots written this iteration are complete before any
+      // of them is published
+      if (ballot(n > 0) != 0ull) drain();
       if (n > 0) fetch_add_relaxed(&deque_meta(p, me, qq)->count, static_cast<int32_t>(n));
       wave_sync();
       if (n > 0) {
@@ -1103,12 +1132,12 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     tcont = ln < nres;
     cnt = nres + keep;
     if (keep > 0) cur_q = R;
-    const bool resumed = tail && (static_cast<uint64_t>(join_old) & kJoinMask) == run_len;
-    const uint64_t m_res = ballot(resumed);
-    wave_sync();
-    if (resumed) L.res[rank_below(m_res)] = o.parent;
-    npend = __popcll(m_res);
-    wave_sync();
+    npend = 0;  // staged above
+    pend_any = true;
+    pend_tail = tail;
+    pend_old = join_old;
+    pend_len = run_len;
+    pend_par = pend_par_next;
     // serving: live-frame deltas reach the shared counters in batches (two
     // same-address atomics per wavefront per iteration would serialise)
     if (p.serving && ((iter & 63u) == 0 || PS.net > 1024 || PS.net < -1024 || PB.net > 256 || PB.net < -256)) {
