@@ -217,3 +217,27 @@ def test_split_rule_keeps_levels_close(small):
         far = np.abs(la - lb) >= 2
         wider = np.where(la < lb, lst[:, 0], lst[:, 1])
         assert np.all(cells["nchild"][wider[far]] == 0)
+
+
+def _golden_1m():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "fmm_plummer_1m.txt")
+    lists = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("# lists:"):
+                f = line.split()[2:]
+                lists = {f[i]: int(f[i + 1]) for i in range(0, len(f), 2)}
+    data = np.loadtxt(path)
+    return data[:, 0].astype(np.int64), data[:, 1], data[:, 2], lists
+
+
+def test_full_size_oracle_against_direct_summation():
+    """10^6 Plummer points: the oracle FMM at 4,096 sampled targets (stored by
+    tests/golden/make_fmm_golden.py) against fp64 direct summation."""
+    idx, direct, fmm_v, lists = _golden_1m()
+    assert idx.size == 4096 and len(np.unique(idx)) == 4096
+    err = fmm_v - direct
+    assert np.linalg.norm(err) / np.linalg.norm(direct) < 1e-4
+    assert np.abs(err).max() < 2e-4 * np.abs(direct).max()
+    assert lists["m2l_pairs"] > 0 and lists["p2p_pairs"] > 0
