@@ -418,7 +418,7 @@ def main() -> int:
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run only a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--fmm-points", type=int, default=1000000, help="fmm: number of points")
-    ap.add_argument("--fmm-wpg", type=int, default=1, help="fmm: wavefronts per workgroup (1, 2, 4)")
+    ap.add_argument("--fmm-wpg", type=int, default=2, help="fmm: wavefronts per workgroup (1, 2, 4)")
     ap.add_argument("--workload", default="microbench", choices=("microbench", "kclique7", "serving", "fmm"),
                     help="kclique7: 7-cliques of the n=10^6 Chung-Lu graph (DAQ comparison); "
                          "serving: batched / served job mix against one launch per job")

@@ -87,7 +87,8 @@ struct alignas(128) JobSlot {
   uint64_t a[8];       // kind arguments (see runtime.hip: pack_args)
   uint64_t t_done;     // device wall clock at completion
   uint64_t ticket;     // serving: the job's ticket (set by the admitting wave)
-  uint64_t pad[3];
+  int64_t pending;     // block-mode FMM: outstanding cell-pair tasks (see sched_block.h)
+  uint64_t pad[2];
 };
 static_assert(sizeof(JobSlot) == 128, "job slot is one 128-byte line");
 

@@ -659,6 +659,7 @@ int gtap_run(gtap_ctx *c) {
         return rc;
       }
       c->pending[j].a[0] = reinterpret_cast<uint64_t>(fm[j].desc);
+      c->pending[j].pending = 1;  // the root cell pair
     }
   }
   if (hipMemcpyAsync(p.jobs, c->pending.data(), nj * sizeof(JobSlot), hipMemcpyHostToDevice, c->stream) !=

@@ -7,10 +7,17 @@
 // broadcasts the task through LDS; wavefront 0 allocates and frees frames with
 // the same pools and depot as thread mode; the body runs on all threads.
 //
-// Frames, join words and the implicit join at task return are the ones of
-// thread mode.  A task whose continuation does nothing (an FMM cell pair)
-// never runs again after its join: the completion of its last child completes
-// it in place and the completion moves on to its parent.
+// Fib and UTS tasks use the frames, join words and implicit join at task
+// return of thread mode.  FMM cell-pair tasks have no result and nothing to
+// do after their children, so they are counted instead: a job keeps the
+// number of its outstanding cell-pair tasks, a workgroup accumulates
+// (children created - tasks completed) and adds it to the job's counter at
+// once when positive, lazily when negative.  Every workgroup's unadded
+// amount is thus <= 0, the counter never falls below the true outstanding
+// count, and it reaches zero exactly when the job is done.  Their children
+// stay as 32-byte images on a private LDS stack and are run newest first;
+// only the oldest get frames and go to the Chase-Lev deque, when the stack
+// overflows or the deque has run dry.
 //
 // Memory ordering: every cross-workgroup word is accessed device-coherently
 // and drain() waits for completion.  The owner's bottom decrement is an atomic
@@ -33,6 +40,8 @@ static_assert(sizeof(ClDeque) == sizeof(DequeMeta), "block deques reuse the dequ
 
 constexpr uint32_t kMaxBlockThreads = 256;
 constexpr uint32_t kP2PTile = 64;
+constexpr uint32_t kBlkLocal = 128;  // private stack of cell-pair task images
+constexpr uint32_t kM2LSlots = 1024; // >= ceil(924 / threads) * threads for 64, 128, 256 threads
 
 struct BlockLds {
   uint32_t stk_s[kStackSmall];
@@ -50,7 +59,48 @@ struct BlockLds {
   double QB[fmm::kNc];
   double sx[kP2PTile], sy[kP2PTile], sz[kP2PTile], sq[kP2PTile];
   double red[kMaxBlockThreads];
+  uint4 lstk[2 * kBlkLocal];    // private stack (frame words 0..7 of each task)
+  uint32_t lbot, ltop, local, dry;
+  // M2L term table, copied once per workgroup: coefficient and
+  // a | b << 8 | (a+b) << 16.  Thread t owns the consecutive terms
+  // [t*C, (t+1)*C) (C = ceil(924 / threads)); its r-th term is stored at
+  // r * threads + t so that a round of loads touches consecutive words.
+  double mc[kM2LSlots];
+  uint32_t mab[kM2LSlots];
+  // Running sums for the target cell of consecutive pairs (siblings of one
+  // split share it): M2L local coefficients of cell lcell, P2P potentials of
+  // the points of leaf pcell.  Added to memory when the target changes.
+  double lacc[fmm::kNc];
+  double pacc[kP2PTile];
+  const fmm::FmmDesc *ldesc;
+  const fmm::FmmDesc *pdesc;
+  uint32_t lcell, pcell;
+  int32_t pbegin, pn;
 };
+
+// Add the running M2L / P2P sums of the workgroup to memory (all threads).
+template <int NT>
+GTAP_DEV void fmm_flush_acc(BlockLds &S, bool m2l, bool p2p) {
+  const uint32_t tx = threadIdx.x;
+  if (m2l && S.lcell != kNone) {
+    for (uint32_t t = tx; t < static_cast<uint32_t>(fmm::kNc); t += NT) {
+      unsafeAtomicAdd(S.ldesc->L + static_cast<size_t>(S.lcell) * fmm::kNc + t, S.lacc[t]);
+      S.lacc[t] = 0.0;
+    }
+  }
+  if (p2p && S.pcell != kNone) {
+    for (uint32_t t = tx; t < static_cast<uint32_t>(S.pn); t += NT) {
+      unsafeAtomicAdd(S.pdesc->phi + S.pbegin + t, S.pacc[t]);
+      S.pacc[t] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (tx == 0) {
+    if (m2l) S.lcell = kNone;
+    if (p2p) S.pcell = kNone;
+  }
+  __syncthreads();
+}
 
 GTAP_DEV ClDeque *cl_deque(const Params &p, uint32_t w) { return reinterpret_cast<ClDeque *>(p.dq) + w; }
 GTAP_DEV uint32_t *cl_buf(const Params &p, uint32_t w) { return p.rings + static_cast<size_t>(w) * p.cap; }
@@ -113,6 +163,7 @@ GTAP_DEV void store_result(const Params &p, uint32_t job, int64_t v) {
 struct FmmCounters {
   uint32_t job;
   uint64_t m2l, p2p, m2l_hash, p2p_hash, inter;
+  const fmm::FmmDesc *desc;  // descriptor of `job` (read once per job)
 };
 
 GTAP_DEV void fmm_flush(const Params &p, FmmCounters &fc) {
@@ -125,18 +176,19 @@ GTAP_DEV void fmm_flush(const Params &p, FmmCounters &fc) {
     if (fc.p2p_hash) fetch_add_relaxed(&D->p2p_hash, fc.p2p_hash);
     if (fc.inter) fetch_add_relaxed(&D->p2p_inter, fc.inter);
   }
-  fc = FmmCounters{kNone, 0, 0, 0, 0, 0};
+  fc = FmmCounters{kNone, 0, 0, 0, 0, 0, nullptr};
 }
 
 template <int NT>
 GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &fc) {
   const uint32_t tx = threadIdx.x;
-  const fmm::FmmDesc *D = reinterpret_cast<const fmm::FmmDesc *>(co_ld64(&p.jobs[job].a[0]));
   const uint32_t a = S.fw[FW_P0], b = S.fw[FW_P0 + 1];
   if (fc.job != job) {
     fmm_flush(p, fc);
     fc.job = job;
+    fc.desc = reinterpret_cast<const fmm::FmmDesc *>(co_ld64(&p.jobs[job].a[0]));
   }
+  const fmm::FmmDesc *D = fc.desc;
   if (tx < fmm::kCellInts) {
     S.ca[tx] = D->cell[static_cast<size_t>(a) * fmm::kCellInts + tx];
     S.cb[tx] = D->cell[static_cast<size_t>(b) * fmm::kCellInts + tx];
@@ -194,12 +246,31 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
       }
       __syncthreads();
     }
-    for (uint32_t t = tx; t < static_cast<uint32_t>(fmm::kNc); t += NT) {
-      double acc = 0.0;
-      for (int m = fmm::kTab.m2l_first[t]; m < fmm::kTab.m2l_first[t + 1]; ++m)
-        acc += fmm::kTab.m2l_c[m] * S.T[fmm::kTab.m2l_g[m]] * S.QB[fmm::kTab.m2l_b[m]];
-      unsafeAtomicAdd(D->L + static_cast<size_t>(a) * fmm::kNc + t, acc);
+    // the running sums belong to target cell a
+    if (S.lcell != a || S.ldesc != D) {
+      fmm_flush_acc<NT>(S, true, false);
+      if (tx == 0) {
+        S.lcell = a;
+        S.ldesc = D;
+      }
     }
+    // the 924 terms spread evenly over the workgroup: each thread sums its
+    // run of terms per target coefficient and adds to LDS when it changes
+    constexpr uint32_t C = (fmm::kM2LTerms + NT - 1) / NT;
+    uint32_t cur = 0xFFu;
+    double acc = 0.0;
+#pragma unroll
+    for (uint32_t r = 0; r < C; ++r) {
+      const uint32_t w = S.mab[r * NT + tx];
+      const uint32_t at = w & 0xFFu;
+      if (at != cur) {
+        if (cur != 0xFFu) atomicAdd(&S.lacc[cur], acc);
+        acc = 0.0;
+        cur = at;
+      }
+      if (at != 0xFFu) acc += S.mc[r * NT + tx] * S.T[w >> 16] * S.QB[(w >> 8) & 0xFFu];
+    }
+    if (cur != 0xFFu) atomicAdd(&S.lacc[cur], acc);
     fc.m2l += 1;
     fc.m2l_hash += fmm::pair_hash(a, b);
     return;
@@ -208,6 +279,17 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
   constexpr uint32_t G = NT / kP2PTile;
   const int32_t ab = S.ca[4], ae = S.ca[5], bb = S.cb[4], be = S.cb[5];
   uint32_t coinc = 0;
+  const bool keep_sum = (ae - ab) <= static_cast<int32_t>(kP2PTile);  // sums stay in LDS
+  if (keep_sum && (S.pcell != a || S.pdesc != D)) {
+    fmm_flush_acc<NT>(S, false, true);
+    if (tx == 0) {
+      S.pcell = a;
+      S.pdesc = D;
+      S.pbegin = ab;
+      S.pn = ae - ab;
+    }
+    __syncthreads();
+  }
   for (int32_t t0 = ab; t0 < ae; t0 += kP2PTile) {
     const int32_t i = t0 + static_cast<int32_t>(tx % kP2PTile);
     const bool live = i < ae;
@@ -247,7 +329,8 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
       double s = 0.0;
 #pragma unroll
       for (uint32_t g = 0; g < G; ++g) s += S.red[tx + g * kP2PTile];
-      unsafeAtomicAdd(D->phi + i, s);
+      if (keep_sum) S.pacc[tx] += s;
+      else unsafeAtomicAdd(D->phi + i, s);
     }
   }
   if (coinc) atomicAdd(reinterpret_cast<unsigned long long *>(const_cast<uint64_t *>(&D->coincident)),
@@ -285,15 +368,65 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
               p.bincap_b, &p.ctl->bump_big, p.nframes_b, kBigBit, 1};
   WaveCounters wc;
   for (int i = 0; i < static_cast<int>(ST_COUNT); ++i) wc.v[i] = 0;
-  FmmCounters fc{kNone, 0, 0, 0, 0, 0};
+  FmmCounters fc{kNone, 0, 0, 0, 0, 0, nullptr};
   uint32_t rng = 0x9E3779B9u ^ (me * 0x85EBCA6Bu + 1u);
   uint64_t t_loop = clock64(), busy_cycles = 0, idle_cycles = 0;
   if (tx == 0) {
     S.bottom = 0;
     S.top_seen = 0;
     S.stop = 0;
+    S.lbot = 0;
+    S.ltop = 0;
+    S.local = 0;
+    S.dry = 0;
+  }
+  {
+    constexpr uint32_t C = (fmm::kM2LTerms + NT - 1) / NT;
+    static_assert(C * NT <= kM2LSlots, "M2L term slots");
+    for (uint32_t r = 0; r < C; ++r) {
+      const uint32_t m = tx * C + r;  // this thread's r-th term
+      uint32_t w = 0xFFu;
+      double c = 0.0;
+      if (m < static_cast<uint32_t>(fmm::kM2LTerms)) {
+        uint32_t at = 0;
+        while (fmm::kTab.m2l_first[at + 1] <= m) ++at;
+        w = at | (static_cast<uint32_t>(fmm::kTab.m2l_b[m]) << 8) | (static_cast<uint32_t>(fmm::kTab.m2l_g[m]) << 16);
+        c = fmm::kTab.m2l_c[m];
+      }
+      S.mab[r * NT + tx] = w;
+      S.mc[r * NT + tx] = c;
+    }
+  }
+  for (uint32_t t = tx; t < static_cast<uint32_t>(fmm::kNc); t += NT) S.lacc[t] = 0.0;
+  for (uint32_t t = tx; t < kP2PTile; t += NT) S.pacc[t] = 0.0;
+  if (tx == 0) {
+    S.lcell = kNone;
+    S.pcell = kNone;
+    S.ldesc = nullptr;
+    S.pdesc = nullptr;
+    S.pbegin = 0;
+    S.pn = 0;
   }
   __syncthreads();
+  // counted cell-pair tasks (thread 0's registers): the job they belong to
+  // and its unadded outstanding-count delta
+  uint32_t cjob = kNone;
+  int64_t cdelta = 0;
+  auto cflush = [&](bool positive_only) {
+    if (cjob == kNone || cdelta == 0 || (positive_only && cdelta < 0)) return;
+    int64_t *pc = &p.jobs[cjob].pending;
+    if (cdelta > 0) {
+      fetch_add_relaxed(pc, cdelta);  // cannot end the job: no wait
+    } else {
+      const int64_t old = fetch_add_relaxed(pc, cdelta);
+      if (old + cdelta == 0) {  // the job's last task completed here
+        store_result(p, cjob, 0);
+        drain();
+        fetch_add_relaxed(&p.ctl->jobs_remaining, -1);
+      }
+    }
+    cdelta = 0;
+  };
 
   // roots: job j goes to worker j mod nw, onto its deque
   if (wv == 0) {
@@ -322,9 +455,22 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
     // ---- acquire: own deque, then random victims ----
     if (tid == kNone) {
       if (tx == 0) {
-        uint32_t t = cl_pop(p, S, me);
+        uint32_t t = kNone;
+        S.local = 0;
+        if (S.ltop != S.lbot) {
+          // private stack, newest first: the image becomes the frame copy
+          const uint32_t e = (S.ltop - 1) & (kBlkLocal - 1);
+          const uint4 a = S.lstk[2 * e], b = S.lstk[2 * e + 1];
+          S.fw[0] = a.x; S.fw[1] = a.y; S.fw[2] = a.z; S.fw[3] = a.w;
+          S.fw[4] = b.x; S.fw[5] = b.y; S.fw[6] = b.z; S.fw[7] = b.w;
+          S.ltop -= 1;
+          S.local = 1;
+        } else {
+          t = cl_pop(p, S, me);
+        }
         if (t != kNone) {
           wc.add(ST_POPPED, 1);
+        } else if (S.local) {
         } else if (nw > 1) {
           wc.add(ST_STEAL_ATTEMPTS, 1);
           for (uint32_t k = 0; k < p.steal_probes && t == kNone; ++k) {
@@ -337,7 +483,8 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
         S.task = t;
         S.next_cont = 0;
         uint32_t stop = 0;
-        if (t == kNone && (idle & 3u) == 0u) {
+        if (t == kNone && !S.local) cflush(false);  // nothing to run: report completions
+        if (t == kNone && !S.local && (idle & 3u) == 0u) {
           if (ld_relaxed(&p.ctl->jobs_remaining) <= 0 || ld_relaxed(&p.ctl->error) != 0) stop = 1;
           else if (wall_ticks() > deadline) {
             raise_error(p, -8 /*GTAP_E_TIMEOUT*/, 3, p.timeout_ticks, 0, me, -1);
@@ -350,7 +497,7 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
       tid = S.task;
       cont = 0;
       if (S.stop) break;
-      if (tid == kNone) {
+      if (tid == kNone && !S.local) {
         ++idle;
         wc.add(ST_IDLE, 1);
         backoff_sleep(idle);
@@ -378,8 +525,9 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
       if (S.stop) break;
     }
 
-    // ---- load the frame ----
-    if (tx < kFrameWords) S.fw[tx] = co_ld32(frame_ptr(p, tid) + tx);
+    // ---- load the frame (a private-stack image is already in place) ----
+    const bool from_local = (tid == kNone);
+    if (!from_local && tx < kFrameWords) S.fw[tx] = co_ld32(frame_ptr(p, tid) + tx);
     if (tx == 0) {
       S.out_type = OUT_DONE;
       S.nchild = 0;
@@ -445,7 +593,93 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
     __syncthreads();
 
     // ---- fork or complete (wavefront 0) ----
-    if (wv == 0) {
+    if (wv == 0 && kind == TK_FMM) {
+      // counted cell-pair task: children onto the private stack, completion
+      // into the job's outstanding count
+      const uint32_t k = (S.out_type == OUT_FORK) ? S.nchild : 0u;
+      if (!from_local) free_frames(PS, me, ln == 0, tid, wc);  // the root or an exposed task
+      const uint32_t have_l = S.ltop - S.lbot;
+      uint32_t dry = 0;
+      if ((iter & 15u) == 0 && have_l >= 4) {
+        if (ln == 0) {
+          const int64_t t = static_cast<int64_t>(co_ld64(reinterpret_cast<const uint64_t *>(&cl_deque(p, me)->top)));
+          S.top_seen = t;
+          dry = (S.bottom - t <= 0) ? 1u : 0u;
+        }
+        dry = uniform(dry);
+      }
+      // expose the oldest entries when the stack would overflow or the deque is dry
+      uint32_t E = (have_l + k > kBlkLocal) ? (have_l + k - kBlkLocal) : 0u;
+      if (dry && have_l / 2 > E) E = have_l / 2;
+      if (E > have_l) E = have_l;
+      bool ok = true;
+      if (E > 0) {
+        uint32_t room = 1;
+        if (ln == 0) room = cl_room(p, S, me, E) ? 1u : 0u;
+        ok = uniform(room) != 0;
+        if (!ok) {
+          if (ln == 0) raise_error(p, -6 /*GTAP_E_CAPACITY*/, 2, p.cap, E, me, static_cast<int32_t>(job));
+        } else {
+          const int64_t bot = S.bottom;
+          const uint32_t lb = S.lbot;
+          for (uint32_t i0 = 0; i0 < E; i0 += kWave) {
+            const uint32_t chunk = (E - i0) < kWave ? (E - i0) : kWave;
+            AllocResult ar{};
+            if (!alloc_frames(p, PS, me, chunk, ar, wc)) {
+              ok = false;
+              break;
+            }
+            wave_sync();
+            if (ln < chunk) {
+              const uint32_t i = i0 + ln;
+              const uint32_t e = (lb + i) & (kBlkLocal - 1);
+              const uint4 a = S.lstk[2 * e], b = S.lstk[2 * e + 1];
+              const uint32_t cid = alloc_id(PS, ar, ln);
+              uint64_t *f64 = frame64(frame_ptr(p, cid));
+              co_st64(f64 + 0, pack(a.x, a.y));
+              co_st64(f64 + 1, pack(a.z, a.w));
+              co_st64(f64 + 2, pack(b.x, b.y));
+              co_st64(f64 + 3, pack(b.z, b.w));
+              co_st32(cl_buf(p, me) + (static_cast<uint64_t>(bot + i) & (p.cap - 1)), cid);
+            }
+          }
+          if (ok) {
+            drain();  // frames and slots complete before the deque grows
+            if (ln == 0) {
+              co_st64(reinterpret_cast<uint64_t *>(&cl_deque(p, me)->bottom), static_cast<uint64_t>(bot + E));
+              S.bottom = bot + E;
+              S.lbot = lb + E;
+            }
+            wc.add(ST_PUSHED, E);
+          }
+        }
+        wave_sync();
+      }
+      if (ok) {
+        const uint32_t lt = S.ltop;
+        if (ln < k) {
+          const uint32_t e = (lt + ln) & (kBlkLocal - 1);
+          S.lstk[2 * e] = make_uint4(kNone, job, state_word(TK_FMM, 0, 0), S.child[ln][0]);
+          S.lstk[2 * e + 1] = make_uint4(S.child[ln][1], 0, 0, 0);
+        }
+        wave_sync();
+        if (ln == 0) {
+          S.ltop = lt + k;
+          if (cjob != job) {
+            cflush(false);
+            cjob = job;
+          }
+          cdelta += static_cast<int64_t>(k) - 1;
+          cflush(true);
+        }
+        wc.add(ST_SPAWNS, k);
+        wc.add(ST_LOCAL, k);
+      }
+      if (ln == 0) {
+        S.next = kNone;
+        S.next_cont = 0;
+      }
+    } else if (wv == 0) {
       const uint32_t out = S.out_type;
       uint32_t next = kNone, next_cont = 0;
       if (out == OUT_FORK) {
@@ -573,6 +807,7 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
     t_loop = now;
   }
 
+  fmm_flush_acc<NT>(S, true, true);
   fmm_flush(p, fc);
   if (tx == 0) {
     for (int i = 0; i < static_cast<int>(ST_COUNT); ++i)
