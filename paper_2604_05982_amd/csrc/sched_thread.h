@@ -676,6 +676,10 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   // completion RMWs.
   bool pend_any = false;
   bool pend_tail = false;
+  // frame words of the continuation this lane runs next iteration, loaded as
+  // soon as the parent is known to resume (one iteration ahead)
+  TaskImage cpre{0, 0, 0, 0};
+  bool cpre_ok = false;
   int64_t pend_old = 0;
   uint32_t pend_len = 0, pend_par = kNone;
   auto examine = [&]() {
@@ -817,7 +821,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         const uint4 a = L.vdesc[2 * ln], b = L.vdesc[2 * ln + 1];
         img = TaskImage{pack(a.x, a.y), pack(a.z, a.w), pack(b.x, b.y), pack(b.z, b.w)};
       } else if (tcont) {
-        img = load_continuation(p, tid);
+        img = cpre_ok ? cpre : load_continuation(p, tid);
       } else {
         img = load_image(p, tid);
       }
@@ -865,7 +869,16 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     const int64_t run_val = static_cast<int64_t>(pre - before);
     const uint32_t run_len = ln - hidx + 1;
     // the previous iteration's RMW results (its writes complete before these RMWs)
-    if (pend_any) examine();
+    cpre_ok = false;
+    if (pend_any) {
+      examine();
+      // the parents it resumed run next iteration on lanes [0, npend): their
+      // frames are fetched now
+      if (ln < npend) {
+        cpre = load_continuation(p, L.res[ln]);
+        cpre_ok = true;
+      }
+    }
     const int64_t lim = static_cast<int64_t>(1) << kSmallValueBits;
     const bool big_val = tail && (run_val >= lim || run_val <= -lim);
     if (ballot(big_val)) {
