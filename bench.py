@@ -406,6 +406,73 @@ def bench_fmm(args, gtap) -> int:
     return 0
 
 
+def bench_schedulers(args, gtap) -> int:
+    """Scheduler comparison (Sec. 6.5): fib(n) in thread mode under four queue
+    managements over a sweep of grid sizes -- batched work stealing with the
+    private LDS stack (this runtime), the same without it (the paper's
+    Algorithm 1), non-batched work stealing (one task per pop and per steal)
+    and one centralised FIFO queue.  Every run is checked against the closed
+    forms F(n), 2F(n+1)-1 calls and F(n+1)-1 continuations."""
+    import torch
+    n = args.fib_n
+    f = [0, 1]
+    while len(f) < n + 2:
+        f.append(f[-1] + f[-2])
+    want = (f[n], 2 * f[n + 1] - 1, f[n + 1] - 1)
+    variants = [("batched, LDS stack", 0), ("batched", gtap.GTAP_FLAG_NO_PRIVATE_STACK),
+                ("non-batched", gtap.GTAP_FLAG_SCHED_SINGLE), ("central queue", gtap.GTAP_FLAG_SCHED_CENTRAL)]
+    grid = [int(w) for w in args.sched_waves.split(",")]
+    rows = []
+    for name, flag in variants:
+        slow = None
+        for w in grid:
+            if slow is not None:
+                rows.append({"variant": name, "waves": w, "skipped": slow})
+                continue
+            rt = gtap.Runtime(flags=flag, num_waves=w, waves_per_group=4, small_frames=1 << 26,
+                              deque_capacity=(1 << 20) if flag == gtap.GTAP_FLAG_SCHED_CENTRAL else (1 << 16),
+                              timeout_ms=20000)
+            ms = []
+            try:
+                for it in range(args.warmup + args.steps):
+                    jid = rt.submit_fib(n)
+                    rt.run()
+                    st = rt.stats()
+                    got = (rt.result(jid), st["tasks"], st["conts"])
+                    if got != want:
+                        raise SystemExit(f"{name}, {w} waves: got {got}, expected {want}")
+                    if it >= args.warmup:
+                        ms.append(st["kernel_ms"])
+            except gtap.GtapError as e:
+                rt.close()
+                slow = f"a run at {w} wavefronts ended with {gtap.gtap_status_string(e.code)}"
+                rows.append({"variant": name, "waves": w, "error": slow})
+                print(f"# {name:20s} waves {w:5d}: {slow}", file=sys.stderr, flush=True)
+                continue
+            torch.cuda.synchronize()
+            rt.close()
+            med = sorted(ms)[len(ms) // 2]
+            row = {"variant": name, "waves": st["num_waves"], "kernel_ms_median": med,
+                   "kernel_ms_min": min(ms), "tasks_per_s": want[1] / (med * 1e-3),
+                   "pushed": st["pushed"], "popped": st["popped"], "stolen": st["stolen"],
+                   "pop_batches": st["pop_batches"], "steal_batches": st["steal_batches"],
+                   "steal_attempts": st["steal_attempts"], "iterations": st["iterations"]}
+            rows.append(row)
+            print(f"# {name:20s} waves {row['waves']:5d}: {med:9.3f} ms  {row['tasks_per_s'] / 1e9:7.3f} G tasks/s",
+                  file=sys.stderr, flush=True)
+            if med > 3000.0:
+                slow = f"over 3 s per run at {w} wavefronts"
+    best = max(r["tasks_per_s"] for r in rows if r["variant"] == variants[0][0] and "tasks_per_s" in r)
+    out = {"metric": METRIC, "value": best, "unit": "tasks/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+           "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"scheduler comparison: fib({n}) in thread mode, one launch per run, "
+                                  f"grid sweep over {grid} wavefronts (4 per workgroup)"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,7 +486,10 @@ def main() -> int:
                     help="run only a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--fmm-points", type=int, default=1000000, help="fmm: number of points")
     ap.add_argument("--fmm-wpg", type=int, default=2, help="fmm: wavefronts per workgroup (1, 2, 4)")
-    ap.add_argument("--workload", default="microbench", choices=("microbench", "kclique7", "serving", "fmm"),
+    ap.add_argument("--fib-n", type=int, default=35, help="schedulers: fib argument")
+    ap.add_argument("--sched-waves", default="64,128,256,512,1024", help="schedulers: grid sizes (wavefronts)")
+    ap.add_argument("--workload", default="microbench",
+                    choices=("microbench", "kclique7", "serving", "fmm", "schedulers"),
                     help="kclique7: 7-cliques of the n=10^6 Chung-Lu graph (DAQ comparison); "
                          "serving: batched / served job mix against one launch per job")
     ap.add_argument("--jobs", type=int, default=20000, help="serving: jobs in the trace")
@@ -445,6 +515,8 @@ def main() -> int:
         return bench_serving(args, gtap)
     if args.workload == "fmm":
         return bench_fmm(args, gtap)
+    if args.workload == "schedulers":
+        return bench_schedulers(args, gtap)
 
     rt = gtap.Runtime(waves_per_group=args.waves_per_group, num_waves=args.num_waves,
                       steal_below=args.steal_below, small_frames=1 << 25, timeout_ms=60000)

@@ -172,13 +172,37 @@ typedef struct gtap_config {
     uint32_t big_frame_ints;  /* int32 capacity of a big frame's buffer        */
     uint32_t max_jobs;        /* jobs per run                                  */
     uint32_t timeout_ms;      /* device watchdog per run (0 = 120000)          */
-    uint32_t flags;           /* reserved, must be 0                           */
+    uint32_t flags;           /* gtap_flags (thread mode); 0 = the scheduler
+                                 as designed                                  */
     void *stream;             /* hipStream_t to launch on (NULL = default)     */
     void *workspace_dev;      /* optional caller-owned device memory of
                                  workspace_bytes (>= gtap_workspace_size);
                                  NULL = the library allocates and frees it    */
     uint64_t workspace_bytes;
 } gtap_config;
+
+/* Scheduler variants for the comparison of thread-mode schedulers (Sec. 6.5,
+ * "GPU-Side Scheduler Comparison"): all share the runtime and differ only in
+ * queue management.  Thread mode, one queue, batch runs only (serving and
+ * block mode reject them).
+ *   GTAP_FLAG_NO_PRIVATE_STACK  children beyond the 64 lanes go to the
+ *                               wavefront's deque at once (no LDS stack), as
+ *                               in the paper's Algorithm 1
+ *   GTAP_FLAG_SCHED_SINGLE      non-batched work stealing: every pop and every
+ *                               steal claims one task; a wavefront issues up
+ *                               to 64 of them per iteration (implies no
+ *                               private stack)
+ *   GTAP_FLAG_SCHED_CENTRAL     one FIFO queue for the whole grid instead of
+ *                               per-wavefront deques: batched pushes reserve
+ *                               ring positions with one atomic, pops claim
+ *                               by CAS on its count; no stealing (implies no
+ *                               private stack)
+ * SINGLE and CENTRAL are exclusive. */
+enum gtap_flags {
+    GTAP_FLAG_NO_PRIVATE_STACK = 1,
+    GTAP_FLAG_SCHED_SINGLE = 2,
+    GTAP_FLAG_SCHED_CENTRAL = 4
+};
 
 /* Fill *cfg with defaults (thread mode, occupancy-sized grid, one queue). */
 void gtap_config_default(gtap_config *cfg);

@@ -135,6 +135,19 @@ struct alignas(128) Control {
 };
 
 // Kernel parameters (passed by value).
+// Centralised queue (scheduler comparison): positions are 32-bit counters
+// that wrap; a slot holds (position << 32 | task ID), so a reader waits for
+// the writer of its own position.  Each word on its own line.
+struct alignas(128) CentralQueue {
+  uint32_t tail;      // next position to reserve (pushes)
+  uint32_t pad0[31];
+  int32_t count;      // published, unclaimed entries (claims CAS on it)
+  uint32_t pad1[31];
+  uint32_t head;      // next position to claim (pops)
+  uint32_t pad2[31];
+};
+constexpr uint32_t kSchedBatched = 0, kSchedSingle = 1, kSchedCentral = 2;
+
 struct Params {
   Control *ctl;
   JobSlot *jobs;
@@ -172,6 +185,12 @@ struct Params {
   uint32_t max_inflight;    // admitted and not completed
   uint32_t admit_headroom_small;  // frames that must stay free after admitting a job
   uint32_t admit_headroom_big;
+  // scheduler variant (kSched*) and the private LDS stack switch
+  uint32_t sched;
+  uint32_t no_local;
+  CentralQueue *cq;         // kSchedCentral only
+  uint64_t *cring;          // [ccap] tagged slots
+  uint32_t ccap;            // power of two, 0 unless kSchedCentral
 };
 
 }  // namespace gtap

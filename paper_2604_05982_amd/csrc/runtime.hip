@@ -31,9 +31,22 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t ctl, jobs, dq, rings, bins_s, store_s, bins_b, store_b, frames_s, frames_b, total;
-  uint32_t bincap_s, bincap_b, stride_b;
+  size_t ctl, jobs, dq, rings, bins_s, store_s, bins_b, store_b, frames_s, frames_b, cq, cring, total;
+  uint32_t bincap_s, bincap_b, stride_b, ccap;
 };
+
+// Centralised-queue variant: one ring for the grid, as many slots as all the
+// wavefronts' deques together (a power of two, at most 2^26), and at least
+// 256 per wavefront (a reservation keeps 64 per wavefront clear of claims
+// that may still be reading).
+uint32_t central_capacity(const gtap_config &c, uint32_t nwaves) {
+  if (!(c.flags & GTAP_FLAG_SCHED_CENTRAL)) return 0;
+  uint64_t want = static_cast<uint64_t>(c.deque_capacity) * nwaves;
+  if (want > (1ull << 26)) want = 1ull << 26;
+  uint32_t cap = 1u << 16;
+  while (static_cast<uint64_t>(cap) * 2 <= want || cap < 256ull * nwaves) cap *= 2;
+  return cap;
+}
 
 Layout make_layout(const gtap_config &c, uint32_t nwaves) {
   Layout L{};
@@ -58,6 +71,9 @@ Layout make_layout(const gtap_config &c, uint32_t nwaves) {
   L.store_b = take(sizeof(uint32_t) * static_cast<size_t>(kDepotBins) * L.bincap_b);
   L.frames_s = take(sizeof(uint32_t) * kFrameWords * static_cast<size_t>(c.small_frames));
   L.frames_b = take(sizeof(uint32_t) * static_cast<size_t>(L.stride_b) * c.big_frames);
+  L.ccap = central_capacity(c, nwaves);
+  L.cq = take(L.ccap ? sizeof(CentralQueue) : 0);
+  L.cring = take(sizeof(uint64_t) * static_cast<size_t>(L.ccap));
   L.total = off;
   return L;
 }
@@ -120,8 +136,16 @@ int validate(const gtap_config &c) {
   if (c.big_frames >= (1ull << 31)) return GTAP_E_INVAL;
   if (c.big_frame_ints > (1u << 24)) return GTAP_E_INVAL;
   if (c.max_jobs < 1 || c.max_jobs > (1u << 24)) return GTAP_E_INVAL;
-  if (c.flags != 0) return GTAP_E_INVAL;
+  const uint32_t known = GTAP_FLAG_NO_PRIVATE_STACK | GTAP_FLAG_SCHED_SINGLE | GTAP_FLAG_SCHED_CENTRAL;
+  if (c.flags & ~known) return GTAP_E_INVAL;
+  if (c.flags && (c.mode != GTAP_MODE_THREAD || c.num_queues != 1)) return GTAP_E_INVAL;
+  if ((c.flags & GTAP_FLAG_SCHED_SINGLE) && (c.flags & GTAP_FLAG_SCHED_CENTRAL)) return GTAP_E_INVAL;
   return GTAP_OK;
+}
+
+uint32_t reset_blocks(uint32_t ndeques, uint32_t ccap) {
+  const uint32_t n = std::max(ndeques, ccap);
+  return std::min<uint32_t>(std::max<uint32_t>((n + 255) / 256, 1), 4096);
 }
 
 __global__ void reset_kernel(Params p, uint32_t ndeques) {
@@ -138,6 +162,14 @@ __global__ void reset_kernel(Params p, uint32_t ndeques) {
     p.bins_s[b].nchunks = 0;
     p.bins_b[b].lock = 0;
     p.bins_b[b].nchunks = 0;
+  }
+  // centralised queue: positions restart at 0, so no slot may carry a tag
+  // from an earlier run
+  for (size_t s = i0; s < p.ccap; s += stride) p.cring[s] = ~0ull;
+  if (i0 == 0 && p.ccap) {
+    p.cq->tail = 0;
+    p.cq->count = 0;
+    p.cq->head = 0;
   }
   if (i0 == 0) {
     Control *c = p.ctl;
@@ -285,6 +317,12 @@ int gtap_init(const gtap_config *cfg, gtap_ctx **out) {
   p.steal_div = c->cfg.steal_div;
   p.daq_policy = static_cast<uint32_t>(c->cfg.daq_policy);
   for (uint32_t i = 0; i < kMaxQueues - 1; ++i) p.daq_bounds[i] = c->cfg.daq_bounds[i];
+  const uint32_t fl = c->cfg.flags;
+  p.sched = (fl & GTAP_FLAG_SCHED_CENTRAL) ? kSchedCentral : (fl & GTAP_FLAG_SCHED_SINGLE) ? kSchedSingle : kSchedBatched;
+  p.no_local = (fl & (GTAP_FLAG_NO_PRIVATE_STACK | GTAP_FLAG_SCHED_SINGLE | GTAP_FLAG_SCHED_CENTRAL)) ? 1u : 0u;
+  p.ccap = c->lay.ccap;
+  p.cq = p.ccap ? reinterpret_cast<CentralQueue *>(c->ws + c->lay.cq) : nullptr;
+  p.cring = p.ccap ? reinterpret_cast<uint64_t *>(c->ws + c->lay.cring) : nullptr;
   int dev = 0, rate_khz = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
@@ -668,8 +706,7 @@ int gtap_run(gtap_ctx *c) {
     return GTAP_E_HIP;
   }
   const uint32_t ndq = c->nwaves * p.Q;
-  hipLaunchKernelGGL(reset_kernel, dim3(std::max<uint32_t>((ndq + 255) / 256, 1)), dim3(256), 0, c->stream, p,
-                     ndq);
+  hipLaunchKernelGGL(reset_kernel, dim3(reset_blocks(ndq, p.ccap)), dim3(256), 0, c->stream, p, ndq);
   int rc = GTAP_OK;
   if (hipGetLastError() != hipSuccess || hipEventRecord(c->ev0, c->stream) != hipSuccess) rc = GTAP_E_HIP;
   if (rc == GTAP_OK) rc = launch_sched(c);
@@ -718,7 +755,7 @@ static double host_seconds() {
 int gtap_serve_start(gtap_ctx *c, uint32_t max_inflight, uint32_t headroom_small, uint32_t headroom_big) {
   if (!c) return GTAP_E_INVAL;
   if (c->serving || !c->pending.empty()) return GTAP_E_STATE;
-  if (c->cfg.mode != GTAP_MODE_THREAD) return GTAP_E_INVAL;
+  if (c->cfg.mode != GTAP_MODE_THREAD || c->cfg.flags != 0) return GTAP_E_INVAL;
   if (max_inflight == 0 || max_inflight > c->cfg.max_jobs) return GTAP_E_INVAL;
   const size_t R = c->cfg.max_jobs;
   if (!c->ring) {
@@ -747,8 +784,7 @@ int gtap_serve_start(gtap_ctx *c, uint32_t max_inflight, uint32_t headroom_small
   p.admit_headroom_small = headroom_small;
   p.admit_headroom_big = headroom_big;
   const uint32_t ndq = c->nwaves * p.Q;
-  hipLaunchKernelGGL(reset_kernel, dim3(std::max<uint32_t>((ndq + 255) / 256, 1)), dim3(256), 0, c->stream, p,
-                     ndq);
+  hipLaunchKernelGGL(reset_kernel, dim3(reset_blocks(ndq, p.ccap)), dim3(256), 0, c->stream, p, ndq);
   if (hipGetLastError() != hipSuccess) return GTAP_E_HIP;
   if (hipEventRecord(c->ev0, c->stream) != hipSuccess) return GTAP_E_HIP;
   const int rc = launch_sched(c);

@@ -294,13 +294,13 @@ GTAP_DEV uint32_t *deque_ring(const Params &p, uint32_t wave, uint32_t q) {
 
 // PopBatch (Algorithm 2): claim up to 64-cnt IDs from the tail of own deque q.
 GTAP_DEV uint32_t pop_batch(const Params &p, WaveLds &L, uint32_t me, uint32_t q, uint32_t cnt,
-                            uint32_t &tid, WaveCounters &wc) {
+                            uint32_t &tid, WaveCounters &wc, uint32_t limit = kWave) {
   // Only the owner raises count, so once a pop found it empty (or took all of
   // it) nothing can be popped until the owner pushes again.
   if (L.hint[q] == 0) return 0;
   DequeMeta *m = deque_meta(p, me, q);
   const uint32_t ln = lane_id();
-  const int32_t want = static_cast<int32_t>(kWave - cnt);
+  const int32_t want = static_cast<int32_t>((kWave - cnt) < limit ? (kWave - cnt) : limit);
   int32_t claim = 0;
   uint32_t drained = 0;
   if (ln == 0) {
@@ -342,7 +342,7 @@ GTAP_DEV uint32_t pop_batch(const Params &p, WaveLds &L, uint32_t me, uint32_t q
 // loaded from head, then head advances and the lock is released.  With DAQ
 // this takes the victim's fullest queue (Sec. 5.1.3, thread mode).
 GTAP_DEV uint32_t steal_batch(const Params &p, uint32_t me, uint32_t &rng, uint32_t cnt, uint32_t &tid,
-                              uint32_t &qout, WaveCounters &wc) {
+                              uint32_t &qout, WaveCounters &wc, uint32_t limit = kWave) {
   const uint32_t ln = lane_id();
   wc.add(ST_STEAL_ATTEMPTS, 1);
   const uint32_t probe = ln / p.Q, qi = ln % p.Q;
@@ -368,7 +368,7 @@ GTAP_DEV uint32_t steal_batch(const Params &p, uint32_t me, uint32_t &rng, uint3
   const uint32_t victim = uniform(static_cast<uint32_t>(__shfl(static_cast<int>(v), static_cast<int>(win), 64)));
   const uint32_t q = win % p.Q;
   DequeMeta *m = deque_meta(p, victim, q);
-  const int32_t want = static_cast<int32_t>(kWave - cnt);
+  const int32_t want = static_cast<int32_t>((kWave - cnt) < limit ? (kWave - cnt) : limit);
   int32_t claim = 0;
   uint32_t h = 0;
   if (ln == 0) {
@@ -483,6 +483,109 @@ GTAP_DEV bool push_batch(const Params &p, WaveLds &L, uint32_t me, uint32_t q, u
   wc.add(ST_PUSHED, n);
   wc.add(ST_PUSH_BATCHES, 1);
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// Centralised queue (the baseline of the scheduler comparison, Sec. 6.5): one
+// FIFO ring for the whole grid.  A push reserves n positions with one atomic
+// on tail, writes (position << 32 | ID) into each slot, drains, then raises
+// count once.  The slot write is what publishes an entry, so the frame it
+// names is drained before it.  A pop claims k <= count by CAS on count (a few attempts per
+// call: one while lanes are busy, eight on an empty wavefront; a failed CAS
+// means another wavefront claimed), takes positions [head, head + k) with one
+// atomic on head and waits until each slot carries its own position (a push
+// that reserved earlier may still be writing).  Subtracting first and giving
+// back the excess would avoid the retries but can starve: with hundreds of
+// pollers the pending give-backs keep the count below zero.  A reservation
+// waits while it would reach positions that claims below head - 64 * nwaves
+// might still be reading.
+GTAP_DEV bool central_reserve(const Params &p, WaveLds &L, uint32_t me, uint32_t n, uint32_t &base) {
+  uint32_t b = 0, ok = 1;
+  if (lane_id() == 0) {
+    b = fetch_add_relaxed(&p.cq->tail, n);
+    const uint32_t room = p.ccap - kWave * p.nwaves;
+    uint32_t h = L.head_seen[0];
+    uint32_t spins = 0;
+    while (b + n - h > room) {
+      h = ld_relaxed(&p.cq->head);
+      if (b + n - h <= room) break;
+      if (++spins > kPushSpinLimit) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    L.head_seen[0] = h;
+  }
+  ok = uniform(ok);
+  base = uniform(b);
+  wave_sync();
+  if (!ok && lane_id() == 0) raise_error(p, -6 /*GTAP_E_CAPACITY*/, 2, p.ccap, n, me, -1);
+  return ok != 0;
+}
+
+GTAP_DEV void central_put(const Params &p, uint32_t pos, uint32_t id) {
+  co_st64(p.cring + (pos & (p.ccap - 1)), (static_cast<uint64_t>(pos) << 32) | id);
+}
+
+// The slot write publishes an entry (see central_pop): the frames the IDs name
+// must be complete (drained) before the call.
+template <class IdFn>
+GTAP_DEV bool central_push(const Params &p, WaveLds &L, uint32_t me, uint32_t n, IdFn id_of, WaveCounters &wc) {
+  if (n == 0) return true;
+  uint32_t b = 0;
+  if (!central_reserve(p, L, me, n, b)) return false;
+  for (uint32_t i = lane_id(); i < n; i += kWave) central_put(p, b + i, id_of(i));
+  drain();
+  if (lane_id() == 0) fetch_add_relaxed(&p.cq->count, static_cast<int32_t>(n));
+  wc.add(ST_PUSHED, n);
+  wc.add(ST_PUSH_BATCHES, 1);
+  return true;
+}
+
+// Returns the number claimed, or -1 (error raised) if a slot never arrived.
+GTAP_DEV int32_t central_pop(const Params &p, uint32_t me, uint32_t cnt, uint32_t &tid, WaveCounters &wc) {
+  const uint32_t ln = lane_id();
+  const int32_t want = static_cast<int32_t>(kWave - cnt);
+  int32_t claim = 0;
+  uint32_t pos = 0;
+  if (ln == 0) {
+    int32_t c = ld_relaxed(&p.cq->count);
+    for (uint32_t attempt = cnt == 0 ? 8u : 1u; c > 0 && attempt > 0; --attempt) {
+      const int32_t take = c < want ? c : want;
+      if (cas_relaxed(&p.cq->count, &c, c - take)) {
+        claim = take;
+        break;
+      }
+    }
+    if (claim > 0) pos = fetch_add_relaxed(&p.cq->head, static_cast<uint32_t>(claim));
+  }
+  claim = uniform(claim);
+  if (claim == 0) return 0;
+  pos = uniform(pos);
+  bool lost = false;
+  if (ln >= cnt && ln < cnt + static_cast<uint32_t>(claim)) {
+    const uint32_t my = pos + (ln - cnt);
+    const uint64_t *s = p.cring + (my & (p.ccap - 1));
+    uint64_t v = co_ld64(s);
+    uint32_t spins = 0;
+    while (static_cast<uint32_t>(v >> 32) != my) {
+      if (++spins > kPushSpinLimit) {
+        lost = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      v = co_ld64(s);
+    }
+    tid = static_cast<uint32_t>(v);
+  }
+  if (ballot(lost) != 0ull) {
+    if (ln == 0) raise_error(p, -6 /*GTAP_E_CAPACITY*/, 2, p.ccap, 0, me, -1);
+    return -1;
+  }
+  wc.add(ST_POPPED, static_cast<uint32_t>(claim));
+  wc.add(ST_POP_BATCHES, 1);
+  return claim;
 }
 
 // ---------------------------------------------------------------------------
@@ -661,7 +764,9 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       const uint32_t keep = nroots < kWave ? nroots : kWave;
       if (ln < keep) tid = alloc_id(PS, ar, ln);
       cnt = keep;
-      push_batch(p, L, me, 0, nroots - keep, [&](uint32_t i) { return alloc_id(PS, ar, keep + i); }, wc);
+      auto root_id = [&](uint32_t i) { return alloc_id(PS, ar, keep + i); };
+      if (p.sched == kSchedCentral) central_push(p, L, me, nroots - keep, root_id, wc);
+      else push_batch(p, L, me, 0, nroots - keep, root_id, wc);
     }
   }
 
@@ -733,7 +838,18 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       ltop -= take;
       cnt += take;
     }
-    if (cnt < kWave) {
+    if (cnt < kWave && p.sched == kSchedCentral) {
+      const int32_t got = central_pop(p, me, cnt, tid, wc);
+      if (got < 0) break;
+      cnt += static_cast<uint32_t>(got);
+    } else if (cnt < kWave && p.sched == kSchedSingle) {
+      // non-batched: one task per pop, up to the free lanes
+      while (cnt < kWave) {
+        const uint32_t got = pop_batch(p, L, me, 0, cnt, tid, wc, 1);
+        if (got == 0) break;
+        cnt += got;
+      }
+    } else if (cnt < kWave) {
       uint32_t qp = cur_q;
       if (cnt == 0 && p.Q > 1) {
         qp = fullest_own_queue(p, L, me, daq_pressure);
@@ -745,7 +861,15 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     // partial batch rather than stealing, so it finishes its own subtrees
     // first (stealing new work instead grows the pending frontier breadth-first)
     const bool own_left = p.Q > 1 && cnt > 0 && ballot(ln < p.Q && L.hint[ln] != 0) != 0ull;
-    if (cnt < p.steal_below && p.nwaves > 1 && !own_left) {
+    if (cnt < p.steal_below && p.nwaves > 1 && !own_left && p.sched == kSchedSingle) {
+      // non-batched: one task per steal, until one fails or the lanes are full
+      while (cnt < kWave) {
+        uint32_t qs = 0;
+        const uint32_t got = steal_batch(p, me, rng, cnt, tid, qs, wc, 1);
+        if (got == 0) break;
+        cnt += got;
+      }
+    } else if (cnt < p.steal_below && p.nwaves > 1 && !own_left && p.sched == kSchedBatched) {
       uint32_t qs = cur_q;
       const uint32_t got = steal_batch(p, me, rng, cnt, tid, qs, wc);
       if (got > 0 && cnt == 0) cur_q = qs;
@@ -970,7 +1094,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     // ---- private stack (one queue): small children beyond the lanes stay in
     // LDS; the oldest entries are exposed when it would overflow, or when the
     // wavefront's own deque has run dry (thieves then find work) ----
-    const bool use_local = (p.Q == 1);
+    const bool use_local = (p.Q == 1) && !p.no_local;
     uint32_t E = 0, direct = 0, nsmall = 0;
     if (use_local) {
       nsmall = F - keep;  // every child beyond the lanes is a candidate
@@ -988,9 +1112,15 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     }
     const uint32_t nglob = use_local ? (F - keep) - (nsmall - direct) + E : 0u;
     bool room = true;
-    for (uint32_t qq = 0; qq < p.Q; ++qq) {
-      const uint32_t n = use_local ? nglob : L.qn[qq] - (qq == R ? keep : 0u);
-      if (n > 0) room = room && ensure_room(p, L, me, qq, n);
+    uint32_t cbase = 0;  // centralised queue: first reserved position
+    if (p.sched == kSchedCentral) {
+      const uint32_t n = L.qn[0] - keep;
+      if (n > 0) room = central_reserve(p, L, me, n, cbase);
+    } else {
+      for (uint32_t qq = 0; qq < p.Q; ++qq) {
+        const uint32_t n = use_local ? nglob : L.qn[qq] - (qq == R ? keep : 0u);
+        if (n > 0) room = room && ensure_room(p, L, me, qq, n);
+      }
     }
     if (!room) break;
     if (E > 0) {
@@ -1065,6 +1195,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         }
       }
       const bool keep_me = act && c == R && rank < keep;
+      uint32_t cput_pos = 0, cput_id = kNone;
       // small children beyond the lanes: the first `direct` go to the shared
       // deque, the rest onto the private stack
       const bool cand = use_local && act && !keep_me;
@@ -1108,8 +1239,20 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
           L.next_tid[nres + rank] = cid;
         } else if (!to_local) {
           const uint32_t pos = use_local ? gpos : rank - (c == R ? keep : 0u);
-          co_st32(deque_ring(p, me, c) + ((L.tail[c] + pos) & (p.cap - 1)), cid);
+          if (p.sched == kSchedCentral) {
+            cput_pos = cbase + pos;
+            cput_id = cid;
+          } else {
+            co_st32(deque_ring(p, me, c) + ((L.tail[c] + pos) & (p.cap - 1)), cid);
+          }
         }
+      }
+      // centralised queue: a claim may cover positions of pushes that have not
+      // raised count yet, so the slot write itself publishes the entry -- the
+      // frames it names complete first
+      if (p.sched == kSchedCentral && ballot(cput_id != kNone) != 0ull) {
+        drain();
+        if (cput_id != kNone) central_put(p, cput_pos, cput_id);
       }
     }
     if (!alloc_ok) break;
@@ -1123,7 +1266,9 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       // frames and ring slots written this iteration are complete before any
       // of them is published
       if (ballot(n > 0) != 0ull) drain();
-      if (n > 0) fetch_add_relaxed(&deque_meta(p, me, qq)->count, static_cast<int32_t>(n));
+      if (n > 0)
+        fetch_add_relaxed(p.sched == kSchedCentral ? &p.cq->count : &deque_meta(p, me, qq)->count,
+                          static_cast<int32_t>(n));
       wave_sync();
       if (n > 0) {
         L.tail[qq] += n;

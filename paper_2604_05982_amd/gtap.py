@@ -44,6 +44,11 @@ GTAP_DAQ_NONE = 0
 GTAP_DAQ_BY_KIND = 1
 GTAP_DAQ_KCLIQUE = 2
 
+# scheduler variants (config.flags): the scheduler comparison of Sec. 6.5
+GTAP_FLAG_NO_PRIVATE_STACK = 1
+GTAP_FLAG_SCHED_SINGLE = 2
+GTAP_FLAG_SCHED_CENTRAL = 4
+
 
 class gtap_config(ctypes.Structure):
     _fields_ = [

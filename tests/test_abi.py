@@ -57,3 +57,26 @@ def test_struct_layout_matches_header(tmp_path):
         assert int(got[st.__name__]) == ctypes.sizeof(st), st.__name__
         for name, _ in st._fields_:
             assert int(got[f"{st.__name__}.{name}"]) == getattr(st, name).offset, (st.__name__, name)
+
+
+def test_enum_values_match_header(tmp_path):
+    """Status codes, modes, kinds, DAQ policies and flags: the binding's
+    constants equal the header's enumerators."""
+    import subprocess
+    from paper_2604_05982_amd import gtap
+    text = open(os.path.join(ROOT, "include", "gtap.h")).read()
+    names = sorted(set(re.findall(r"\b(GTAP_[A-Z0-9_]+)\s*=", text)))
+    assert names
+    lines = ['#include <stdio.h>', '#include "gtap.h"', "int main(void){"]
+    lines += [f'printf("{n} %d\\n", (int){n});' for n in names]
+    lines.append("return 0;}")
+    src = tmp_path / "enums.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "enums"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                   check=True).stdout.splitlines())
+    missing = [n for n in names if not hasattr(gtap, n)]
+    assert not missing, missing
+    for n in names:
+        assert getattr(gtap, n) == int(got[n]), n
