@@ -183,8 +183,9 @@ typedef struct gtap_config {
 
 /* Scheduler variants for the comparison of thread-mode schedulers (Sec. 6.5,
  * "GPU-Side Scheduler Comparison"): all share the runtime and differ only in
- * queue management.  Thread mode, one queue, batch runs only (serving and
- * block mode reject them).
+ * queue management.  Thread mode, one queue, four wavefronts per group, batch
+ * runs only (serving and block mode reject them); each variant is its own
+ * kernel instantiation, so flags == 0 runs the scheduler unchanged.
  *   GTAP_FLAG_NO_PRIVATE_STACK  children beyond the 64 lanes go to the
  *                               wavefront's deque at once (no LDS stack), as
  *                               in the paper's Algorithm 1

@@ -146,7 +146,7 @@ struct alignas(128) CentralQueue {
   uint32_t head;      // next position to claim (pops)
   uint32_t pad2[31];
 };
-constexpr uint32_t kSchedBatched = 0, kSchedSingle = 1, kSchedCentral = 2;
+constexpr uint32_t kSchedBatched = 0, kSchedSingle = 1, kSchedCentral = 2, kSchedBatchedNoLocal = 3;
 
 struct Params {
   Control *ctl;
@@ -185,9 +185,8 @@ struct Params {
   uint32_t max_inflight;    // admitted and not completed
   uint32_t admit_headroom_small;  // frames that must stay free after admitting a job
   uint32_t admit_headroom_big;
-  // scheduler variant (kSched*) and the private LDS stack switch
+  // scheduler variant (kSched*; the kernel is instantiated per variant)
   uint32_t sched;
-  uint32_t no_local;
   CentralQueue *cq;         // kSchedCentral only
   uint64_t *cring;          // [ccap] tagged slots
   uint32_t ccap;            // power of two, 0 unless kSchedCentral

@@ -138,7 +138,8 @@ int validate(const gtap_config &c) {
   if (c.max_jobs < 1 || c.max_jobs > (1u << 24)) return GTAP_E_INVAL;
   const uint32_t known = GTAP_FLAG_NO_PRIVATE_STACK | GTAP_FLAG_SCHED_SINGLE | GTAP_FLAG_SCHED_CENTRAL;
   if (c.flags & ~known) return GTAP_E_INVAL;
-  if (c.flags && (c.mode != GTAP_MODE_THREAD || c.num_queues != 1)) return GTAP_E_INVAL;
+  // the comparison variants are built for four wavefronts per group only
+  if (c.flags && (c.mode != GTAP_MODE_THREAD || c.num_queues != 1 || c.waves_per_group != 4)) return GTAP_E_INVAL;
   if ((c.flags & GTAP_FLAG_SCHED_SINGLE) && (c.flags & GTAP_FLAG_SCHED_CENTRAL)) return GTAP_E_INVAL;
   return GTAP_OK;
 }
@@ -318,8 +319,10 @@ int gtap_init(const gtap_config *cfg, gtap_ctx **out) {
   p.daq_policy = static_cast<uint32_t>(c->cfg.daq_policy);
   for (uint32_t i = 0; i < kMaxQueues - 1; ++i) p.daq_bounds[i] = c->cfg.daq_bounds[i];
   const uint32_t fl = c->cfg.flags;
-  p.sched = (fl & GTAP_FLAG_SCHED_CENTRAL) ? kSchedCentral : (fl & GTAP_FLAG_SCHED_SINGLE) ? kSchedSingle : kSchedBatched;
-  p.no_local = (fl & (GTAP_FLAG_NO_PRIVATE_STACK | GTAP_FLAG_SCHED_SINGLE | GTAP_FLAG_SCHED_CENTRAL)) ? 1u : 0u;
+  p.sched = (fl & GTAP_FLAG_SCHED_CENTRAL)       ? kSchedCentral
+            : (fl & GTAP_FLAG_SCHED_SINGLE)      ? kSchedSingle
+            : (fl & GTAP_FLAG_NO_PRIVATE_STACK) ? kSchedBatchedNoLocal
+                                                 : kSchedBatched;
   p.ccap = c->lay.ccap;
   p.cq = p.ccap ? reinterpret_cast<CentralQueue *>(c->ws + c->lay.cq) : nullptr;
   p.cring = p.ccap ? reinterpret_cast<uint64_t *>(c->ws + c->lay.cring) : nullptr;
@@ -481,7 +484,20 @@ static int launch_sched(gtap_ctx *c) {
   switch (wpb) {
     case 1: hipLaunchKernelGGL(thread_sched_kernel<1>, grid, block, 0, c->stream, c->params); break;
     case 2: hipLaunchKernelGGL(thread_sched_kernel<2>, grid, block, 0, c->stream, c->params); break;
-    case 4: hipLaunchKernelGGL(thread_sched_kernel<4>, grid, block, 0, c->stream, c->params); break;
+    case 4:
+      switch (c->params.sched) {
+        case kSchedSingle:
+          hipLaunchKernelGGL((thread_sched_kernel<4, kSchedSingle>), grid, block, 0, c->stream, c->params);
+          break;
+        case kSchedCentral:
+          hipLaunchKernelGGL((thread_sched_kernel<4, kSchedCentral>), grid, block, 0, c->stream, c->params);
+          break;
+        case kSchedBatchedNoLocal:
+          hipLaunchKernelGGL((thread_sched_kernel<4, kSchedBatchedNoLocal>), grid, block, 0, c->stream, c->params);
+          break;
+        default: hipLaunchKernelGGL(thread_sched_kernel<4>, grid, block, 0, c->stream, c->params); break;
+      }
+      break;
     case 8: hipLaunchKernelGGL(thread_sched_kernel<8>, grid, block, 0, c->stream, c->params); break;
     default: return GTAP_E_INVAL;
   }

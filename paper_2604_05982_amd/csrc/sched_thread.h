@@ -711,8 +711,14 @@ struct LocalCap {
   static constexpr uint32_t v = WPB >= 8 ? 128u : 512u;
 };
 
-template <int WPB>
+// V selects the queue management (kSchedBatched, kSchedSingle, kSchedCentral;
+// kSchedBatchedNoLocal = batched without the private stack) at compile time,
+// so the comparison variants add nothing to the scheduler as designed.
+template <int WPB, uint32_t V = kSchedBatched>
 __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
+  constexpr bool kCentral = (V == kSchedCentral);
+  constexpr bool kSingle = (V == kSchedSingle);
+  constexpr bool kNoLocal = (V != kSchedBatched);
   __shared__ WaveLds lds_all[WPB];
   // Private task stack: children a wavefront cannot run in its lanes this
   // iteration stay here as frameless images and are popped (newest first)
@@ -765,7 +771,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       if (ln < keep) tid = alloc_id(PS, ar, ln);
       cnt = keep;
       auto root_id = [&](uint32_t i) { return alloc_id(PS, ar, keep + i); };
-      if (p.sched == kSchedCentral) central_push(p, L, me, nroots - keep, root_id, wc);
+      if constexpr (kCentral) central_push(p, L, me, nroots - keep, root_id, wc);
       else push_batch(p, L, me, 0, nroots - keep, root_id, wc);
     }
   }
@@ -838,11 +844,13 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       ltop -= take;
       cnt += take;
     }
-    if (cnt < kWave && p.sched == kSchedCentral) {
-      const int32_t got = central_pop(p, me, cnt, tid, wc);
-      if (got < 0) break;
-      cnt += static_cast<uint32_t>(got);
-    } else if (cnt < kWave && p.sched == kSchedSingle) {
+    if constexpr (kCentral) {
+      if (cnt < kWave) {
+        const int32_t got = central_pop(p, me, cnt, tid, wc);
+        if (got < 0) break;
+        cnt += static_cast<uint32_t>(got);
+      }
+    } else if constexpr (kSingle) {
       // non-batched: one task per pop, up to the free lanes
       while (cnt < kWave) {
         const uint32_t got = pop_batch(p, L, me, 0, cnt, tid, wc, 1);
@@ -861,15 +869,17 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     // partial batch rather than stealing, so it finishes its own subtrees
     // first (stealing new work instead grows the pending frontier breadth-first)
     const bool own_left = p.Q > 1 && cnt > 0 && ballot(ln < p.Q && L.hint[ln] != 0) != 0ull;
-    if (cnt < p.steal_below && p.nwaves > 1 && !own_left && p.sched == kSchedSingle) {
+    if constexpr (kSingle) {
       // non-batched: one task per steal, until one fails or the lanes are full
-      while (cnt < kWave) {
-        uint32_t qs = 0;
-        const uint32_t got = steal_batch(p, me, rng, cnt, tid, qs, wc, 1);
-        if (got == 0) break;
-        cnt += got;
+      if (cnt < p.steal_below && p.nwaves > 1) {
+        while (cnt < kWave) {
+          uint32_t qs = 0;
+          const uint32_t got = steal_batch(p, me, rng, cnt, tid, qs, wc, 1);
+          if (got == 0) break;
+          cnt += got;
+        }
       }
-    } else if (cnt < p.steal_below && p.nwaves > 1 && !own_left && p.sched == kSchedBatched) {
+    } else if (!kCentral && cnt < p.steal_below && p.nwaves > 1 && !own_left) {
       uint32_t qs = cur_q;
       const uint32_t got = steal_batch(p, me, rng, cnt, tid, qs, wc);
       if (got > 0 && cnt == 0) cur_q = qs;
@@ -1094,7 +1104,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     // ---- private stack (one queue): small children beyond the lanes stay in
     // LDS; the oldest entries are exposed when it would overflow, or when the
     // wavefront's own deque has run dry (thieves then find work) ----
-    const bool use_local = (p.Q == 1) && !p.no_local;
+    const bool use_local = !kNoLocal && (p.Q == 1);
     uint32_t E = 0, direct = 0, nsmall = 0;
     if (use_local) {
       nsmall = F - keep;  // every child beyond the lanes is a candidate
@@ -1113,7 +1123,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     const uint32_t nglob = use_local ? (F - keep) - (nsmall - direct) + E : 0u;
     bool room = true;
     uint32_t cbase = 0;  // centralised queue: first reserved position
-    if (p.sched == kSchedCentral) {
+    if constexpr (kCentral) {
       const uint32_t n = L.qn[0] - keep;
       if (n > 0) room = central_reserve(p, L, me, n, cbase);
     } else {
@@ -1239,7 +1249,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
           L.next_tid[nres + rank] = cid;
         } else if (!to_local) {
           const uint32_t pos = use_local ? gpos : rank - (c == R ? keep : 0u);
-          if (p.sched == kSchedCentral) {
+          if constexpr (kCentral) {
             cput_pos = cbase + pos;
             cput_id = cid;
           } else {
@@ -1250,9 +1260,11 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       // centralised queue: a claim may cover positions of pushes that have not
       // raised count yet, so the slot write itself publishes the entry -- the
       // frames it names complete first
-      if (p.sched == kSchedCentral && ballot(cput_id != kNone) != 0ull) {
-        drain();
-        if (cput_id != kNone) central_put(p, cput_pos, cput_id);
+      if constexpr (kCentral) {
+        if (ballot(cput_id != kNone) != 0ull) {
+          drain();
+          if (cput_id != kNone) central_put(p, cput_pos, cput_id);
+        }
       }
     }
     if (!alloc_ok) break;
@@ -1267,8 +1279,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       // of them is published
       if (ballot(n > 0) != 0ull) drain();
       if (n > 0)
-        fetch_add_relaxed(p.sched == kSchedCentral ? &p.cq->count : &deque_meta(p, me, qq)->count,
-                          static_cast<int32_t>(n));
+        fetch_add_relaxed(kCentral ? &p.cq->count : &deque_meta(p, me, qq)->count, static_cast<int32_t>(n));
       wave_sync();
       if (n > 0) {
         L.tail[qq] += n;

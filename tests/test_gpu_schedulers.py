@@ -110,6 +110,7 @@ def test_variant_configs_rejected(gtap):
     bad = [dict(flags=gtap.GTAP_FLAG_SCHED_SINGLE | gtap.GTAP_FLAG_SCHED_CENTRAL),
            dict(flags=gtap.GTAP_FLAG_SCHED_CENTRAL, num_queues=4),
            dict(flags=gtap.GTAP_FLAG_SCHED_SINGLE, mode=gtap.GTAP_MODE_BLOCK, waves_per_group=1),
+           dict(flags=gtap.GTAP_FLAG_NO_PRIVATE_STACK, waves_per_group=2),
            dict(flags=8)]
     for kw in bad:
         with pytest.raises(gtap.GtapError) as e:
