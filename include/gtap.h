@@ -59,7 +59,8 @@ enum gtap_kind {
     GTAP_KIND_NQUEENS = 2,  /* gtap_nqueens_args                               */
     GTAP_KIND_UTS = 3,      /* gtap_uts_args                                   */
     GTAP_KIND_KCLIQUE = 4,  /* gtap_kclique_args                               */
-    GTAP_KIND_FMM = 5       /* gtap_fmm_args (block mode only)                 */
+    GTAP_KIND_FMM = 5       /* gtap_fmm_args (traversal TASKS: block mode;
+                               LISTS, WORKLIST: thread mode)                  */
 };
 
 /* Fibonacci with a task at every call (Sec. 6.3, microbenchmarks): result is
@@ -118,8 +119,28 @@ typedef struct {
     int32_t theta_num;
     int32_t theta_den;
     int32_t order;
-    int32_t reserved;
+    int32_t traversal;       /* gtap_fmm_traversal                            */
+    uint64_t m2l_capacity;   /* LISTS / WORKLIST: list capacities in pairs     */
+    uint64_t p2p_capacity;   /*   (0 = estimated from the tree and theta)      */
 } gtap_fmm_args;
+
+/* How an FMM job's dual-tree traversal runs.
+ *   GTAP_FMM_TASKS     block mode: every cell-pair task does its M2L or
+ *                      workgroup-wide P2P itself (the description above)
+ *   GTAP_FMM_LISTS     thread mode, as in the paper's FMM pipeline: the
+ *                      cell-pair tasks only append accepted pairs to an M2L
+ *                      list and leaf pairs to a P2P list (fixed-capacity
+ *                      arrays, one atomic add per wavefront and list); the
+ *                      lists are then sorted by target and evaluated by
+ *                      data-parallel M2L and P2P kernels
+ *   GTAP_FMM_WORKLIST  thread mode, the level-synchronous GPU worklist
+ *                      baseline of the same section: ping-pong frontiers of
+ *                      cell pairs, one kernel launch and one host
+ *                      synchronisation per frontier, the same lists and
+ *                      evaluation kernels (its root task is empty)
+ * Lists that overflow their capacity are counted to the end; the library then
+ * re-runs the traversal once with capacities that fit (list_retries). */
+enum gtap_fmm_traversal { GTAP_FMM_TASKS = 0, GTAP_FMM_LISTS = 1, GTAP_FMM_WORKLIST = 2 };
 
 /* What gtap_result returns for an FMM job (out_bytes >= its size).  The pair
  * hashes are wrapping sums of splitmix64((A << 32) | B) over the (target cell,
@@ -136,8 +157,15 @@ typedef struct {
     int64_t coincident;        /* of those, distinct points at the same place */
     double tree_ms;            /* sort and octree construction               */
     double upward_ms;          /* P2M and M2M                                */
-    double traversal_ms;       /* the block-mode launch (shared by the run's jobs) */
+    double traversal_ms;       /* TASKS, LISTS: the scheduler launch (shared by
+                                  the run's jobs); WORKLIST: its kernels and
+                                  host loop                                   */
     double downward_ms;        /* L2L, L2P and the scatter to phi_dev        */
+    double sort_ms;            /* LISTS, WORKLIST: sorting the lists by target */
+    double m2l_ms;             /*   M2L list evaluation                      */
+    double p2p_ms;             /*   P2P list evaluation                      */
+    int64_t dtt_rounds;        /* WORKLIST: frontier launches                */
+    int64_t list_retries;      /* traversals re-run after a list overflowed   */
 } gtap_fmm_result;
 
 /* ---- configuration -------------------------------------------------------- */

@@ -108,6 +108,11 @@ struct FmmDesc {
   double *phi;             // potentials in sorted order (accumulated)
   int64_t ta, tb;          // MAC theta = ta / tb
   uint64_t m2l_pairs, p2p_pairs, m2l_hash, p2p_hash, p2p_inter, coincident;
+  // interaction lists (list-building traversals): (target << 32 | source)
+  // pairs, appended at m2l_n / p2p_n, which keep counting past the capacity
+  uint64_t *m2l_list, *p2p_list;
+  uint64_t m2l_cap, p2p_cap;
+  uint64_t m2l_n, p2p_n;
 };
 
 GTAP_DEV double cell_centre(int32_t anchor, int32_t level) {

@@ -1,0 +1,300 @@
+// fmm_lists.h -- the FMM pipeline of GTaP Sec. 6.4.1: the dual-tree traversal
+// only builds interaction lists (well-separated cell pairs for M2L, leaf
+// pairs for P2P) in fixed-capacity arrays appended with atomic adds; the lists
+// are then evaluated by data-parallel kernels.  Two traversals build them:
+// thread-mode tasks of the runtime (one cell pair per task, see tasks.h) and a
+// level-synchronous worklist (ping-pong frontiers, one launch per frontier).
+//
+// MI355X choices: appends are aggregated per wavefront (one atomic per
+// wavefront and list); the lists are sorted by target cell so that one
+// workgroup owns a target and adds its result once, without atomics; M2L
+// stages 32 sources at a time in LDS (Taylor coefficients and moments) and
+// spreads the 924 (target, source) coefficient terms over 256 threads, each
+// accumulating its terms across all sources in registers.
+#pragma once
+#include "fmm.h"
+#include "wave.h"
+
+namespace gtap {
+namespace fmm {
+
+// The cell-pair decision, the same in every traversal (the oracle's rule):
+// 1 = accepted by the MAC (M2L), 2 = two leaves (P2P), 0 = split the wider
+// cell (on equal levels the target unless it is a leaf; never a leaf), with
+// split_a telling which.
+GTAP_DEV uint32_t dtt_decide(const int32_t *A, const int32_t *B, int64_t ta, int64_t tb, bool &split_a) {
+  split_a = false;
+  if (mac_accept(A, B, ta, tb)) return 1;
+  if (A[7] == 0 && B[7] == 0) return 2;
+  bool s = A[0] < B[0] ? true : (A[0] > B[0] ? false : A[7] != 0);
+  if (s && A[7] == 0) s = false;
+  if (!s && B[7] == 0) s = true;
+  split_a = s;
+  return 0;
+}
+
+GTAP_DEV uint64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), lane));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v >> 32)), lane));
+  return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32);
+}
+
+// Append `pair` to list `which` (0 = M2L, 1 = P2P) of each active lane's
+// descriptor: one atomic add per wavefront and descriptor.  Entries past the
+// capacity are counted but not stored.  Every lane of the wavefront calls it.
+GTAP_DEV void list_append(FmmDesc *D, uint32_t which, bool act, uint64_t pair) {
+  uint64_t m = ballot(act);
+  while (m != 0ull) {
+    const int leader = __ffsll(static_cast<long long>(m)) - 1;
+    const uint64_t dl = readlane64(reinterpret_cast<uint64_t>(D), leader);
+    const bool same = act && reinterpret_cast<uint64_t>(D) == dl;
+    const uint64_t ms = ballot(same);
+    uint64_t base = 0;
+    if (static_cast<int>(lane_id()) == leader)
+      base = fetch_add_relaxed(which ? &D->p2p_n : &D->m2l_n, static_cast<uint64_t>(__popcll(ms)));
+    base = readlane64(base, leader);
+    if (same) {
+      const uint64_t idx = base + rank_below(ms);
+      if (idx < (which ? D->p2p_cap : D->m2l_cap)) (which ? D->p2p_list : D->m2l_list)[idx] = pair;
+    }
+    m &= ~ms;
+  }
+}
+
+GTAP_DEV void load_cell(const int32_t *cell, uint32_t c, int32_t *C) {
+  const int4 *p = reinterpret_cast<const int4 *>(cell + static_cast<size_t>(c) * kCellInts);
+  const int4 u = p[0], v = p[1];
+  C[0] = u.x; C[1] = u.y; C[2] = u.z; C[3] = u.w;
+  C[4] = v.x; C[5] = v.y; C[6] = v.z; C[7] = v.w;
+}
+
+// ---- level-synchronous worklist traversal ------------------------------------
+// One thread per pair of the frontier: accepted pairs and leaf pairs go to the
+// lists, the child pairs of a split go to the next frontier (one atomic add per
+// wavefront).  *nout keeps counting past cap_out.
+__global__ __launch_bounds__(256) void k_dtt_frontier(FmmDesc *D, const uint64_t *fin, uint64_t nin, uint64_t *fout,
+                                                      uint64_t *nout, uint64_t cap_out) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool act = i < nin;
+  uint64_t pair = 0;
+  uint32_t dec = 3, k = 0, child0 = 0, a = 0, b = 0;
+  bool split_a = false;
+  if (act) {
+    pair = fin[i];
+    a = static_cast<uint32_t>(pair >> 32);
+    b = static_cast<uint32_t>(pair);
+    int32_t A[kCellInts], B[kCellInts];
+    load_cell(D->cell, a, A);
+    load_cell(D->cell, b, B);
+    dec = dtt_decide(A, B, D->ta, D->tb, split_a);
+    if (dec == 0) {
+      k = static_cast<uint32_t>(split_a ? A[7] : B[7]);
+      child0 = static_cast<uint32_t>(split_a ? A[6] : B[6]);
+    }
+  }
+  list_append(D, 0, dec == 1, pair);
+  list_append(D, 1, dec == 2, pair);
+  uint32_t total = 0;
+  const uint32_t off = wave_exclusive_scan(k, &total);
+  uint64_t base = 0;
+  if (lane_id() == 0 && total) base = fetch_add_relaxed(nout, static_cast<uint64_t>(total));
+  base = readlane64(base, 0);
+  for (uint32_t j = 0; j < k; ++j) {
+    const uint64_t at = base + off + j;
+    const uint32_t c = child0 + j;
+    if (at < cap_out) fout[at] = split_a ? ((static_cast<uint64_t>(c) << 32) | b) : ((static_cast<uint64_t>(a) << 32) | c);
+  }
+}
+
+// ---- list evaluation ------------------------------------------------------------
+// Segment [lo[a], hi[a]) of target a in a list sorted by target (both zeroed
+// beforehand, so targets without pairs have empty segments).
+__global__ void k_list_segments(const uint64_t *pairs, uint64_t n, uint64_t *lo, uint64_t *hi) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t a = static_cast<uint32_t>(pairs[i] >> 32);
+  if (i == 0 || static_cast<uint32_t>(pairs[i - 1] >> 32) != a) lo[a] = i;
+  if (i + 1 == n || static_cast<uint32_t>(pairs[i + 1] >> 32) != a) hi[a] = i + 1;
+}
+
+// Order-independent wrapping sum of pair hashes of a list (the oracle's check).
+__global__ __launch_bounds__(256) void k_list_hash(const uint64_t *pairs, uint64_t n, uint64_t *out) {
+  uint64_t h = 0;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    h += pair_hash(static_cast<uint32_t>(pairs[i] >> 32), static_cast<uint32_t>(pairs[i]));
+  h = readlane64(wave_inclusive_sum64(h), 63);
+  if (lane_id() == 0 && h) fetch_add_relaxed(out, h);
+}
+
+// Taylor coefficients T_g of 1/|d + h| at h = 0, total degree <= 6, by the
+// Coulomb three-term recurrence, fully unrolled so that T stays in registers.
+GTAP_DEV void taylor_coeffs(double d0, double d1, double d2, double *T) {
+  const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+  const double inv_r2 = 1.0 / r2;
+  T[0] = sqrt(inv_r2);
+  const double dd[3] = {d0, d1, d2};
+#pragma unroll
+  for (int t = 1; t < kNc; ++t) {
+    const double deg = static_cast<double>(kTab.deg[t]);
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const uint8_t m1 = kTab.dm1[t][i], m2 = kTab.dm2[t][i];
+      if (m1 != 0xFF) s1 += dd[i] * T[m1];
+      if (m2 != 0xFF) s2 += T[m2];
+    }
+    T[t] = -((2.0 * deg - 1.0) * s1 + (deg - 1.0) * s2) * inv_r2 / deg;
+  }
+}
+
+constexpr uint32_t kM2LThreads = 256;
+constexpr uint32_t kM2LChunk = 32;
+constexpr uint32_t kM2LPer = (kM2LTerms + kM2LThreads - 1) / kM2LThreads;  // 4 terms per thread
+
+// M2L over the sorted list: workgroup = target cell a.  Per chunk of 32
+// sources, thread s < 32 computes source s's Taylor coefficients while all
+// threads stage the chunk's moments; then every thread adds its 4 terms
+// C(a+b, a) (-1)^|b| T_{a+b} Q_b over the chunk.  L[a] receives the sum once.
+__global__ __launch_bounds__(kM2LThreads) void k_m2l_list(const int32_t *cell, const double *Q, double *L,
+                                                          const uint64_t *pairs, const uint64_t *seg_lo,
+                                                          const uint64_t *seg_hi) {
+  const uint32_t a = blockIdx.x;
+  const uint64_t lo = seg_lo[a], hi = seg_hi[a];
+  if (lo == hi) return;
+  __shared__ double sT[kM2LChunk][kNc + 1];
+  __shared__ double sQ[kM2LChunk][kNc + 1];
+  __shared__ double lacc[kNc];
+  const uint32_t tx = threadIdx.x;
+  if (tx < static_cast<uint32_t>(kNc)) lacc[tx] = 0.0;
+  int32_t A[kCellInts];
+  load_cell(cell, a, A);
+  const double cx = cell_centre(A[1], A[0]), cy = cell_centre(A[2], A[0]), cz = cell_centre(A[3], A[0]);
+  // this thread's terms [tx * 4, tx * 4 + 4)
+  double coef[kM2LPer], acc[kM2LPer];
+  uint32_t tg[kM2LPer], tb[kM2LPer], ta[kM2LPer];
+#pragma unroll
+  for (uint32_t r = 0; r < kM2LPer; ++r) {
+    const uint32_t m = tx * kM2LPer + r;
+    acc[r] = 0.0;
+    coef[r] = 0.0;
+    tg[r] = tb[r] = 0;
+    ta[r] = 0xFFu;
+    if (m < static_cast<uint32_t>(kM2LTerms)) {
+      coef[r] = kTab.m2l_c[m];
+      tg[r] = kTab.m2l_g[m];
+      tb[r] = kTab.m2l_b[m];
+      uint32_t t = 0;
+      while (kTab.m2l_first[t + 1] <= m) ++t;
+      ta[r] = t;
+    }
+  }
+  for (uint64_t s0 = lo; s0 < hi; s0 += kM2LChunk) {
+    const uint32_t ns = static_cast<uint32_t>(hi - s0 < kM2LChunk ? hi - s0 : kM2LChunk);
+    __syncthreads();  // the previous chunk's terms are done
+    for (uint32_t idx = tx; idx < ns * static_cast<uint32_t>(kNc); idx += kM2LThreads) {
+      const uint32_t s = idx / kNc, t = idx % kNc;
+      const uint32_t b = static_cast<uint32_t>(pairs[s0 + s]);
+      sQ[s][t] = Q[static_cast<size_t>(b) * kNc + t];
+    }
+    if (tx < ns) {
+      const uint32_t b = static_cast<uint32_t>(pairs[s0 + tx]);
+      int32_t B[kCellInts];
+      load_cell(cell, b, B);
+      double T[kNc];
+      taylor_coeffs(cx - cell_centre(B[1], B[0]), cy - cell_centre(B[2], B[0]), cz - cell_centre(B[3], B[0]), T);
+#pragma unroll
+      for (int t = 0; t < kNc; ++t) sT[tx][t] = T[t];
+    }
+    __syncthreads();
+    for (uint32_t s = 0; s < ns; ++s) {
+#pragma unroll
+      for (uint32_t r = 0; r < kM2LPer; ++r) acc[r] += coef[r] * sT[s][tg[r]] * sQ[s][tb[r]];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t r = 0; r < kM2LPer; ++r)
+    if (ta[r] != 0xFFu) atomicAdd(&lacc[ta[r]], acc[r]);
+  __syncthreads();
+  if (tx < static_cast<uint32_t>(kNc)) L[static_cast<size_t>(a) * kNc + tx] += lacc[tx];
+}
+
+constexpr uint32_t kP2PThreads = 128;
+constexpr uint32_t kP2PTileL = 64;
+
+// P2P over the sorted list: workgroup = target leaf a; thread = (target
+// tx mod 64, source group tx / 64); sources staged 64 points at a time.
+// phi[i] receives the sum once; interactions and coincident pairs are counted.
+__global__ __launch_bounds__(kP2PThreads) void k_p2p_list(const int32_t *cell, const double *px, const double *py,
+                                                          const double *pz, const double *pq, double *phi,
+                                                          const uint64_t *pairs, const uint64_t *seg_lo,
+                                                          const uint64_t *seg_hi, uint64_t *inter_out,
+                                                          uint64_t *coinc_out) {
+  const uint32_t a = blockIdx.x;
+  const uint64_t lo = seg_lo[a], hi = seg_hi[a];
+  if (lo == hi) return;
+  constexpr uint32_t G = kP2PThreads / kP2PTileL;
+  __shared__ double sx[kP2PTileL], sy[kP2PTileL], sz[kP2PTileL], sq[kP2PTileL];
+  __shared__ double red[kP2PThreads];
+  const uint32_t tx = threadIdx.x;
+  int32_t A[kCellInts];
+  load_cell(cell, a, A);
+  const int32_t ab = A[4], ae = A[5];
+  uint64_t coinc = 0, inter = 0;
+  for (int32_t t0 = ab; t0 < ae; t0 += kP2PTileL) {
+    const int32_t i = t0 + static_cast<int32_t>(tx % kP2PTileL);
+    const bool live = i < ae;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    if (live) {
+      xi = px[i];
+      yi = py[i];
+      zi = pz[i];
+    }
+    double acc = 0.0;
+    for (uint64_t s = lo; s < hi; ++s) {
+      const uint32_t b = static_cast<uint32_t>(pairs[s]);
+      int32_t B[kCellInts];
+      load_cell(cell, b, B);
+      const int32_t bb = B[4], be = B[5];
+      if (t0 == ab && tx == 0) inter += static_cast<uint64_t>(static_cast<int64_t>(ae - ab) * (be - bb) - (a == b ? ae - ab : 0));
+      for (int32_t s0 = bb; s0 < be; s0 += kP2PTileL) {
+        const int32_t nsrc = min(static_cast<int32_t>(kP2PTileL), be - s0);
+        __syncthreads();
+        if (tx < static_cast<uint32_t>(nsrc)) {
+          sx[tx] = px[s0 + tx];
+          sy[tx] = py[s0 + tx];
+          sz[tx] = pz[s0 + tx];
+          sq[tx] = pq[s0 + tx];
+        }
+        __syncthreads();
+        if (live)
+          for (int32_t j = static_cast<int32_t>(tx / kP2PTileL); j < nsrc; j += G) {
+            if (s0 + j == i) continue;
+            const double dx = xi - sx[j], dy = yi - sy[j], dz = zi - sz[j];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) {
+              ++coinc;
+              continue;
+            }
+            acc += sq[j] / sqrt(r2);
+          }
+      }
+    }
+    __syncthreads();
+    red[tx] = acc;
+    __syncthreads();
+    if (tx < kP2PTileL && live) {
+      double sum = 0.0;
+#pragma unroll
+      for (uint32_t g = 0; g < G; ++g) sum += red[tx + g * kP2PTileL];
+      phi[i] += sum;
+    }
+  }
+  if (tx == 0 && inter) fetch_add_relaxed(inter_out, inter);
+  coinc = readlane64(wave_inclusive_sum64(coinc), 63);
+  if (lane_id() == 0 && coinc) fetch_add_relaxed(coinc_out, coinc);
+}
+
+}  // namespace fmm
+}  // namespace gtap

@@ -61,6 +61,7 @@ enum TaskKind : uint32_t {
   TK_KC_VERTEX = 5,
   TK_KC_CAND = 6,
   TK_FMM = 7,       // block mode: FMM cell pair (A, B)
+  TK_DTT = 8,       // thread mode: FMM cell pair (A, B) that only builds the interaction lists
 };
 
 struct alignas(128) DequeMeta {

@@ -19,6 +19,7 @@
 
 #include "../../include/gtap.h"
 #include "fmm.h"
+#include "fmm_lists.h"
 #include "layout.h"
 #include "sched_block.h"
 #include "sched_thread.h"
@@ -348,7 +349,6 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
   J.kind = static_cast<uint32_t>(kind);
   const bool block = c->cfg.mode == GTAP_MODE_BLOCK;
   if (block && kind != GTAP_KIND_FIB && kind != GTAP_KIND_UTS && kind != GTAP_KIND_FMM) return GTAP_E_INVAL;
-  if (!block && kind == GTAP_KIND_FMM) return GTAP_E_INVAL;
   switch (kind) {
     case GTAP_KIND_FIB: {
       if (args_bytes != sizeof(gtap_fib_args)) return GTAP_E_INVAL;
@@ -404,6 +404,13 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
       if (a.n < 1 || !a.x_dev || !a.y_dev || !a.z_dev || !a.q_dev || !a.phi_dev) return GTAP_E_INVAL;
       if (a.leaf_max < 1 || a.leaf_max > 64 || a.order != fmm::kP) return GTAP_E_INVAL;
       if (a.theta_num < 0 || a.theta_den < 1 || a.theta_den > 64 || a.theta_num > a.theta_den) return GTAP_E_INVAL;
+      // traversal with the work inside the tasks: block mode; list-building
+      // traversals: thread mode (its FMM kernel is built for four wavefronts
+      // per group, without the comparison variants)
+      if (block ? a.traversal != GTAP_FMM_TASKS
+                : (a.traversal != GTAP_FMM_LISTS && a.traversal != GTAP_FMM_WORKLIST) ||
+                      c->cfg.waves_per_group != 4 || c->cfg.flags != 0)
+        return GTAP_E_INVAL;
       return GTAP_OK;  // the device descriptor is built by gtap_run
     }
     default:
@@ -469,7 +476,7 @@ static int record_run(gtap_ctx *c, const Control &ctl, float ms) {
   return GTAP_OK;
 }
 
-static int launch_sched(gtap_ctx *c) {
+static int launch_sched(gtap_ctx *c, bool fmm_lists = false) {
   const uint32_t wpb = static_cast<uint32_t>(c->cfg.waves_per_group);
   const dim3 grid(c->nwaves / wpb), block(64 * wpb);
   if (c->cfg.mode == GTAP_MODE_BLOCK) {
@@ -495,7 +502,12 @@ static int launch_sched(gtap_ctx *c) {
         case kSchedBatchedNoLocal:
           hipLaunchKernelGGL((thread_sched_kernel<4, kSchedBatchedNoLocal>), grid, block, 0, c->stream, c->params);
           break;
-        default: hipLaunchKernelGGL(thread_sched_kernel<4>, grid, block, 0, c->stream, c->params); break;
+        default:
+          if (fmm_lists)
+            hipLaunchKernelGGL((thread_sched_kernel<4, kSchedBatched, true>), grid, block, 0, c->stream, c->params);
+          else
+            hipLaunchKernelGGL(thread_sched_kernel<4>, grid, block, 0, c->stream, c->params);
+          break;
       }
       break;
     case 8: hipLaunchKernelGGL(thread_sched_kernel<8>, grid, block, 0, c->stream, c->params); break;
@@ -522,14 +534,27 @@ struct FmmJobMem {
   std::vector<std::pair<int32_t, int32_t>> levels;
   int32_t ncells = 0;
   hipEvent_t ev[6] = {};
+  // list-building traversals
+  uint64_t *m2l = nullptr, *p2p = nullptr;
+  uint64_t m2l_cap = 0, p2p_cap = 0;
+  uint64_t *front = nullptr;   // two frontiers of front_cap pairs, then the counter
+  uint64_t front_cap = 0;
+  int64_t rounds = 0, retries = 0;
+  float worklist_ms = 0.f;
+  hipEvent_t lev[8] = {};
+  fmm::FmmDesc hdesc{};        // host copy of the descriptor (lists, capacities)
+  uint64_t *seg = nullptr, *sorted = nullptr;
+  void *lsort_tmp = nullptr;
 };
 
 void fmm_free(FmmJobMem &m) {
   void *ptrs[] = {m.keys, m.keys_sorted, m.idx, m.perm, m.sort_tmp, m.pts, m.cell, m.parent, m.scratch,
-                  m.Q, m.L, m.desc};
+                  m.Q, m.L, m.desc, m.m2l, m.p2p, m.front, m.seg, m.sorted, m.lsort_tmp};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   for (hipEvent_t &e : m.ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t &e : m.lev)
     if (e) (void)hipEventDestroy(e);
   m = FmmJobMem{};
 }
@@ -540,6 +565,23 @@ bool dev_alloc(T **p, size_t count) {
 }
 
 unsigned nblk(int64_t n, unsigned b) { return static_cast<unsigned>(std::max<int64_t>((n + b - 1) / b, 1)); }
+
+// Interaction-list capacities: the caller's, else an estimate from the number
+// of cells and theta (about 200 M2L and 30 P2P pairs per cell at theta = 1,
+// growing as theta^-3; every leaf pair when theta = 0).
+void fmm_list_caps(const gtap_fmm_args &a, int32_t ncells, uint64_t &m2l, uint64_t &p2p) {
+  const double nc = static_cast<double>(ncells);
+  double em = 0.0, ep = nc * nc;
+  if (a.theta_num > 0) {
+    const double s = static_cast<double>(a.theta_den) / a.theta_num;
+    em = nc * 200.0 * s * s * s;
+    ep = nc * 30.0 * s * s * s;
+  }
+  em = std::min(std::max(em, 65536.0), 4.0e9);
+  ep = std::min(std::max(ep, 65536.0), 4.0e9);
+  m2l = a.m2l_capacity ? a.m2l_capacity : static_cast<uint64_t>(em);
+  p2p = a.p2p_capacity ? a.p2p_capacity : static_cast<uint64_t>(ep);
+}
 
 // Sort, octree, P2M and M2M of one FMM job; fills the device descriptor.
 int fmm_prepare(gtap_ctx *c, const gtap_fmm_args &a, FmmJobMem &m) {
@@ -633,11 +675,175 @@ int fmm_prepare(gtap_ctx *c, const gtap_fmm_args &a, FmmJobMem &m) {
   d.phi = phi;
   d.ta = a.theta_num;
   d.tb = a.theta_den;
+  if (a.traversal != GTAP_FMM_TASKS) {
+    fmm_list_caps(a, m.ncells, m.m2l_cap, m.p2p_cap);
+    if (!dev_alloc(&m.m2l, m.m2l_cap) || !dev_alloc(&m.p2p, m.p2p_cap)) return GTAP_E_NOMEM;
+    d.m2l_list = m.m2l;
+    d.p2p_list = m.p2p;
+    d.m2l_cap = m.m2l_cap;
+    d.p2p_cap = m.p2p_cap;
+  }
+  m.hdesc = d;
   if (!dev_alloc(&m.desc, 1)) return GTAP_E_NOMEM;
   if (hipMemcpyAsync(m.desc, &d, sizeof(d), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return GTAP_E_HIP;
   return hipGetLastError() == hipSuccess ? GTAP_OK : GTAP_E_HIP;
+}
+
+// Give the lists room for need_m2l / need_p2p pairs (plus a quarter), clear
+// their counters and the descriptor's statistics.
+int fmm_grow_lists(gtap_ctx *c, FmmJobMem &m, uint64_t need_m2l, uint64_t need_p2p) {
+  if (need_m2l > m.m2l_cap) {
+    (void)hipFree(m.m2l);
+    m.m2l = nullptr;
+    m.m2l_cap = need_m2l + need_m2l / 4 + 1024;
+    if (!dev_alloc(&m.m2l, m.m2l_cap)) return GTAP_E_NOMEM;
+  }
+  if (need_p2p > m.p2p_cap) {
+    (void)hipFree(m.p2p);
+    m.p2p = nullptr;
+    m.p2p_cap = need_p2p + need_p2p / 4 + 1024;
+    if (!dev_alloc(&m.p2p, m.p2p_cap)) return GTAP_E_NOMEM;
+  }
+  fmm::FmmDesc &d = m.hdesc;
+  d.m2l_list = m.m2l;
+  d.p2p_list = m.p2p;
+  d.m2l_cap = m.m2l_cap;
+  d.p2p_cap = m.p2p_cap;
+  d.m2l_n = d.p2p_n = 0;
+  d.m2l_pairs = d.p2p_pairs = d.m2l_hash = d.p2p_hash = d.p2p_inter = d.coincident = 0;
+  if (hipMemcpyAsync(m.desc, &d, sizeof(d), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return GTAP_E_HIP;
+  return GTAP_OK;
+}
+
+// The list counters after a traversal (they count past the capacities).
+int fmm_list_counts(gtap_ctx *c, const FmmJobMem &m, uint64_t &n_m2l, uint64_t &n_p2p) {
+  uint64_t v[2] = {0, 0};
+  static_assert(offsetof(fmm::FmmDesc, p2p_n) == offsetof(fmm::FmmDesc, m2l_n) + sizeof(uint64_t), "counters");
+  if (hipMemcpyAsync(v, &m.desc->m2l_n, sizeof(v), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return GTAP_E_HIP;
+  n_m2l = v[0];
+  n_p2p = v[1];
+  return GTAP_OK;
+}
+
+// Level-synchronous worklist traversal (the GPU baseline of Sec. 6.4.1): one
+// launch per frontier, the host reads the next frontier's size after each.
+// A frontier or list overflow re-runs it with room to spare.
+int fmm_worklist(gtap_ctx *c, FmmJobMem &m) {
+  hipStream_t st = c->stream;
+  for (hipEvent_t &e : m.lev)
+    if (!e && hipEventCreate(&e) != hipSuccess) return GTAP_E_HIP;
+  if (!m.front) {
+    m.front_cap = std::max<uint64_t>(1u << 20, (m.m2l_cap + m.p2p_cap) / 8);
+    if (!dev_alloc(&m.front, 2 * m.front_cap + 1)) return GTAP_E_NOMEM;
+  }
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    if (hipEventRecord(m.lev[0], st) != hipSuccess) return GTAP_E_HIP;
+    if (hipMemsetAsync(m.front, 0, sizeof(uint64_t), st) != hipSuccess) return GTAP_E_HIP;  // pair (root, root)
+    uint64_t nin = 1, nout = 0;
+    int64_t rounds = 0;
+    bool over = false;
+    while (nin > 0) {
+      uint64_t *fin = m.front + (rounds & 1) * m.front_cap, *fout = m.front + ((rounds + 1) & 1) * m.front_cap;
+      uint64_t *cnt = m.front + 2 * m.front_cap;
+      if (hipMemsetAsync(cnt, 0, sizeof(uint64_t), st) != hipSuccess) return GTAP_E_HIP;
+      hipLaunchKernelGGL(fmm::k_dtt_frontier, dim3(static_cast<unsigned>((nin + 255) / 256)), dim3(256), 0, st,
+                         m.desc, fin, nin, fout, cnt, m.front_cap);
+      if (hipMemcpyAsync(&nout, cnt, sizeof(nout), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return GTAP_E_HIP;
+      ++rounds;
+      if (nout > m.front_cap) {
+        over = true;
+        break;
+      }
+      nin = nout;
+    }
+    if (hipEventRecord(m.lev[1], st) != hipSuccess) return GTAP_E_HIP;
+    uint64_t n_m2l = 0, n_p2p = 0;
+    int rc = fmm_list_counts(c, m, n_m2l, n_p2p);
+    if (rc) return rc;
+    m.rounds = rounds;
+    if (!over && n_m2l <= m.m2l_cap && n_p2p <= m.p2p_cap) {
+      (void)hipEventElapsedTime(&m.worklist_ms, m.lev[0], m.lev[1]);
+      return GTAP_OK;
+    }
+    ++m.retries;
+    if (over) {
+      (void)hipFree(m.front);
+      m.front = nullptr;
+      m.front_cap = 2 * nout;
+      if (!dev_alloc(&m.front, 2 * m.front_cap + 1)) return GTAP_E_NOMEM;
+    }
+    rc = fmm_grow_lists(c, m, over ? 0 : n_m2l, over ? 0 : n_p2p);
+    if (rc) return rc;
+  }
+  return GTAP_E_CAPACITY;
+}
+
+// Sort both lists by target, find each target's segment and evaluate: M2L into
+// the local expansions, P2P into the sorted-order potentials; the pair counts,
+// hashes, interactions and coincident pairs go to the descriptor.
+int fmm_eval_lists(gtap_ctx *c, FmmJobMem &m, uint64_t n_m2l, uint64_t n_p2p, gtap_fmm_result &r) {
+  hipStream_t st = c->stream;
+  for (hipEvent_t &e : m.lev)
+    if (!e && hipEventCreate(&e) != hipSuccess) return GTAP_E_HIP;
+  const uint64_t nmax = std::max<uint64_t>(std::max(n_m2l, n_p2p), 1);
+  unsigned end_bit = 32;
+  while (end_bit < 64 && (static_cast<uint64_t>(m.ncells) >> (end_bit - 32)) != 0) ++end_bit;
+  size_t tmp_bytes = 0;
+  if (rocprim::radix_sort_keys(nullptr, tmp_bytes, m.m2l, m.m2l, static_cast<size_t>(nmax), 32, end_bit, st) !=
+      hipSuccess)
+    return GTAP_E_HIP;
+  if (!dev_alloc(&m.sorted, nmax) || !dev_alloc(&m.seg, 2 * static_cast<size_t>(m.ncells)) ||
+      hipMalloc(&m.lsort_tmp, tmp_bytes ? tmp_bytes : 1) != hipSuccess)
+    return GTAP_E_NOMEM;
+  uint64_t *lo = m.seg, *hi = m.seg + m.ncells;
+  fmm::FmmDesc *D = m.desc;
+  const uint64_t counts[2] = {n_m2l, n_p2p};
+  if (hipMemcpyAsync(&D->m2l_pairs, counts, sizeof(counts), hipMemcpyHostToDevice, st) != hipSuccess)
+    return GTAP_E_HIP;
+  auto prepare = [&](uint64_t *list, uint64_t cnt, uint64_t *hash) -> int {
+    if (hipMemsetAsync(m.seg, 0, sizeof(uint64_t) * 2 * static_cast<size_t>(m.ncells), st) != hipSuccess)
+      return GTAP_E_HIP;
+    if (cnt == 0) return GTAP_OK;
+    size_t tb = tmp_bytes;
+    if (rocprim::radix_sort_keys(m.lsort_tmp, tb, list, m.sorted, static_cast<size_t>(cnt), 32, end_bit, st) !=
+        hipSuccess)
+      return GTAP_E_HIP;
+    hipLaunchKernelGGL(fmm::k_list_segments, dim3(nblk(static_cast<int64_t>(cnt), 256)), dim3(256), 0, st, m.sorted,
+                       cnt, lo, hi);
+    hipLaunchKernelGGL(fmm::k_list_hash, dim3(1024), dim3(256), 0, st, m.sorted, cnt, hash);
+    return GTAP_OK;
+  };
+  int rc = GTAP_OK;
+  if (hipEventRecord(m.lev[2], st) != hipSuccess) return GTAP_E_HIP;
+  if ((rc = prepare(m.m2l, n_m2l, &D->m2l_hash))) return rc;
+  if (hipEventRecord(m.lev[3], st) != hipSuccess) return GTAP_E_HIP;
+  hipLaunchKernelGGL(fmm::k_m2l_list, dim3(m.ncells), dim3(fmm::kM2LThreads), 0, st, m.hdesc.cell, m.hdesc.Q,
+                     m.hdesc.L, m.sorted, lo, hi);
+  if (hipEventRecord(m.lev[4], st) != hipSuccess) return GTAP_E_HIP;
+  if ((rc = prepare(m.p2p, n_p2p, &D->p2p_hash))) return rc;
+  if (hipEventRecord(m.lev[5], st) != hipSuccess) return GTAP_E_HIP;
+  hipLaunchKernelGGL(fmm::k_p2p_list, dim3(m.ncells), dim3(fmm::kP2PThreads), 0, st, m.hdesc.cell, m.hdesc.px,
+                     m.hdesc.py, m.hdesc.pz, m.hdesc.pq, m.hdesc.phi, m.sorted, lo, hi, &D->p2p_inter,
+                     &D->coincident);
+  if (hipEventRecord(m.lev[6], st) != hipSuccess) return GTAP_E_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) return GTAP_E_HIP;
+  float s1 = 0.f, mm = 0.f, s2 = 0.f, pp = 0.f;
+  (void)hipEventElapsedTime(&s1, m.lev[2], m.lev[3]);
+  (void)hipEventElapsedTime(&mm, m.lev[3], m.lev[4]);
+  (void)hipEventElapsedTime(&s2, m.lev[4], m.lev[5]);
+  (void)hipEventElapsedTime(&pp, m.lev[5], m.lev[6]);
+  r.sort_ms = s1 + s2;
+  r.m2l_ms = mm;
+  r.p2p_ms = pp;
+  return GTAP_OK;
 }
 
 // L2L, L2P and the scatter to the caller's order; statistics into r.
@@ -694,7 +900,9 @@ int gtap_run(gtap_ctx *c) {
   Params &p = c->params;
   p.njobs = static_cast<uint32_t>(nj);
   p.serving = 0;
-  // FMM jobs: tree and upward pass before the traversal launch
+  const bool block = c->cfg.mode == GTAP_MODE_BLOCK;
+  // FMM jobs: tree and upward pass before the launch; the worklist traversal
+  // runs here too (its root task in the launch is empty)
   std::vector<FmmJobMem> fm;
   bool any_fmm = false;
   for (size_t j = 0; j < nj; ++j) any_fmm |= c->pending[j].kind == GTAP_KIND_FMM;
@@ -707,42 +915,75 @@ int gtap_run(gtap_ctx *c) {
     fm.resize(nj);
     for (size_t j = 0; j < nj; ++j) {
       if (c->pending[j].kind != GTAP_KIND_FMM) continue;
-      const int rc = fmm_prepare(c, c->pending_fmm[j], fm[j]);
+      const gtap_fmm_args &a = c->pending_fmm[j];
+      int rc = fmm_prepare(c, a, fm[j]);
+      if (rc == GTAP_OK && a.traversal == GTAP_FMM_WORKLIST) rc = fmm_worklist(c, fm[j]);
       if (rc != GTAP_OK) {
         drop_pending();
         return rc;
       }
       c->pending[j].a[0] = reinterpret_cast<uint64_t>(fm[j].desc);
-      c->pending[j].pending = 1;  // the root cell pair
+      if (block) {
+        c->pending[j].pending = 1;  // the root cell pair
+      } else {
+        c->pending[j].a[1] = static_cast<uint64_t>(a.traversal);
+        c->pending[j].a[2] = static_cast<uint64_t>(a.theta_num) | (static_cast<uint64_t>(a.theta_den) << 8);
+      }
     }
   }
-  if (hipMemcpyAsync(p.jobs, c->pending.data(), nj * sizeof(JobSlot), hipMemcpyHostToDevice, c->stream) !=
-      hipSuccess) {
-    drop_pending();
-    return GTAP_E_HIP;
-  }
-  const uint32_t ndq = c->nwaves * p.Q;
-  hipLaunchKernelGGL(reset_kernel, dim3(reset_blocks(ndq, p.ccap)), dim3(256), 0, c->stream, p, ndq);
-  int rc = GTAP_OK;
-  if (hipGetLastError() != hipSuccess || hipEventRecord(c->ev0, c->stream) != hipSuccess) rc = GTAP_E_HIP;
-  if (rc == GTAP_OK) rc = launch_sched(c);
-  if (rc == GTAP_OK && hipEventRecord(c->ev1, c->stream) != hipSuccess) rc = GTAP_E_HIP;
-  if (rc != GTAP_OK) {
-    (void)hipStreamSynchronize(c->stream);
-    drop_pending();
-    return rc;
-  }
-  c->done_jobs.resize(nj);
+  // one launch; a list-building traversal whose lists overflowed is re-run
+  // with lists that fit (every job of the batch runs again)
   Control ctl;
-  if (hipMemcpyAsync(c->done_jobs.data(), p.jobs, nj * sizeof(JobSlot), hipMemcpyDeviceToHost, c->stream) !=
-          hipSuccess ||
-      hipMemcpyAsync(&ctl, p.ctl, sizeof(Control), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
-    drop_pending();
-    return GTAP_E_HIP;
-  }
   float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+  int rc = GTAP_OK;
+  for (int attempt = 0;; ++attempt) {
+    if (hipMemcpyAsync(p.jobs, c->pending.data(), nj * sizeof(JobSlot), hipMemcpyHostToDevice, c->stream) !=
+        hipSuccess) {
+      drop_pending();
+      return GTAP_E_HIP;
+    }
+    const uint32_t ndq = c->nwaves * p.Q;
+    hipLaunchKernelGGL(reset_kernel, dim3(reset_blocks(ndq, p.ccap)), dim3(256), 0, c->stream, p, ndq);
+    if (hipGetLastError() != hipSuccess || hipEventRecord(c->ev0, c->stream) != hipSuccess) rc = GTAP_E_HIP;
+    if (rc == GTAP_OK) rc = launch_sched(c, any_fmm && !block);
+    if (rc == GTAP_OK && hipEventRecord(c->ev1, c->stream) != hipSuccess) rc = GTAP_E_HIP;
+    if (rc != GTAP_OK) {
+      (void)hipStreamSynchronize(c->stream);
+      drop_pending();
+      return rc;
+    }
+    c->done_jobs.resize(nj);
+    if (hipMemcpyAsync(c->done_jobs.data(), p.jobs, nj * sizeof(JobSlot), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(&ctl, p.ctl, sizeof(Control), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+      drop_pending();
+      return GTAP_E_HIP;
+    }
+    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    bool again = false;
+    if (ctl.error == 0 && any_fmm && !block) {
+      std::vector<std::pair<uint64_t, uint64_t>> counts(nj, {0, 0});
+      for (size_t j = 0; j < nj && rc == GTAP_OK; ++j) {
+        if (c->pending[j].kind != GTAP_KIND_FMM || c->pending_fmm[j].traversal != GTAP_FMM_LISTS) continue;
+        rc = fmm_list_counts(c, fm[j], counts[j].first, counts[j].second);
+        if (counts[j].first > fm[j].m2l_cap || counts[j].second > fm[j].p2p_cap) again = true;
+      }
+      if (rc == GTAP_OK && again && attempt >= 2) rc = GTAP_E_CAPACITY;
+      // every list-building job runs again: its lists grow if needed, its
+      // counters restart
+      for (size_t j = 0; j < nj && rc == GTAP_OK && again; ++j) {
+        if (c->pending[j].kind != GTAP_KIND_FMM || c->pending_fmm[j].traversal != GTAP_FMM_LISTS) continue;
+        rc = fmm_grow_lists(c, fm[j], counts[j].first, counts[j].second);
+        ++fm[j].retries;
+      }
+    }
+    if (rc != GTAP_OK) {
+      drop_pending();
+      return rc;
+    }
+    if (!again) break;
+  }
   c->done_first = c->pending_first;
   c->have_done = true;
 
@@ -751,8 +992,25 @@ int gtap_run(gtap_ctx *c) {
     if (c->done_jobs[j].done != 1) rc = GTAP_E_STATE;
   if (rc_run == GTAP_OK && rc == GTAP_OK && any_fmm) {
     c->done_fmm.assign(nj, gtap_fmm_result{});
-    for (size_t j = 0; j < nj && rc == GTAP_OK; ++j)
-      if (c->pending[j].kind == GTAP_KIND_FMM) rc = fmm_finish(c, c->pending_fmm[j], fm[j], ms, c->done_fmm[j]);
+    for (size_t j = 0; j < nj && rc == GTAP_OK; ++j) {
+      if (c->pending[j].kind != GTAP_KIND_FMM) continue;
+      const gtap_fmm_args &a = c->pending_fmm[j];
+      FmmJobMem &m = fm[j];
+      gtap_fmm_result ev{};
+      if (a.traversal != GTAP_FMM_TASKS) {
+        uint64_t n_m2l = 0, n_p2p = 0;
+        rc = fmm_list_counts(c, m, n_m2l, n_p2p);
+        if (rc == GTAP_OK) rc = fmm_eval_lists(c, m, n_m2l, n_p2p, ev);
+      }
+      const float trav = a.traversal == GTAP_FMM_WORKLIST ? m.worklist_ms : ms;
+      if (rc == GTAP_OK) rc = fmm_finish(c, a, m, trav, c->done_fmm[j]);
+      gtap_fmm_result &r = c->done_fmm[j];
+      r.sort_ms = ev.sort_ms;
+      r.m2l_ms = ev.m2l_ms;
+      r.p2p_ms = ev.p2p_ms;
+      r.dtt_rounds = m.rounds;
+      r.list_retries = m.retries;
+    }
   }
   drop_pending();
   if (rc_run != GTAP_OK || rc != GTAP_OK) {

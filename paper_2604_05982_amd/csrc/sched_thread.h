@@ -601,6 +601,7 @@ GTAP_DEV uint32_t owner_of(const uint32_t *offs, uint32_t g) {
 }
 
 // Root frame of job slot j (payload from the job's arguments).
+template <bool kFmm = false>
 GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
   const uint32_t jkind = static_cast<uint32_t>(co_ld64(reinterpret_cast<const uint64_t *>(p.jobs + j)));
   ChildInit c;
@@ -633,6 +634,22 @@ GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
       break;
     default:
       break;
+  }
+  if constexpr (kFmm) {
+    // FMM in thread mode: the list-building traversal starts at the pair
+    // (root, root); a job whose lists the worklist builds has an empty root
+    // (a[0] descriptor, a[1] traversal, a[2] = theta_num | theta_den << 8)
+    if (jkind == 5) {
+      const uint64_t desc = job_arg(p, j, 0);
+      kind = TK_FIB;
+      c.p[0] = 0;
+      if (job_arg(p, j, 1) == 1) {
+        kind = TK_DTT;
+        c.p[2] = static_cast<uint32_t>(desc);
+        c.p[3] = static_cast<uint32_t>(desc >> 32);
+        c.p[4] = static_cast<uint32_t>(job_arg(p, j, 2));
+      }
+    }
   }
   write_frame(frame_ptr(p, id), kNone, j, state_word(kind, 0, 0), c);
 }
@@ -713,8 +730,9 @@ struct LocalCap {
 
 // V selects the queue management (kSchedBatched, kSchedSingle, kSchedCentral;
 // kSchedBatchedNoLocal = batched without the private stack) at compile time,
-// so the comparison variants add nothing to the scheduler as designed.
-template <int WPB, uint32_t V = kSchedBatched>
+// so the comparison variants add nothing to the scheduler as designed; kFmm
+// adds the FMM list-building cell-pair tasks and their list appends.
+template <int WPB, uint32_t V = kSchedBatched, bool kFmm = false>
 __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   constexpr bool kCentral = (V == kSchedCentral);
   constexpr bool kSingle = (V == kSchedSingle);
@@ -765,7 +783,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     const bool ok = alloc_frames(p, PS, me, nroots, ar, wc);
     if (ok && nroots > 0) {
       wave_sync();
-      for (uint32_t g = ln; g < nroots; g += kWave) write_root(p, alloc_id(PS, ar, g), me + g * p.nwaves);
+      for (uint32_t g = ln; g < nroots; g += kWave) write_root<kFmm>(p, alloc_id(PS, ar, g), me + g * p.nwaves);
       drain();
       const uint32_t keep = nroots < kWave ? nroots : kWave;
       if (ln < keep) tid = alloc_id(PS, ar, ln);
@@ -949,6 +967,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     o.big = 0;
     o.first = 0;
     for (int i = 0; i < 6; ++i) o.d[i] = 0;
+    if constexpr (kFmm) o.emit = 0;
     if (ln < cnt) {
       TaskImage img;
       if (tid == kNone) {
@@ -959,7 +978,17 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       } else {
         img = load_image(p, tid);
       }
-      exec_task(p, tid, img, o);
+      exec_task<kFmm>(p, tid, img, o);
+    }
+    if constexpr (kFmm) {
+      // FMM list traversal: accepted pairs and leaf pairs go to their lists
+      const bool em = o.type == OUT_DONE && o.emit != 0;
+      if (ballot(em) != 0ull) {
+        fmm::FmmDesc *D = reinterpret_cast<fmm::FmmDesc *>(pack(o.d[3], o.d[4]));
+        const uint64_t pair = (static_cast<uint64_t>(o.d[0]) << 32) | o.d[1];
+        fmm::list_append(D, 0, em && o.emit == 1, pair);
+        fmm::list_append(D, 1, em && o.emit == 2, pair);
+      }
     }
     const uint32_t nfirst = __popcll(ballot(o.first != 0));
     wc.add(ST_TASKS, nfirst);
@@ -1079,7 +1108,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
           const ForkDesc dsc = L.desc[own];
           const uint32_t d[6] = {dsc.d0, dsc.d1, dsc.d2, dsc.d3, dsc.d4, dsc.ckind_big_d5 >> 8};
           ChildInit ci;
-          make_child(dsc.ckind_big_d5 & 0x7Fu, d, g - L.offs[own], ci);
+          make_child<kFmm>(dsc.ckind_big_d5 & 0x7Fu, d, g - L.offs[own], ci);
           c = child_class(p, dsc.job, dsc.ckind_big_d5 & 0x7Fu, ci);
           if (g < kClassCache) L.cls[g] = static_cast<uint8_t>(c);
         }
@@ -1189,7 +1218,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         j = g - L.offs[own];
         dsc = L.desc[own];
         const uint32_t d[6] = {dsc.d0, dsc.d1, dsc.d2, dsc.d3, dsc.d4, dsc.ckind_big_d5 >> 8};
-        make_child(dsc.ckind_big_d5 & 0x7Fu, d, j, ci);
+        make_child<kFmm>(dsc.ckind_big_d5 & 0x7Fu, d, j, ci);
         if (p.Q > 1) c = g < kClassCache ? L.cls[g] : child_class(p, dsc.job, dsc.ckind_big_d5 & 0x7Fu, ci);
       }
       const bool big = act && (dsc.ckind_big_d5 & 0x80u);

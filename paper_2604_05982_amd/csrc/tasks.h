@@ -16,6 +16,7 @@
 // semantics, Sec. 4.1).  Each task has an implicit join at its end, so a
 // parent always completes after all of its children.
 #pragma once
+#include "fmm_lists.h"
 #include "layout.h"
 #include "wave.h"
 
@@ -34,6 +35,7 @@ struct Outcome {
   uint32_t job;
   uint32_t kind;     // this task's kind
   uint32_t first;    // 1: first execution (resume point 0), 0: continuation
+  uint32_t emit;     // FMM list traversal: 1 = M2L pair, 2 = P2P pair (d[0], d[1]), descriptor d[3..4]
 };
 
 // Payload of a new frame (words 3..7).
@@ -141,7 +143,10 @@ GTAP_DEV TaskImage load_continuation(const Params &p, uint32_t tid) {
 
 // ---------------------------------------------------------------------------
 // Execute one task on this lane.  tid is its frame, or kNone for a task
-// without one (then it runs at resume point 0 and needs no buffer).
+// without one (then it runs at resume point 0 and needs no buffer).  kFmm
+// adds the list-building FMM cell-pair task (instantiated separately, so the
+// other task kinds compile unchanged).
+template <bool kFmm = false>
 GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Outcome &o) {
   uint32_t *f = tid != kNone ? frame_ptr(p, tid) : nullptr;
   const uint64_t w01 = img.w01;
@@ -157,6 +162,7 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
   o.nchild = 0;
   o.big = 0;
   o.value = 0;
+  if constexpr (kFmm) o.emit = 0;
 
   if (pc != 0) {
     // Continuation after the join (image from load_continuation): every kind
@@ -171,6 +177,31 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
   const uint32_t p0 = static_cast<uint32_t>(w23 >> 32);
   const uint32_t p1 = static_cast<uint32_t>(w45), p2 = static_cast<uint32_t>(w45 >> 32);
   const uint32_t p3 = static_cast<uint32_t>(w67), p4 = static_cast<uint32_t>(w67 >> 32);
+  if constexpr (kFmm) {
+    if (kind == TK_DTT) {
+      // FMM cell pair (A, B) (Sec. 6.4.1): an accepted pair or a pair of
+      // leaves goes to its list (the scheduler appends it, one atomic per
+      // wavefront), any other pair forks the pairs of the wider cell's
+      // children.  Payload: A, B, descriptor (p2, p3), theta = p4 & 255 over
+      // p4 >> 8.
+      const fmm::FmmDesc *D = reinterpret_cast<const fmm::FmmDesc *>(pack(p2, p3));
+      int32_t A[fmm::kCellInts], B[fmm::kCellInts];
+      fmm::load_cell(D->cell, p0, A);
+      fmm::load_cell(D->cell, p1, B);
+      bool split_a = false;
+      const uint32_t dec = fmm::dtt_decide(A, B, static_cast<int64_t>(p4 & 0xFFu), static_cast<int64_t>(p4 >> 8), split_a);
+      o.d[0] = p0; o.d[1] = p1; o.d[3] = p2; o.d[4] = p3; o.d[5] = p4;
+      if (dec != 0) {
+        o.emit = dec;
+        return;
+      }
+      o.type = OUT_FORK;
+      o.nchild = static_cast<uint32_t>(split_a ? A[7] : B[7]);
+      o.ckind = TK_DTT;
+      o.d[2] = static_cast<uint32_t>(split_a ? A[6] : B[6]) | (split_a ? 0x80000000u : 0u);
+      return;
+    }
+  }
   switch (kind) {
     case TK_FIB: {
       // fib(n): n < 2 returns n, else spawn fib(n-1), fib(n-2) and join.
@@ -340,8 +371,21 @@ GTAP_DEV uint32_t nth_set_bit(uint32_t m, uint32_t j) {
 
 // Payload of child j of a forked parent with child kind `ckind` and
 // descriptor d.
+template <bool kFmm = false>
 GTAP_DEV void make_child(uint32_t ckind, const uint32_t *d, uint32_t j, ChildInit &c) {
   for (uint32_t i = 0; i < kPayloadWords; ++i) c.p[i] = 0;
+  if constexpr (kFmm) {
+    if (ckind == TK_DTT) {  // pair (child j of the split cell, the other cell)
+      const bool sa = (d[2] >> 31) != 0;
+      const uint32_t c0 = d[2] & 0x7FFFFFFFu;
+      c.p[0] = sa ? c0 + j : d[0];
+      c.p[1] = sa ? d[1] : c0 + j;
+      c.p[2] = d[3];
+      c.p[3] = d[4];
+      c.p[4] = d[5];
+      return;
+    }
+  }
   switch (ckind) {
     case TK_FIB:
       c.p[0] = d[0] - 1 - j;

@@ -40,6 +40,10 @@ GTAP_KIND_UTS = 3
 GTAP_KIND_KCLIQUE = 4
 GTAP_KIND_FMM = 5
 
+GTAP_FMM_TASKS = 0
+GTAP_FMM_LISTS = 1
+GTAP_FMM_WORKLIST = 2
+
 GTAP_DAQ_NONE = 0
 GTAP_DAQ_BY_KIND = 1
 GTAP_DAQ_KCLIQUE = 2
@@ -97,14 +101,17 @@ class gtap_fmm_args(ctypes.Structure):
     _fields_ = [("x_dev", ctypes.c_void_p), ("y_dev", ctypes.c_void_p), ("z_dev", ctypes.c_void_p),
                 ("q_dev", ctypes.c_void_p), ("phi_dev", ctypes.c_void_p), ("n", ctypes.c_int32),
                 ("leaf_max", ctypes.c_int32), ("theta_num", ctypes.c_int32), ("theta_den", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("traversal", ctypes.c_int32),
+                ("m2l_capacity", ctypes.c_uint64), ("p2p_capacity", ctypes.c_uint64)]
 
 
 class gtap_fmm_result(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("n_cells", "n_leaves", "max_level", "m2l_pairs", "p2p_pairs")] + \
                [("m2l_hash", ctypes.c_uint64), ("p2p_hash", ctypes.c_uint64),
                 ("p2p_interactions", ctypes.c_int64), ("coincident", ctypes.c_int64)] + \
-               [(f, ctypes.c_double) for f in ("tree_ms", "upward_ms", "traversal_ms", "downward_ms")]
+               [(f, ctypes.c_double) for f in ("tree_ms", "upward_ms", "traversal_ms", "downward_ms",
+                                                "sort_ms", "m2l_ms", "p2p_ms")] + \
+               [("dtt_rounds", ctypes.c_int64), ("list_retries", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -420,9 +427,12 @@ class Runtime:
                            gtap_kclique_args(rp.data_ptr(), cl.data_ptr(), n, int(k),
                                              int(range_leaf), int(max_outdeg)))
 
-    def submit_fmm(self, x, y, z, q, phi, leaf_max: int = 64, theta=(1, 2), order: int = 6) -> int:
-        """FMM job (block mode): x, y, z, q, phi are float64 CUDA tensors of n
-        entries, kept alive until run() returns; phi receives the potentials."""
+    def submit_fmm(self, x, y, z, q, phi, leaf_max: int = 64, theta=(1, 2), order: int = 6,
+                   traversal: int = GTAP_FMM_TASKS, m2l_capacity: int = 0, p2p_capacity: int = 0) -> int:
+        """FMM job: x, y, z, q, phi are float64 CUDA tensors of n entries, kept
+        alive until run() returns; phi receives the potentials.  traversal
+        GTAP_FMM_TASKS needs a block-mode runtime, LISTS and WORKLIST a
+        thread-mode one."""
         torch = self._torch
         ts = [t.to(device="cuda", dtype=torch.float64).contiguous() for t in (x, y, z, q)]
         if not (phi.is_cuda and phi.dtype == torch.float64 and phi.is_contiguous()):
@@ -432,7 +442,7 @@ class Runtime:
         return gtap_submit(self.ctx, GTAP_KIND_FMM,
                            gtap_fmm_args(ts[0].data_ptr(), ts[1].data_ptr(), ts[2].data_ptr(), ts[3].data_ptr(),
                                          phi.data_ptr(), n, int(leaf_max), int(theta[0]), int(theta[1]),
-                                         int(order), 0))
+                                         int(order), int(traversal), int(m2l_capacity), int(p2p_capacity)))
 
     def fmm_result(self, job_id: int) -> dict:
         r = gtap_fmm_result()
