@@ -345,8 +345,12 @@ def serving_cpu_baseline(specs, subs, gpu_results, budget_s: float = 15.0) -> di
 
 
 def bench_fmm(args, gtap) -> int:
-    """3D Laplace FMM in block mode on 10^6 Plummer points (leaf 64, theta 1/2,
-    order 6): traversal tasks with M2L and cooperative P2P inside."""
+    """3D Laplace FMM on 10^6 Plummer points (leaf 64, theta 1/2, order 6).
+    --fmm-traversal tasks (default): block-mode traversal tasks with M2L and
+    cooperative P2P inside; lists / worklist: the traversal builds M2L and
+    P2P lists (thread-mode tasks or the level-synchronous worklist) that sorted
+    data-parallel kernels evaluate.  value = P2P interactions per second of the
+    interaction phase (traversal, plus sort and list evaluation for lists)."""
     import numpy as np
     import torch
     from synth import points
@@ -354,17 +358,24 @@ def bench_fmm(args, gtap) -> int:
     x, y, z, q = points.plummer(n, 3)
     tx, ty, tz, tq = (torch.as_tensor(a).cuda() for a in (x, y, z, q))
     phi = torch.zeros_like(tx)
-    rt = gtap.Runtime(mode=gtap.GTAP_MODE_BLOCK, waves_per_group=args.fmm_wpg, small_frames=1 << 24,
-                      big_frames=0, timeout_ms=120000, num_waves=args.num_waves if args.num_waves != 1024 else 0)
+    trav = {"tasks": gtap.GTAP_FMM_TASKS, "lists": gtap.GTAP_FMM_LISTS,
+            "worklist": gtap.GTAP_FMM_WORKLIST}[args.fmm_traversal]
+    if trav == gtap.GTAP_FMM_TASKS:
+        rt = gtap.Runtime(mode=gtap.GTAP_MODE_BLOCK, waves_per_group=args.fmm_wpg, small_frames=1 << 24,
+                          big_frames=0, timeout_ms=120000,
+                          num_waves=args.num_waves if args.num_waves != 1024 else 0)
+    else:
+        rt = gtap.Runtime(mode=gtap.GTAP_MODE_THREAD, waves_per_group=4, small_frames=1 << 24,
+                          big_frames=1 << 10, timeout_ms=120000)
     for _ in range(args.warmup):
-        rt.submit_fmm(tx, ty, tz, tq, phi)
+        rt.submit_fmm(tx, ty, tz, tq, phi, traversal=trav)
         rt.run()
     torch.cuda.synchronize()
     res, wall = [], []
     for _ in range(args.steps):
         phi.zero_()
         t0 = time.perf_counter()
-        j = rt.submit_fmm(tx, ty, tz, tq, phi)
+        j = rt.submit_fmm(tx, ty, tz, tq, phi, traversal=trav)
         rt.run()
         wall.append(time.perf_counter() - t0)
         res.append(rt.fmm_result(j))
@@ -372,18 +383,25 @@ def bench_fmm(args, gtap) -> int:
     rt.close()
     med = sorted(range(len(wall)), key=lambda i: wall[i])[len(wall) // 2]
     r = res[med]
-    trav_s = r["traversal_ms"] * 1e-3
+    inter_ms = r["traversal_ms"] + r["sort_ms"] + r["m2l_ms"] + r["p2p_ms"]
+    trav_s = inter_ms * 1e-3
     e2e = wall[med]
+    mode = "block mode, work inside the tasks" if trav == gtap.GTAP_FMM_TASKS else \
+        ("thread-mode list-building tasks + list kernels" if trav == gtap.GTAP_FMM_LISTS
+         else "level-synchronous worklist + list kernels")
     out = {"metric": METRIC, "value": r["p2p_interactions"] / trav_s, "unit": "P2P interactions/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"FMM dual-tree traversal, block mode: {n} Plummer points (seed 3), "
+           "config": {"workload": f"FMM dual-tree traversal ({mode}): {n} Plummer points (seed 3), "
                                   "leaf 64, theta 1/2, Cartesian order 6", "waves": st["num_waves"],
                       "waves_per_group": st["waves_per_group"]},
-           "m2l_pairs_per_s": r["m2l_pairs"] / trav_s, "traversal_tasks_per_s": st["tasks"] / trav_s,
+           "interaction_phase_ms": inter_ms,
+           "m2l_pairs_per_s": r["m2l_pairs"] / trav_s,
+           "traversal_tasks_per_s": st["tasks"] / (r["traversal_ms"] * 1e-3),
            "end_to_end_ms_median": 1e3 * e2e, "end_to_end_ms_min": 1e3 * min(wall),
            "end_to_end_ms_max": 1e3 * max(wall),
-           "phase_ms": {k: r[k] for k in ("tree_ms", "upward_ms", "traversal_ms", "downward_ms")},
+           "phase_ms": {k: r[k] for k in ("tree_ms", "upward_ms", "traversal_ms", "sort_ms", "m2l_ms", "p2p_ms",
+                                          "downward_ms")},
            "lists": {k: r[k] for k in ("n_cells", "n_leaves", "max_level", "m2l_pairs", "p2p_pairs",
                                        "p2p_interactions", "coincident")},
            "traversal_tasks": st["tasks"], "traversal_conts": st["conts"]}
@@ -473,6 +491,73 @@ def bench_schedulers(args, gtap) -> int:
     return 0
 
 
+def bench_fmm_dtt(args, gtap) -> int:
+    """The paper's FMM experiment (Sec. 6.4.1): uniform points, a theta sweep,
+    the dual-tree traversal building M2L / P2P lists either as thread-mode
+    tasks of this runtime or as the level-synchronous GPU worklist (one launch
+    and one host synchronisation per frontier); both feed the same sort and
+    data-parallel M2L / P2P kernels.  Reports the traversal time of each and
+    the end-to-end breakdown."""
+    import numpy as np
+    import torch
+    from synth import points
+    n = args.fmm_points
+    x, y, z, q = points.uniform_cube(n, 21, half=100.0)
+    tx, ty, tz, tq = (torch.as_tensor(a).cuda() for a in (x, y, z, q))
+    phi = torch.zeros_like(tx)
+    thetas = [tuple(int(v) for v in t.split("/")) for t in args.fmm_thetas.split(",")]
+    rt = gtap.Runtime(mode=gtap.GTAP_MODE_THREAD, waves_per_group=4, small_frames=1 << 25, big_frames=1 << 10,
+                      timeout_ms=120000)
+    rows = []
+    for th in thetas:
+        for name, tr in (("tasks", gtap.GTAP_FMM_LISTS), ("worklist", gtap.GTAP_FMM_WORKLIST)):
+            runs = []
+            for it in range(args.warmup + args.steps):
+                phi.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                j = rt.submit_fmm(tx, ty, tz, tq, phi, leaf_max=64, theta=th, traversal=tr)
+                rt.run()
+                wall = time.perf_counter() - t0
+                r = rt.fmm_result(j)
+                r["wall_ms"] = 1e3 * wall
+                if it >= args.warmup:
+                    runs.append(r)
+            runs.sort(key=lambda r: r["traversal_ms"])
+            r = runs[len(runs) // 2]
+            row = {"theta": f"{th[0]}/{th[1]}", "traversal": name, "dtt_ms": r["traversal_ms"],
+                   "dtt_ms_min": runs[0]["traversal_ms"], "end_to_end_ms": r["wall_ms"],
+                   "phase_ms": {k: r[k] for k in ("tree_ms", "upward_ms", "traversal_ms", "sort_ms", "m2l_ms",
+                                                  "p2p_ms", "downward_ms")},
+                   "lists": {k: r[k] for k in ("n_cells", "n_leaves", "max_level", "m2l_pairs", "p2p_pairs",
+                                               "p2p_interactions")},
+                   "dtt_rounds": r["dtt_rounds"], "list_retries": r["list_retries"],
+                   "m2l_hash": r["m2l_hash"], "p2p_hash": r["p2p_hash"]}
+            rows.append(row)
+            print(f"# theta {row['theta']:5s} {name:8s}: DTT {row['dtt_ms']:9.2f} ms, end to end "
+                  f"{row['end_to_end_ms']:9.1f} ms, M2L pairs {r['m2l_pairs']}, P2P pairs {r['p2p_pairs']}",
+                  file=sys.stderr, flush=True)
+        a, b = rows[-2], rows[-1]
+        if (a["m2l_hash"], a["p2p_hash"]) != (b["m2l_hash"], b["p2p_hash"]):
+            raise SystemExit(f"theta {a['theta']}: the two traversals built different lists")
+    st = rt.stats()
+    rt.close()
+    best = min(r["dtt_ms"] for r in rows if r["traversal"] == "tasks")
+    out = {"metric": METRIC, "value": None, "unit": "ms (DTT list construction)", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "scaling": "strong",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"FMM pipeline with list-building DTT: {n} uniform points in [-100, 100)^3 "
+                                  f"(seed 21), leaf 64, order 6, theta sweep {args.fmm_thetas}",
+                      "waves": st["num_waves"], "waves_per_group": st["waves_per_group"]},
+           "rows": rows}
+    out["value"] = best
+    for r in rows:
+        r.pop("m2l_hash")
+        r.pop("p2p_hash")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -487,9 +572,12 @@ def main() -> int:
     ap.add_argument("--fmm-points", type=int, default=1000000, help="fmm: number of points")
     ap.add_argument("--fmm-wpg", type=int, default=2, help="fmm: wavefronts per workgroup (1, 2, 4)")
     ap.add_argument("--fib-n", type=int, default=35, help="schedulers: fib argument")
+    ap.add_argument("--fmm-thetas", default="1/2,2/5,1/3", help="fmm_dtt: MAC parameters")
+    ap.add_argument("--fmm-traversal", default="tasks", choices=("tasks", "lists", "worklist"),
+                    help="fmm: block-mode tasks with the work inside, or a list-building traversal")
     ap.add_argument("--sched-waves", default="64,128,256,512,1024", help="schedulers: grid sizes (wavefronts)")
     ap.add_argument("--workload", default="microbench",
-                    choices=("microbench", "kclique7", "serving", "fmm", "schedulers"),
+                    choices=("microbench", "kclique7", "serving", "fmm", "schedulers", "fmm_dtt"),
                     help="kclique7: 7-cliques of the n=10^6 Chung-Lu graph (DAQ comparison); "
                          "serving: batched / served job mix against one launch per job")
     ap.add_argument("--jobs", type=int, default=20000, help="serving: jobs in the trace")
@@ -517,6 +605,8 @@ def main() -> int:
         return bench_fmm(args, gtap)
     if args.workload == "schedulers":
         return bench_schedulers(args, gtap)
+    if args.workload == "fmm_dtt":
+        return bench_fmm_dtt(args, gtap)
 
     rt = gtap.Runtime(waves_per_group=args.waves_per_group, num_waves=args.num_waves,
                       steal_below=args.steal_below, small_frames=1 << 25, timeout_ms=60000)

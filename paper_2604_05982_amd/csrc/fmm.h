@@ -113,6 +113,8 @@ struct FmmDesc {
   uint64_t *m2l_list, *p2p_list;
   uint64_t m2l_cap, p2p_cap;
   uint64_t m2l_n, p2p_n;
+  uint32_t ncells;         // a list slot holding target ncells is a gap (see list chunks)
+  uint32_t pad_;
 };
 
 GTAP_DEV double cell_centre(int32_t anchor, int32_t level) {

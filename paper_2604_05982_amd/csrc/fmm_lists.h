@@ -61,6 +61,79 @@ GTAP_DEV void list_append(FmmDesc *D, uint32_t which, bool act, uint64_t pair) {
   }
 }
 
+// Chunked appends of a persistent wavefront (thread-mode traversal tasks): the
+// wavefront reserves kListChunk slots with one atomic add and fills them over
+// many iterations, so the two list counters see one atomic per 2,048 pairs
+// instead of one per wavefront and iteration (hundreds of wavefronts adding to
+// one word serialise).  Slots a wavefront leaves unused when it moves on hold
+// the gap pair (ncells << 32), which sorts after every real target and is
+// skipped by the evaluation.
+constexpr uint32_t kListChunk = 2048;
+
+struct ListChunks {
+  FmmDesc *D;          // descriptor the chunks belong to (nullptr: none)
+  uint64_t base[2];    // first slot of the current chunk, per list
+  uint32_t used[2];    // slots of it filled
+};
+
+GTAP_DEV uint64_t gap_pair(const FmmDesc *D) { return static_cast<uint64_t>(D->ncells) << 32; }
+
+// Fill the unused rest of both chunks with gaps (all lanes; wave-uniform state).
+GTAP_DEV void chunks_close(ListChunks &C) {
+  if (C.D == nullptr) return;
+  for (uint32_t w = 0; w < 2; ++w) {
+    const uint64_t cap = w ? C.D->p2p_cap : C.D->m2l_cap;
+    uint64_t *list = w ? C.D->p2p_list : C.D->m2l_list;
+    for (uint32_t i = C.used[w] + lane_id(); i < kListChunk; i += kWave) {
+      const uint64_t at = C.base[w] + i;
+      if (at < cap) list[at] = gap_pair(C.D);
+    }
+    C.used[w] = kListChunk;
+  }
+  C.D = nullptr;
+}
+
+// Append `pair` to list `which` for every active lane whose descriptor is the
+// chunks' one (a wavefront's lanes almost always share it: a different one
+// closes the chunks and takes over; lanes of a third go through list_append).
+GTAP_DEV void chunks_append(ListChunks &C, FmmDesc *D, uint32_t which, bool act, uint64_t pair) {
+  const uint64_t m = ballot(act);
+  if (m == 0ull) return;
+  const int leader = __ffsll(static_cast<long long>(m)) - 1;
+  FmmDesc *dl = reinterpret_cast<FmmDesc *>(readlane64(reinterpret_cast<uint64_t>(D), leader));
+  if (dl != C.D) {
+    chunks_close(C);
+    C.D = dl;
+    C.used[0] = C.used[1] = kListChunk;  // no chunk reserved yet
+  }
+  const bool mine = act && D == dl;
+  const uint64_t ms = ballot(mine);
+  const uint32_t n = static_cast<uint32_t>(__popcll(ms));
+  const uint32_t r = rank_below(ms);
+  const uint64_t cap = which ? dl->p2p_cap : dl->m2l_cap;
+  uint64_t *list = which ? dl->p2p_list : dl->m2l_list;
+  // the part that fits in the current chunk, then a new chunk for the rest
+  const uint32_t room = kListChunk - C.used[which];
+  if (mine && r < room) {
+    const uint64_t at = C.base[which] + C.used[which] + r;
+    if (at < cap) list[at] = pair;
+  }
+  if (n > room) {
+    uint64_t b = 0;
+    if (lane_id() == 0) b = fetch_add_relaxed(which ? &dl->p2p_n : &dl->m2l_n, static_cast<uint64_t>(kListChunk));
+    C.base[which] = readlane64(b, 0);
+    C.used[which] = 0;
+    if (mine && r >= room) {
+      const uint64_t at = C.base[which] + (r - room);
+      if (at < cap) list[at] = pair;
+    }
+    C.used[which] = n - room;
+  } else {
+    C.used[which] += n;
+  }
+  list_append(D, which, act && !mine, pair);
+}
+
 GTAP_DEV void load_cell(const int32_t *cell, uint32_t c, int32_t *C) {
   const int4 *p = reinterpret_cast<const int4 *>(cell + static_cast<size_t>(c) * kCellInts);
   const int4 u = p[0], v = p[1];
@@ -70,11 +143,19 @@ GTAP_DEV void load_cell(const int32_t *cell, uint32_t c, int32_t *C) {
 
 // ---- level-synchronous worklist traversal ------------------------------------
 // One thread per pair of the frontier: accepted pairs and leaf pairs go to the
-// lists, the child pairs of a split go to the next frontier (one atomic add per
-// wavefront).  *nout keeps counting past cap_out.
-__global__ __launch_bounds__(256) void k_dtt_frontier(FmmDesc *D, const uint64_t *fin, uint64_t nin, uint64_t *fout,
-                                                      uint64_t *nout, uint64_t cap_out) {
+// lists, the child pairs of a split go to the next frontier.  Appends are
+// aggregated over the 1,024-thread workgroup: one atomic add per workgroup
+// and counter (the three counters are the hot words of this traversal).
+// *nout keeps counting past cap_out.
+constexpr uint32_t kFrontierThreads = 1024;
+
+__global__ __launch_bounds__(kFrontierThreads) void k_dtt_frontier(FmmDesc *D, const uint64_t *fin, uint64_t nin,
+                                                                   uint64_t *fout, uint64_t *nout, uint64_t cap_out) {
+  constexpr uint32_t W = kFrontierThreads / kWave;
+  __shared__ uint32_t wcnt[3][W];
+  __shared__ uint64_t wbase[3][W];
   const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint32_t wv = threadIdx.x / kWave;
   const bool act = i < nin;
   uint64_t pair = 0;
   uint32_t dec = 3, k = 0, child0 = 0, a = 0, b = 0;
@@ -92,23 +173,47 @@ __global__ __launch_bounds__(256) void k_dtt_frontier(FmmDesc *D, const uint64_t
       child0 = static_cast<uint32_t>(split_a ? A[6] : B[6]);
     }
   }
-  list_append(D, 0, dec == 1, pair);
-  list_append(D, 1, dec == 2, pair);
-  uint32_t total = 0;
-  const uint32_t off = wave_exclusive_scan(k, &total);
-  uint64_t base = 0;
-  if (lane_id() == 0 && total) base = fetch_add_relaxed(nout, static_cast<uint64_t>(total));
-  base = readlane64(base, 0);
+  // per-wavefront counts and offsets
+  const uint64_t m1 = ballot(dec == 1), m2 = ballot(dec == 2);
+  uint32_t ktot = 0;
+  const uint32_t koff = wave_exclusive_scan(k, &ktot);
+  if (lane_id() == 0) {
+    wcnt[0][wv] = static_cast<uint32_t>(__popcll(m1));
+    wcnt[1][wv] = static_cast<uint32_t>(__popcll(m2));
+    wcnt[2][wv] = ktot;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const uint32_t c = threadIdx.x;
+    uint32_t tot = 0;
+    for (uint32_t w = 0; w < W; ++w) tot += wcnt[c][w];
+    uint64_t base = 0;
+    if (tot) base = fetch_add_relaxed(c == 0 ? &D->m2l_n : c == 1 ? &D->p2p_n : nout, static_cast<uint64_t>(tot));
+    for (uint32_t w = 0; w < W; ++w) {
+      wbase[c][w] = base;
+      base += wcnt[c][w];
+    }
+  }
+  __syncthreads();
+  if (dec == 1) {
+    const uint64_t at = wbase[0][wv] + rank_below(m1);
+    if (at < D->m2l_cap) D->m2l_list[at] = pair;
+  } else if (dec == 2) {
+    const uint64_t at = wbase[1][wv] + rank_below(m2);
+    if (at < D->p2p_cap) D->p2p_list[at] = pair;
+  }
+  const uint64_t base = wbase[2][wv] + koff;
   for (uint32_t j = 0; j < k; ++j) {
-    const uint64_t at = base + off + j;
     const uint32_t c = child0 + j;
-    if (at < cap_out) fout[at] = split_a ? ((static_cast<uint64_t>(c) << 32) | b) : ((static_cast<uint64_t>(a) << 32) | c);
+    if (base + j < cap_out)
+      fout[base + j] = split_a ? ((static_cast<uint64_t>(c) << 32) | b) : ((static_cast<uint64_t>(a) << 32) | c);
   }
 }
 
 // ---- list evaluation ------------------------------------------------------------
 // Segment [lo[a], hi[a]) of target a in a list sorted by target (both zeroed
-// beforehand, so targets without pairs have empty segments).
+// beforehand, so targets without pairs have empty segments; a = ncells, the
+// gaps, gets a segment of its own that nothing reads).
 __global__ void k_list_segments(const uint64_t *pairs, uint64_t n, uint64_t *lo, uint64_t *hi) {
   const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -117,14 +222,22 @@ __global__ void k_list_segments(const uint64_t *pairs, uint64_t n, uint64_t *lo,
   if (i + 1 == n || static_cast<uint32_t>(pairs[i + 1] >> 32) != a) hi[a] = i + 1;
 }
 
-// Order-independent wrapping sum of pair hashes of a list (the oracle's check).
-__global__ __launch_bounds__(256) void k_list_hash(const uint64_t *pairs, uint64_t n, uint64_t *out) {
-  uint64_t h = 0;
+// Order-independent wrapping sum of pair hashes of a list (the oracle's check)
+// and the number of real pairs (gaps, target == ncells, are skipped).
+__global__ __launch_bounds__(256) void k_list_hash(const uint64_t *pairs, uint64_t n, uint32_t ncells, uint64_t *out,
+                                                   uint64_t *count) {
+  uint64_t h = 0, k = 0;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
-    h += pair_hash(static_cast<uint32_t>(pairs[i] >> 32), static_cast<uint32_t>(pairs[i]));
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t a = static_cast<uint32_t>(pairs[i] >> 32);
+    if (a >= ncells) continue;
+    h += pair_hash(a, static_cast<uint32_t>(pairs[i]));
+    ++k;
+  }
   h = readlane64(wave_inclusive_sum64(h), 63);
+  k = readlane64(wave_inclusive_sum64(k), 63);
   if (lane_id() == 0 && h) fetch_add_relaxed(out, h);
+  if (lane_id() == 0 && k) fetch_add_relaxed(count, k);
 }
 
 // Taylor coefficients T_g of 1/|d + h| at h = 0, total degree <= 6, by the

@@ -675,8 +675,14 @@ int fmm_prepare(gtap_ctx *c, const gtap_fmm_args &a, FmmJobMem &m) {
   d.phi = phi;
   d.ta = a.theta_num;
   d.tb = a.theta_den;
+  d.ncells = static_cast<uint32_t>(m.ncells);
   if (a.traversal != GTAP_FMM_TASKS) {
     fmm_list_caps(a, m.ncells, m.m2l_cap, m.p2p_cap);
+    if (a.traversal == GTAP_FMM_LISTS && !a.m2l_capacity && !a.p2p_capacity) {
+      // every wavefront may hold a partly filled chunk of each list
+      m.m2l_cap += static_cast<uint64_t>(c->nwaves) * fmm::kListChunk;
+      m.p2p_cap += static_cast<uint64_t>(c->nwaves) * fmm::kListChunk;
+    }
     if (!dev_alloc(&m.m2l, m.m2l_cap) || !dev_alloc(&m.p2p, m.p2p_cap)) return GTAP_E_NOMEM;
     d.m2l_list = m.m2l;
     d.p2p_list = m.p2p;
@@ -752,8 +758,9 @@ int fmm_worklist(gtap_ctx *c, FmmJobMem &m) {
       uint64_t *fin = m.front + (rounds & 1) * m.front_cap, *fout = m.front + ((rounds + 1) & 1) * m.front_cap;
       uint64_t *cnt = m.front + 2 * m.front_cap;
       if (hipMemsetAsync(cnt, 0, sizeof(uint64_t), st) != hipSuccess) return GTAP_E_HIP;
-      hipLaunchKernelGGL(fmm::k_dtt_frontier, dim3(static_cast<unsigned>((nin + 255) / 256)), dim3(256), 0, st,
-                         m.desc, fin, nin, fout, cnt, m.front_cap);
+      hipLaunchKernelGGL(fmm::k_dtt_frontier,
+                         dim3(static_cast<unsigned>((nin + fmm::kFrontierThreads - 1) / fmm::kFrontierThreads)),
+                         dim3(fmm::kFrontierThreads), 0, st, m.desc, fin, nin, fout, cnt, m.front_cap);
       if (hipMemcpyAsync(&nout, cnt, sizeof(nout), hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess)
         return GTAP_E_HIP;
@@ -800,17 +807,15 @@ int fmm_eval_lists(gtap_ctx *c, FmmJobMem &m, uint64_t n_m2l, uint64_t n_p2p, gt
   if (rocprim::radix_sort_keys(nullptr, tmp_bytes, m.m2l, m.m2l, static_cast<size_t>(nmax), 32, end_bit, st) !=
       hipSuccess)
     return GTAP_E_HIP;
-  if (!dev_alloc(&m.sorted, nmax) || !dev_alloc(&m.seg, 2 * static_cast<size_t>(m.ncells)) ||
+  // segments of targets 0..ncells (ncells: the gaps of chunked appends)
+  const size_t nseg = static_cast<size_t>(m.ncells) + 1;
+  if (!dev_alloc(&m.sorted, nmax) || !dev_alloc(&m.seg, 2 * nseg) ||
       hipMalloc(&m.lsort_tmp, tmp_bytes ? tmp_bytes : 1) != hipSuccess)
     return GTAP_E_NOMEM;
-  uint64_t *lo = m.seg, *hi = m.seg + m.ncells;
+  uint64_t *lo = m.seg, *hi = m.seg + nseg;
   fmm::FmmDesc *D = m.desc;
-  const uint64_t counts[2] = {n_m2l, n_p2p};
-  if (hipMemcpyAsync(&D->m2l_pairs, counts, sizeof(counts), hipMemcpyHostToDevice, st) != hipSuccess)
-    return GTAP_E_HIP;
-  auto prepare = [&](uint64_t *list, uint64_t cnt, uint64_t *hash) -> int {
-    if (hipMemsetAsync(m.seg, 0, sizeof(uint64_t) * 2 * static_cast<size_t>(m.ncells), st) != hipSuccess)
-      return GTAP_E_HIP;
+  auto prepare = [&](uint64_t *list, uint64_t cnt, uint64_t *hash, uint64_t *pairs) -> int {
+    if (hipMemsetAsync(m.seg, 0, sizeof(uint64_t) * 2 * nseg, st) != hipSuccess) return GTAP_E_HIP;
     if (cnt == 0) return GTAP_OK;
     size_t tb = tmp_bytes;
     if (rocprim::radix_sort_keys(m.lsort_tmp, tb, list, m.sorted, static_cast<size_t>(cnt), 32, end_bit, st) !=
@@ -818,17 +823,18 @@ int fmm_eval_lists(gtap_ctx *c, FmmJobMem &m, uint64_t n_m2l, uint64_t n_p2p, gt
       return GTAP_E_HIP;
     hipLaunchKernelGGL(fmm::k_list_segments, dim3(nblk(static_cast<int64_t>(cnt), 256)), dim3(256), 0, st, m.sorted,
                        cnt, lo, hi);
-    hipLaunchKernelGGL(fmm::k_list_hash, dim3(1024), dim3(256), 0, st, m.sorted, cnt, hash);
+    hipLaunchKernelGGL(fmm::k_list_hash, dim3(1024), dim3(256), 0, st, m.sorted, cnt,
+                       static_cast<uint32_t>(m.ncells), hash, pairs);
     return GTAP_OK;
   };
   int rc = GTAP_OK;
   if (hipEventRecord(m.lev[2], st) != hipSuccess) return GTAP_E_HIP;
-  if ((rc = prepare(m.m2l, n_m2l, &D->m2l_hash))) return rc;
+  if ((rc = prepare(m.m2l, n_m2l, &D->m2l_hash, &D->m2l_pairs))) return rc;
   if (hipEventRecord(m.lev[3], st) != hipSuccess) return GTAP_E_HIP;
   hipLaunchKernelGGL(fmm::k_m2l_list, dim3(m.ncells), dim3(fmm::kM2LThreads), 0, st, m.hdesc.cell, m.hdesc.Q,
                      m.hdesc.L, m.sorted, lo, hi);
   if (hipEventRecord(m.lev[4], st) != hipSuccess) return GTAP_E_HIP;
-  if ((rc = prepare(m.p2p, n_p2p, &D->p2p_hash))) return rc;
+  if ((rc = prepare(m.p2p, n_p2p, &D->p2p_hash, &D->p2p_pairs))) return rc;
   if (hipEventRecord(m.lev[5], st) != hipSuccess) return GTAP_E_HIP;
   hipLaunchKernelGGL(fmm::k_p2p_list, dim3(m.ncells), dim3(fmm::kP2PThreads), 0, st, m.hdesc.cell, m.hdesc.px,
                      m.hdesc.py, m.hdesc.pz, m.hdesc.pq, m.hdesc.phi, m.sorted, lo, hi, &D->p2p_inter,

@@ -797,6 +797,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   uint32_t idle = 0;
   uint32_t iter = 0;
   bool tcont = false;  // this lane's task is a resumed parent (runs its continuation)
+  fmm::ListChunks lchunks{nullptr, {0, 0}, {fmm::kListChunk, fmm::kListChunk}};  // FMM list traversal only
   uint64_t t_loop = clock64();
   // Join RMWs of the last busy iteration.  Their old values are examined in
   // the next iteration, after its tasks ran, so the RMW latency overlaps that
@@ -981,13 +982,14 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       exec_task<kFmm>(p, tid, img, o);
     }
     if constexpr (kFmm) {
-      // FMM list traversal: accepted pairs and leaf pairs go to their lists
+      // FMM list traversal: accepted pairs and leaf pairs go to their lists,
+      // through this wavefront's chunks of them
       const bool em = o.type == OUT_DONE && o.emit != 0;
       if (ballot(em) != 0ull) {
         fmm::FmmDesc *D = reinterpret_cast<fmm::FmmDesc *>(pack(o.d[3], o.d[4]));
         const uint64_t pair = (static_cast<uint64_t>(o.d[0]) << 32) | o.d[1];
-        fmm::list_append(D, 0, em && o.emit == 1, pair);
-        fmm::list_append(D, 1, em && o.emit == 2, pair);
+        fmm::chunks_append(lchunks, D, 0, em && o.emit == 1, pair);
+        fmm::chunks_append(lchunks, D, 1, em && o.emit == 2, pair);
       }
     }
     const uint32_t nfirst = __popcll(ballot(o.first != 0));
@@ -1351,6 +1353,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     t_loop = now;
   }
 
+  if constexpr (kFmm) fmm::chunks_close(lchunks);
   // ---- flush counters ----
   if (ln == 0) {
     for (int i = 0; i < static_cast<int>(ST_COUNT); ++i)
