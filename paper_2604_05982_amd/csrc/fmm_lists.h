@@ -333,80 +333,76 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_list(const int32_t *cell, c
   if (tx < static_cast<uint32_t>(kNc)) L[static_cast<size_t>(a) * kNc + tx] += lacc[tx];
 }
 
-constexpr uint32_t kP2PThreads = 128;
+constexpr uint32_t kP2PThreads = 256;
 constexpr uint32_t kP2PTileL = 64;
 
-// P2P over the sorted list: workgroup = target leaf a; thread = (target
-// tx mod 64, source group tx / 64); sources staged 64 points at a time.
-// phi[i] receives the sum once; interactions and coincident pairs are counted.
-__global__ __launch_bounds__(kP2PThreads) void k_p2p_list(const int32_t *cell, const double *px, const double *py,
-                                                          const double *pz, const double *pq, double *phi,
-                                                          const uint64_t *pairs, const uint64_t *seg_lo,
-                                                          const uint64_t *seg_hi, uint64_t *inter_out,
+// 1 / sqrt(x) for x > 0: the hardware estimate refined by two Newton-Raphson
+// steps y <- y (3 - x y^2) / 2 (each squares the relative error).
+GTAP_DEV double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
+// P2P over the sorted list: workgroup = target leaf a, lane = target point,
+// wavefront w takes the source leaves w, w + 4, ... of a's segment.  Every
+// lane of a wavefront reads the same source point at the same time, so the
+// sources come through scalar loads (no LDS staging, no barriers in the
+// loop); the four partial sums meet in LDS once per 64 targets.  phi[i]
+// receives the sum once; interactions and coincident pairs are counted.
+__global__ __launch_bounds__(kP2PThreads) void k_p2p_list(const int32_t *__restrict__ cell,
+                                                          const double *__restrict__ px,
+                                                          const double *__restrict__ py,
+                                                          const double *__restrict__ pz,
+                                                          const double *__restrict__ pq, double *phi,
+                                                          const uint64_t *__restrict__ pairs,
+                                                          const uint64_t *__restrict__ seg_lo,
+                                                          const uint64_t *__restrict__ seg_hi, uint64_t *inter_out,
                                                           uint64_t *coinc_out) {
   const uint32_t a = blockIdx.x;
   const uint64_t lo = seg_lo[a], hi = seg_hi[a];
   if (lo == hi) return;
-  constexpr uint32_t G = kP2PThreads / kP2PTileL;
-  __shared__ double sx[kP2PTileL], sy[kP2PTileL], sz[kP2PTileL], sq[kP2PTileL];
-  __shared__ double red[kP2PThreads];
-  const uint32_t tx = threadIdx.x;
-  int32_t A[kCellInts];
-  load_cell(cell, a, A);
-  const int32_t ab = A[4], ae = A[5];
+  constexpr uint32_t W = kP2PThreads / kWave;
+  __shared__ double red[W][kWave];
+  // wave-uniform source indices let the source reads be scalar loads
+  const uint32_t tx = threadIdx.x, ln = tx % kWave;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(tx / kWave);
+  const int32_t ab = cell[static_cast<size_t>(a) * kCellInts + 4], ae = cell[static_cast<size_t>(a) * kCellInts + 5];
   uint64_t coinc = 0, inter = 0;
   for (int32_t t0 = ab; t0 < ae; t0 += kP2PTileL) {
-    const int32_t i = t0 + static_cast<int32_t>(tx % kP2PTileL);
+    const int32_t i = t0 + static_cast<int32_t>(ln);
     const bool live = i < ae;
-    double xi = 0.0, yi = 0.0, zi = 0.0;
-    if (live) {
-      xi = px[i];
-      yi = py[i];
-      zi = pz[i];
-    }
+    const double xi = live ? px[i] : 0.0, yi = live ? py[i] : 0.0, zi = live ? pz[i] : 0.0;
     double acc = 0.0;
-    for (uint64_t s = lo; s < hi; ++s) {
+    for (uint64_t s = lo + wv; s < hi; s += W) {
       const uint32_t b = static_cast<uint32_t>(pairs[s]);
-      int32_t B[kCellInts];
-      load_cell(cell, b, B);
-      const int32_t bb = B[4], be = B[5];
-      if (t0 == ab && tx == 0) inter += static_cast<uint64_t>(static_cast<int64_t>(ae - ab) * (be - bb) - (a == b ? ae - ab : 0));
-      for (int32_t s0 = bb; s0 < be; s0 += kP2PTileL) {
-        const int32_t nsrc = min(static_cast<int32_t>(kP2PTileL), be - s0);
-        __syncthreads();
-        if (tx < static_cast<uint32_t>(nsrc)) {
-          sx[tx] = px[s0 + tx];
-          sy[tx] = py[s0 + tx];
-          sz[tx] = pz[s0 + tx];
-          sq[tx] = pq[s0 + tx];
+      const int32_t bb = cell[static_cast<size_t>(b) * kCellInts + 4], be = cell[static_cast<size_t>(b) * kCellInts + 5];
+      if (t0 == ab) inter += static_cast<uint64_t>(static_cast<int64_t>(ae - ab) * (be - bb) - (a == b ? ae - ab : 0));
+#pragma unroll 4
+      for (int32_t j = bb; j < be; ++j) {
+        const double dx = xi - px[j], dy = yi - py[j], dz = zi - pz[j];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 == 0.0) {
+          if (live && j != i) ++coinc;
+        } else {
+          acc += pq[j] * rsqrt_nr(r2);
         }
-        __syncthreads();
-        if (live)
-          for (int32_t j = static_cast<int32_t>(tx / kP2PTileL); j < nsrc; j += G) {
-            if (s0 + j == i) continue;
-            const double dx = xi - sx[j], dy = yi - sy[j], dz = zi - sz[j];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 == 0.0) {
-              ++coinc;
-              continue;
-            }
-            acc += sq[j] / sqrt(r2);
-          }
       }
     }
+    red[wv][ln] = acc;
     __syncthreads();
-    red[tx] = acc;
-    __syncthreads();
-    if (tx < kP2PTileL && live) {
+    if (wv == 0 && live) {
       double sum = 0.0;
 #pragma unroll
-      for (uint32_t g = 0; g < G; ++g) sum += red[tx + g * kP2PTileL];
+      for (uint32_t g = 0; g < W; ++g) sum += red[g][ln];
       phi[i] += sum;
     }
+    __syncthreads();
   }
-  if (tx == 0 && inter) fetch_add_relaxed(inter_out, inter);
+  if (ln == 0 && inter) fetch_add_relaxed(inter_out, inter);
   coinc = readlane64(wave_inclusive_sum64(coinc), 63);
-  if (lane_id() == 0 && coinc) fetch_add_relaxed(coinc_out, coinc);
+  if (ln == 0 && coinc) fetch_add_relaxed(coinc_out, coinc);
 }
 
 }  // namespace fmm
