@@ -57,7 +57,6 @@ struct BlockLds {
   int64_t bottom, top_seen;     // owner's view of its deque
   double T[fmm::kNc];
   double QB[fmm::kNc];
-  double sx[kP2PTile], sy[kP2PTile], sz[kP2PTile], sq[kP2PTile];
   double red[kMaxBlockThreads];
   uint4 lstk[2 * kBlkLocal];    // private stack (frame words 0..7 of each task)
   uint32_t lbot, ltop, local, dry;
@@ -275,8 +274,11 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
     fc.m2l_hash += fmm::pair_hash(a, b);
     return;
   }
-  // ---- P2P(A <- B), cooperative: target = tx mod 64, source group = tx / 64 ----
+  // ---- P2P(A <- B), cooperative: target = tx mod 64, wavefront w takes the
+  // sources w, w + G, ...: every lane of a wavefront reads the same source
+  // point at once (wave-uniform loads, no staging, no barriers in the loop) ----
   constexpr uint32_t G = NT / kP2PTile;
+  const int32_t wsrc = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(tx / kP2PTile));
   const int32_t ab = S.ca[4], ae = S.ca[5], bb = S.cb[4], be = S.cb[5];
   uint32_t coinc = 0;
   const bool keep_sum = (ae - ab) <= static_cast<int32_t>(kP2PTile);  // sums stay in LDS
@@ -300,27 +302,17 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
       zi = D->pz[i];
     }
     double acc = 0.0;
-    for (int32_t s0 = bb; s0 < be; s0 += kP2PTile) {
-      const int32_t ns = min(static_cast<int32_t>(kP2PTile), be - s0);
-      __syncthreads();
-      if (tx < static_cast<uint32_t>(ns)) {
-        S.sx[tx] = D->px[s0 + tx];
-        S.sy[tx] = D->py[s0 + tx];
-        S.sz[tx] = D->pz[s0 + tx];
-        S.sq[tx] = D->pq[s0 + tx];
+    const double *__restrict__ px = D->px, *__restrict__ py = D->py, *__restrict__ pz = D->pz,
+                 *__restrict__ pq = D->pq;
+#pragma unroll 4
+    for (int32_t j = bb + wsrc; j < be; j += static_cast<int32_t>(G)) {
+      const double dx = xi - px[j], dy = yi - py[j], dz = zi - pz[j];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 == 0.0) {
+        if (live && j != i) ++coinc;
+      } else {
+        acc += pq[j] * fmm::rsqrt_nr(r2);
       }
-      __syncthreads();
-      if (live)
-        for (int32_t j = static_cast<int32_t>(tx / kP2PTile); j < ns; j += G) {
-          if (s0 + j == i) continue;
-          const double dx = xi - S.sx[j], dy = yi - S.sy[j], dz = zi - S.sz[j];
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 == 0.0) {
-            ++coinc;
-            continue;
-          }
-          acc += S.sq[j] / sqrt(r2);
-        }
     }
     __syncthreads();
     S.red[tx] = acc;
