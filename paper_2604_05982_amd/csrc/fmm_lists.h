@@ -267,8 +267,9 @@ constexpr uint32_t kM2LPer = (kM2LTerms + kM2LThreads - 1) / kM2LThreads;  // 4 
 
 // M2L over the sorted list: workgroup = target cell a.  Per chunk of 32
 // sources, thread s < 32 computes source s's Taylor coefficients while all
-// threads stage the chunk's moments; then every thread adds its 4 terms
-// C(a+b, a) (-1)^|b| T_{a+b} Q_b over the chunk.  L[a] receives the sum once.
+// threads stage the chunk's moments; then every thread adds its 4 of the 924
+// terms C(a+b, a) (-1)^|b| T_{a+b} Q_b over the chunk.  L[a] receives the sum
+// once.
 __global__ __launch_bounds__(kM2LThreads) void k_m2l_list(const int32_t *cell, const double *Q, double *L,
                                                           const uint64_t *pairs, const uint64_t *seg_lo,
                                                           const uint64_t *seg_hi) {
@@ -283,12 +284,13 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_list(const int32_t *cell, c
   int32_t A[kCellInts];
   load_cell(cell, a, A);
   const double cx = cell_centre(A[1], A[0]), cy = cell_centre(A[2], A[0]), cz = cell_centre(A[3], A[0]);
-  // this thread's terms [tx * 4, tx * 4 + 4)
+  // this thread's terms tx, tx + 256, ...: the lanes of a wavefront read
+  // consecutive coefficients (no LDS bank conflicts)
   double coef[kM2LPer], acc[kM2LPer];
   uint32_t tg[kM2LPer], tb[kM2LPer], ta[kM2LPer];
 #pragma unroll
   for (uint32_t r = 0; r < kM2LPer; ++r) {
-    const uint32_t m = tx * kM2LPer + r;
+    const uint32_t m = tx + r * kM2LThreads;
     acc[r] = 0.0;
     coef[r] = 0.0;
     tg[r] = tb[r] = 0;
@@ -320,6 +322,8 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l_list(const int32_t *cell, c
       for (int t = 0; t < kNc; ++t) sT[tx][t] = T[t];
     }
     __syncthreads();
+    // (unrolled so that the LDS reads of several sources are in flight together)
+#pragma unroll 8
     for (uint32_t s = 0; s < ns; ++s) {
 #pragma unroll
       for (uint32_t r = 0; r < kM2LPer; ++r) acc[r] += coef[r] * sT[s][tg[r]] * sQ[s][tb[r]];
