@@ -745,7 +745,8 @@ int fmm_worklist(gtap_ctx *c, FmmJobMem &m) {
   for (hipEvent_t &e : m.lev)
     if (!e && hipEventCreate(&e) != hipSuccess) return GTAP_E_HIP;
   if (!m.front) {
-    m.front_cap = std::max<uint64_t>(1u << 20, (m.m2l_cap + m.p2p_cap) / 8);
+    // a frontier holds the pairs of one level: at most half of all pairs
+    m.front_cap = std::max<uint64_t>(1u << 20, (m.m2l_cap + m.p2p_cap) / 2);
     if (!dev_alloc(&m.front, 2 * m.front_cap + 1)) return GTAP_E_NOMEM;
   }
   for (int attempt = 0; attempt < 4; ++attempt) {
