@@ -62,6 +62,9 @@ def _load():
     lib.orc_kclique.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                 ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, P(_Counts)]
     lib.orc_kclique.restype = ctypes.c_int64
+    lib.orc_cilksort.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_int64, P(_Counts)]
+    lib.orc_cilksort.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -228,3 +231,15 @@ def direct(x, y, z, q, targets) -> np.ndarray:
     _fmm_lib().orc_direct(x.size, x.ctypes.data, y.ctypes.data, z.ctypes.data, q.ctypes.data, tg.ctypes.data,
                           tg.size, phi.ctypes.data)
     return phi[: tg.size]
+
+
+def cilksort(keys, sort_cutoff: int = 64, merge_cutoff: int = 256):
+    """Cilksort (GTaP Sec. 6.3) of uint32 keys: returns (sorted copy, counts).
+    counts.aux is the number of merge tasks, counts.leaves the serial sorts and
+    serial merges.  The recursion is written out in oracle/cilksort.c."""
+    x = np.array(keys, dtype=np.uint32, copy=True)
+    t = np.empty_like(x)
+    c = _Counts()
+    v = _load().orc_cilksort(x.ctypes.data, t.ctypes.data, int(x.size), int(sort_cutoff), int(merge_cutoff),
+                             ctypes.byref(c))
+    return x, _res(v, c)
