@@ -558,6 +558,49 @@ def bench_fmm_dtt(args, gtap) -> int:
     return 0
 
 
+def bench_cilksort(args, gtap) -> int:
+    """Cilksort (Sec. 6.3) of n uniform random 32-bit keys in thread mode,
+    sort / merge cutoffs 64 / 256; --queues 3 runs the paper's DAQ setup
+    (recursive, serial-sort and serial-merge queues).  value = keys sorted per
+    second (kernel time, HIP events); every run is checked for sortedness and
+    for the key sum."""
+    import torch
+    n = args.sort_n
+    g = torch.Generator(device="cuda").manual_seed(13)
+    src = torch.randint(-2**31, 2**31, (n,), dtype=torch.int64, device="cuda", generator=g).to(torch.int32)
+    ssum = int((src.to(torch.int64) & 0xFFFFFFFF).sum())
+    kw = dict(num_queues=args.queues, daq_policy=gtap.GTAP_DAQ_CILKSORT) if args.queues > 1 else {}
+    rt = gtap.Runtime(waves_per_group=4, small_frames=1 << 25, big_frames=1 << 10, deque_capacity=1 << 18,
+                      timeout_ms=120000, **kw)
+    keys = torch.empty_like(src)
+    tmp = torch.empty_like(src)
+    ms = []
+    for it in range(args.warmup + args.steps):
+        keys.copy_(src)
+        torch.cuda.synchronize()
+        jid = rt.submit_cilksort(keys, tmp, sort_cutoff=args.sort_cutoff, merge_cutoff=args.merge_cutoff)
+        rt.run()
+        st = rt.stats()
+        v = keys.to(torch.int64) & 0xFFFFFFFF
+        if rt.result(jid) != n or not bool((v[1:] >= v[:-1]).all()) or int(v.sum()) != ssum:
+            raise SystemExit("cilksort output is not the sorted input")
+        if it >= args.warmup:
+            ms.append(st["kernel_ms"])
+    rt.close()
+    med = sorted(ms)[len(ms) // 2]
+    out = {"metric": METRIC, "value": n / (med * 1e-3), "unit": "keys/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u32", "data": "synthetic",
+           "config": {"workload": f"Cilksort of {n} uniform random 32-bit keys (seed 13), sort / merge cutoffs "
+                                  f"{args.sort_cutoff} / {args.merge_cutoff}, thread mode",
+                      "queues": args.queues, "waves": st["num_waves"]},
+           "kernel_ms_median": med, "kernel_ms_min": min(ms),
+           "runtime_counters_per_run": {k: st[k] for k in ("tasks", "conts", "pushed", "stolen", "iterations",
+                                                           "idle_iterations", "local_pushed")}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -573,11 +616,14 @@ def main() -> int:
     ap.add_argument("--fmm-wpg", type=int, default=2, help="fmm: wavefronts per workgroup (1, 2, 4)")
     ap.add_argument("--fib-n", type=int, default=35, help="schedulers: fib argument")
     ap.add_argument("--fmm-thetas", default="1/2,2/5,1/3", help="fmm_dtt: MAC parameters")
+    ap.add_argument("--sort-n", type=int, default=100000000, help="cilksort: number of keys")
+    ap.add_argument("--sort-cutoff", type=int, default=64, help="cilksort: serial sort cutoff")
+    ap.add_argument("--merge-cutoff", type=int, default=256, help="cilksort: serial merge cutoff")
     ap.add_argument("--fmm-traversal", default="tasks", choices=("tasks", "lists", "worklist"),
                     help="fmm: block-mode tasks with the work inside, or a list-building traversal")
     ap.add_argument("--sched-waves", default="64,128,256,512,1024", help="schedulers: grid sizes (wavefronts)")
     ap.add_argument("--workload", default="microbench",
-                    choices=("microbench", "kclique7", "serving", "fmm", "schedulers", "fmm_dtt"),
+                    choices=("microbench", "kclique7", "serving", "fmm", "schedulers", "fmm_dtt", "cilksort"),
                     help="kclique7: 7-cliques of the n=10^6 Chung-Lu graph (DAQ comparison); "
                          "serving: batched / served job mix against one launch per job")
     ap.add_argument("--jobs", type=int, default=20000, help="serving: jobs in the trace")
@@ -607,6 +653,8 @@ def main() -> int:
         return bench_schedulers(args, gtap)
     if args.workload == "fmm_dtt":
         return bench_fmm_dtt(args, gtap)
+    if args.workload == "cilksort":
+        return bench_cilksort(args, gtap)
 
     rt = gtap.Runtime(waves_per_group=args.waves_per_group, num_waves=args.num_waves,
                       steal_below=args.steal_below, small_frames=1 << 25, timeout_ms=60000)

@@ -59,8 +59,9 @@ enum gtap_kind {
     GTAP_KIND_NQUEENS = 2,  /* gtap_nqueens_args                               */
     GTAP_KIND_UTS = 3,      /* gtap_uts_args                                   */
     GTAP_KIND_KCLIQUE = 4,  /* gtap_kclique_args                               */
-    GTAP_KIND_FMM = 5       /* gtap_fmm_args (traversal TASKS: block mode;
+    GTAP_KIND_FMM = 5,      /* gtap_fmm_args (traversal TASKS: block mode;
                                LISTS, WORKLIST: thread mode)                  */
+    GTAP_KIND_CILKSORT = 6  /* gtap_cilksort_args (thread mode)                */
 };
 
 /* Fibonacci with a task at every call (Sec. 6.3, microbenchmarks): result is
@@ -168,12 +169,33 @@ typedef struct {
     int64_t list_retries;      /* traversals re-run after a list overflowed   */
 } gtap_fmm_result;
 
+/* Cilksort (Sec. 6.3, microbenchmarks): sorts keys_dev[0, n) in place with a
+ * parallel mergesort whose merges are split in parallel too.  sort(lo, n)
+ * sorts ranges of at most sort_cutoff keys serially (a 64-wide sorting network
+ * on one lane), otherwise sorts both halves into the other buffer and merges
+ * them back; a merge of more than merge_cutoff keys splits the longer range at
+ * its middle key and the other by binary search into two independent merges.
+ * tmp_dev is a scratch buffer of n keys.  Both are device arrays borrowed
+ * until gtap_run returns.  Thread mode with four wavefronts per group; the
+ * result is n.  Requires 0 <= n < 2^29, 1 <= sort_cutoff <= 64,
+ * 2 <= merge_cutoff <= 2^20.  With num_queues >= 3 and GTAP_DAQ_CILKSORT,
+ * recursive tasks, serial sorts and serial merges wait in separate queues. */
+typedef struct {
+    uint32_t *keys_dev;
+    uint32_t *tmp_dev;
+    int64_t n;
+    int32_t sort_cutoff;
+    int32_t merge_cutoff;
+} gtap_cilksort_args;
+
 /* ---- configuration -------------------------------------------------------- */
 enum gtap_daq_policy {
     GTAP_DAQ_NONE = 0,      /* every task in queue 0                            */
     GTAP_DAQ_BY_KIND = 1,   /* queue = task kind (mod num_queues)               */
-    GTAP_DAQ_KCLIQUE = 2    /* k-clique: queue = bucket of the candidate-set
+    GTAP_DAQ_KCLIQUE = 2,   /* k-clique: queue = bucket of the candidate-set
                                bound, buckets split at daq_bounds[]            */
+    GTAP_DAQ_CILKSORT = 3   /* Cilksort: queue 0 recursive sorts and merges,
+                               1 serial sorts, 2 serial merges (mod num_queues) */
 };
 
 typedef struct gtap_config {

@@ -62,6 +62,8 @@ enum TaskKind : uint32_t {
   TK_KC_CAND = 6,
   TK_FMM = 7,       // block mode: FMM cell pair (A, B)
   TK_DTT = 8,       // thread mode: FMM cell pair (A, B) that only builds the interaction lists
+  TK_SORT = 9,      // Cilksort: sort a range into a buffer
+  TK_MERGE = 10,    // Cilksort: merge two sorted ranges
 };
 
 struct alignas(128) DequeMeta {

@@ -129,7 +129,7 @@ int validate(const gtap_config &c) {
     return GTAP_E_INVAL;
   if (c.mode == GTAP_MODE_BLOCK && (c.waves_per_group > 4 || c.num_queues != 1)) return GTAP_E_INVAL;
   if (c.num_waves < 0 || c.num_queues < 1 || c.num_queues > static_cast<int32_t>(kMaxQueues)) return GTAP_E_INVAL;
-  if (c.daq_policy < GTAP_DAQ_NONE || c.daq_policy > GTAP_DAQ_KCLIQUE) return GTAP_E_INVAL;
+  if (c.daq_policy < GTAP_DAQ_NONE || c.daq_policy > GTAP_DAQ_CILKSORT) return GTAP_E_INVAL;
   if (!is_pow2(c.deque_capacity) || c.deque_capacity < 128 || c.deque_capacity > (1u << 28)) return GTAP_E_INVAL;
   if (c.steal_below < 1 || c.steal_below > 64) return GTAP_E_INVAL;
   if (c.steal_probes < 1 || c.steal_probes > 64 || c.steal_div < 1 || c.steal_div > 64) return GTAP_E_INVAL;
@@ -397,6 +397,20 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
       J.a[5] = static_cast<uint64_t>(a.max_outdeg);
       return GTAP_OK;
     }
+    case GTAP_KIND_CILKSORT: {
+      if (args_bytes != sizeof(gtap_cilksort_args)) return GTAP_E_INVAL;
+      gtap_cilksort_args a;
+      std::memcpy(&a, args, sizeof(a));
+      if (block || c->cfg.waves_per_group != 4 || c->cfg.flags != 0) return GTAP_E_INVAL;
+      if (a.n < 0 || a.n >= (1ll << 29) || a.sort_cutoff < 1 || a.sort_cutoff > 64 || a.merge_cutoff < 2 ||
+          a.merge_cutoff > (1 << 20) || (a.n > 0 && (!a.keys_dev || !a.tmp_dev)))
+        return GTAP_E_INVAL;
+      J.a[0] = reinterpret_cast<uint64_t>(a.keys_dev);
+      J.a[1] = reinterpret_cast<uint64_t>(a.tmp_dev);
+      J.a[2] = static_cast<uint64_t>(a.n);
+      J.a[3] = static_cast<uint64_t>(a.sort_cutoff) | (static_cast<uint64_t>(a.merge_cutoff) << 32);
+      return GTAP_OK;
+    }
     case GTAP_KIND_FMM: {
       if (args_bytes != sizeof(gtap_fmm_args)) return GTAP_E_INVAL;
       gtap_fmm_args a;
@@ -476,7 +490,7 @@ static int record_run(gtap_ctx *c, const Control &ctl, float ms) {
   return GTAP_OK;
 }
 
-static int launch_sched(gtap_ctx *c, bool fmm_lists = false) {
+static int launch_sched(gtap_ctx *c, bool ext_kinds = false) {
   const uint32_t wpb = static_cast<uint32_t>(c->cfg.waves_per_group);
   const dim3 grid(c->nwaves / wpb), block(64 * wpb);
   if (c->cfg.mode == GTAP_MODE_BLOCK) {
@@ -503,7 +517,7 @@ static int launch_sched(gtap_ctx *c, bool fmm_lists = false) {
           hipLaunchKernelGGL((thread_sched_kernel<4, kSchedBatchedNoLocal>), grid, block, 0, c->stream, c->params);
           break;
         default:
-          if (fmm_lists)
+          if (ext_kinds)  // FMM list traversal, Cilksort
             hipLaunchKernelGGL((thread_sched_kernel<4, kSchedBatched, true>), grid, block, 0, c->stream, c->params);
           else
             hipLaunchKernelGGL(thread_sched_kernel<4>, grid, block, 0, c->stream, c->params);
@@ -911,8 +925,11 @@ int gtap_run(gtap_ctx *c) {
   // FMM jobs: tree and upward pass before the launch; the worklist traversal
   // runs here too (its root task in the launch is empty)
   std::vector<FmmJobMem> fm;
-  bool any_fmm = false;
-  for (size_t j = 0; j < nj; ++j) any_fmm |= c->pending[j].kind == GTAP_KIND_FMM;
+  bool any_fmm = false, any_ext = false;
+  for (size_t j = 0; j < nj; ++j) {
+    any_fmm |= c->pending[j].kind == GTAP_KIND_FMM;
+    any_ext |= c->pending[j].kind == GTAP_KIND_FMM || c->pending[j].kind == GTAP_KIND_CILKSORT;
+  }
   auto drop_pending = [&]() {
     for (FmmJobMem &m : fm) fmm_free(m);
     c->pending.clear();
@@ -952,7 +969,7 @@ int gtap_run(gtap_ctx *c) {
     const uint32_t ndq = c->nwaves * p.Q;
     hipLaunchKernelGGL(reset_kernel, dim3(reset_blocks(ndq, p.ccap)), dim3(256), 0, c->stream, p, ndq);
     if (hipGetLastError() != hipSuccess || hipEventRecord(c->ev0, c->stream) != hipSuccess) rc = GTAP_E_HIP;
-    if (rc == GTAP_OK) rc = launch_sched(c, any_fmm && !block);
+    if (rc == GTAP_OK) rc = launch_sched(c, any_ext && !block);
     if (rc == GTAP_OK && hipEventRecord(c->ev1, c->stream) != hipSuccess) rc = GTAP_E_HIP;
     if (rc != GTAP_OK) {
       (void)hipStreamSynchronize(c->stream);
@@ -1079,6 +1096,8 @@ int gtap_serve_start(gtap_ctx *c, uint32_t max_inflight, uint32_t headroom_small
 int gtap_serve_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, uint64_t *ticket) {
   if (!c || !ticket) return GTAP_E_INVAL;
   if (!c->serving) return GTAP_E_STATE;
+  // the serving kernel runs the scheduler as designed: no FMM, no Cilksort
+  if (kind == GTAP_KIND_FMM || kind == GTAP_KIND_CILKSORT) return GTAP_E_INVAL;
   JobSlot J;
   const int rc = pack_job(c, kind, args, args_bytes, J);
   if (rc) return rc;

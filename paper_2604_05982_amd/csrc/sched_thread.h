@@ -601,7 +601,7 @@ GTAP_DEV uint32_t owner_of(const uint32_t *offs, uint32_t g) {
 }
 
 // Root frame of job slot j (payload from the job's arguments).
-template <bool kFmm = false>
+template <bool kExt = false>
 GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
   const uint32_t jkind = static_cast<uint32_t>(co_ld64(reinterpret_cast<const uint64_t *>(p.jobs + j)));
   ChildInit c;
@@ -635,7 +635,13 @@ GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
     default:
       break;
   }
-  if constexpr (kFmm) {
+  if constexpr (kExt) {
+    if (jkind == 6) {  // Cilksort: sort the whole array into the key buffer
+      kind = TK_SORT;
+      c.p[0] = 0;
+      c.p[1] = static_cast<uint32_t>(job_arg(p, j, 2));
+      c.p[2] = 0;
+    }
     // FMM in thread mode: the list-building traversal starts at the pair
     // (root, root); a job whose lists the worklist builds has an empty root
     // (a[0] descriptor, a[1] traversal, a[2] = theta_num | theta_den << 8)
@@ -730,9 +736,9 @@ struct LocalCap {
 
 // V selects the queue management (kSchedBatched, kSchedSingle, kSchedCentral;
 // kSchedBatchedNoLocal = batched without the private stack) at compile time,
-// so the comparison variants add nothing to the scheduler as designed; kFmm
+// so the comparison variants add nothing to the scheduler as designed; kExt
 // adds the FMM list-building cell-pair tasks and their list appends.
-template <int WPB, uint32_t V = kSchedBatched, bool kFmm = false>
+template <int WPB, uint32_t V = kSchedBatched, bool kExt = false>
 __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   constexpr bool kCentral = (V == kSchedCentral);
   constexpr bool kSingle = (V == kSchedSingle);
@@ -783,7 +789,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     const bool ok = alloc_frames(p, PS, me, nroots, ar, wc);
     if (ok && nroots > 0) {
       wave_sync();
-      for (uint32_t g = ln; g < nroots; g += kWave) write_root<kFmm>(p, alloc_id(PS, ar, g), me + g * p.nwaves);
+      for (uint32_t g = ln; g < nroots; g += kWave) write_root<kExt>(p, alloc_id(PS, ar, g), me + g * p.nwaves);
       drain();
       const uint32_t keep = nroots < kWave ? nroots : kWave;
       if (ln < keep) tid = alloc_id(PS, ar, ln);
@@ -968,7 +974,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     o.big = 0;
     o.first = 0;
     for (int i = 0; i < 6; ++i) o.d[i] = 0;
-    if constexpr (kFmm) o.emit = 0;
+    if constexpr (kExt) o.emit = 0;
     if (ln < cnt) {
       TaskImage img;
       if (tid == kNone) {
@@ -979,9 +985,9 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       } else {
         img = load_image(p, tid);
       }
-      exec_task<kFmm>(p, tid, img, o);
+      exec_task<kExt>(p, tid, img, o);
     }
-    if constexpr (kFmm) {
+    if constexpr (kExt) {
       // FMM list traversal: accepted pairs and leaf pairs go to their lists,
       // through this wavefront's chunks of them
       const bool em = o.type == OUT_DONE && o.emit != 0;
@@ -1044,6 +1050,11 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         cpre_ok = true;
       }
     }
+    if constexpr (kExt) {
+      // Cilksort: keys a task wrote are complete before its completion can
+      // resume the parent that hands them to the next task
+      if (ballot(done && (o.kind == TK_SORT || o.kind == TK_MERGE)) != 0ull) drain();
+    }
     const int64_t lim = static_cast<int64_t>(1) << kSmallValueBits;
     const bool big_val = tail && (run_val >= lim || run_val <= -lim);
     if (ballot(big_val)) {
@@ -1088,7 +1099,17 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       const uint32_t self = need_self ? alloc_id(PS, aself, rank_below(m_self)) : tid;
       uint32_t *f = frame_ptr(p, self);
       if (need_self) co_st64(frame64(f), pack(o.parent, o.job));
-      co_st32(f + FW_STATE, state_word(o.kind, 1, 0));
+      if constexpr (kExt) {
+        // Cilksort: a sort resumes twice and reads its range from the frame
+        co_st32(f + FW_STATE, state_word(o.kind, o.pc_next, 0));
+        if (need_self && o.kind == TK_SORT) {
+          co_st32(f + FW_P0, o.d[0]);
+          co_st32(f + FW_P0 + 1, o.d[1]);
+          co_st32(f + FW_P0 + 2, o.d[2]);
+        }
+      } else {
+        co_st32(f + FW_STATE, state_word(o.kind, 1, 0));
+      }
       st_relaxed(bigacc_ptr(f), static_cast<int64_t>(0));
       st_relaxed(join_ptr(f), static_cast<int64_t>(o.nchild));
       L.desc[ln] = ForkDesc{self, o.job, o.ckind | (o.big << 7) | (o.d[5] << 8),
@@ -1110,8 +1131,8 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
           const ForkDesc dsc = L.desc[own];
           const uint32_t d[6] = {dsc.d0, dsc.d1, dsc.d2, dsc.d3, dsc.d4, dsc.ckind_big_d5 >> 8};
           ChildInit ci;
-          make_child<kFmm>(dsc.ckind_big_d5 & 0x7Fu, d, g - L.offs[own], ci);
-          c = child_class(p, dsc.job, dsc.ckind_big_d5 & 0x7Fu, ci);
+          make_child<kExt>(dsc.ckind_big_d5 & 0x7Fu, d, g - L.offs[own], ci);
+          c = child_class<kExt>(p, dsc.job, dsc.ckind_big_d5 & 0x7Fu, ci);
           if (g < kClassCache) L.cls[g] = static_cast<uint8_t>(c);
         }
         for (uint32_t qq = 0; qq < p.Q; ++qq) {
@@ -1220,8 +1241,8 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         j = g - L.offs[own];
         dsc = L.desc[own];
         const uint32_t d[6] = {dsc.d0, dsc.d1, dsc.d2, dsc.d3, dsc.d4, dsc.ckind_big_d5 >> 8};
-        make_child<kFmm>(dsc.ckind_big_d5 & 0x7Fu, d, j, ci);
-        if (p.Q > 1) c = g < kClassCache ? L.cls[g] : child_class(p, dsc.job, dsc.ckind_big_d5 & 0x7Fu, ci);
+        make_child<kExt>(dsc.ckind_big_d5 & 0x7Fu, d, j, ci);
+        if (p.Q > 1) c = g < kClassCache ? L.cls[g] : child_class<kExt>(p, dsc.job, dsc.ckind_big_d5 & 0x7Fu, ci);
       }
       const bool big = act && (dsc.ckind_big_d5 & 0x80u);
       // rank of this child within its class
@@ -1353,7 +1374,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     t_loop = now;
   }
 
-  if constexpr (kFmm) fmm::chunks_close(lchunks);
+  if constexpr (kExt) fmm::chunks_close(lchunks);
   // ---- flush counters ----
   if (ln == 0) {
     for (int i = 0; i < static_cast<int>(ST_COUNT); ++i)

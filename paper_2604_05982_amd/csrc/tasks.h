@@ -36,6 +36,7 @@ struct Outcome {
   uint32_t kind;     // this task's kind
   uint32_t first;    // 1: first execution (resume point 0), 0: continuation
   uint32_t emit;     // FMM list traversal: 1 = M2L pair, 2 = P2P pair (d[0], d[1]), descriptor d[3..4]
+  uint32_t pc_next;  // OUT_FORK of the extended kinds: resume point after the join (Cilksort sorts fork twice)
 };
 
 // Payload of a new frame (words 3..7).
@@ -142,11 +143,52 @@ GTAP_DEV TaskImage load_continuation(const Params &p, uint32_t tid) {
 }
 
 // ---------------------------------------------------------------------------
+// Cilksort pieces (Sec. 6.3).  Buffers: job argument 0 = keys, 1 = scratch;
+// a task's destination bit picks one, its sources are in the other.  Keys
+// pass between tasks that may run on different XCDs, so they are read and
+// written with device-coherent accesses (and the scheduler drains a
+// wavefront's writes before its completions reach the join words).
+constexpr uint32_t kSortNet = 64;            // serial sorts: a 64-wide network
+constexpr uint32_t kMergeD = (1u << 29) - 1;  // merge payload word 4: destination start
+
+// Bitonic sorting network on 64 keys held in registers (all indices are
+// compile-time constants after unrolling, so nothing spills to scratch).
+GTAP_DEV void sort_net64(uint32_t *v) {
+#pragma unroll
+  for (uint32_t k = 2; k <= kSortNet; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (uint32_t i = 0; i < kSortNet; ++i) {
+        const uint32_t l = i ^ j;
+        if (l > i) {
+          const uint32_t lo = v[i] < v[l] ? v[i] : v[l], hi = v[i] < v[l] ? v[l] : v[i];
+          const bool up = (i & k) == 0;
+          v[i] = up ? lo : hi;
+          v[l] = up ? hi : lo;
+        }
+      }
+    }
+  }
+}
+
+// Number of keys of the sorted range s[0, n) below v.
+GTAP_DEV uint32_t count_below(const uint32_t *s, uint32_t n, uint32_t v) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if (co_ld32(s + mid) < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
 // Execute one task on this lane.  tid is its frame, or kNone for a task
-// without one (then it runs at resume point 0 and needs no buffer).  kFmm
+// without one (then it runs at resume point 0 and needs no buffer).  kExt
 // adds the list-building FMM cell-pair task (instantiated separately, so the
 // other task kinds compile unchanged).
-template <bool kFmm = false>
+template <bool kExt = false>
 GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Outcome &o) {
   uint32_t *f = tid != kNone ? frame_ptr(p, tid) : nullptr;
   const uint64_t w01 = img.w01;
@@ -162,7 +204,27 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
   o.nchild = 0;
   o.big = 0;
   o.value = 0;
-  if constexpr (kFmm) o.emit = 0;
+  if constexpr (kExt) {
+    o.emit = 0;
+    o.pc_next = 1;
+    if (pc != 0 && kind == TK_SORT) {
+      // after the two sorts: merge them back (resume point 2 follows); after
+      // the merge: done, the result is the range's length
+      uint32_t *f = frame_ptr(p, tid);
+      const uint32_t lo = co_ld32(f + FW_P0), n = co_ld32(f + FW_P0 + 1), dst = co_ld32(f + FW_P0 + 2);
+      if (pc == 1) {
+        const uint32_t h = n / 2;
+        o.type = OUT_FORK;
+        o.nchild = 1;
+        o.ckind = TK_MERGE;
+        o.d[0] = lo; o.d[1] = h; o.d[2] = lo + h; o.d[3] = n - h; o.d[4] = lo | (dst << 31); o.d[5] = 0;
+        o.pc_next = 2;
+        return;
+      }
+      o.value = n;
+      return;
+    }
+  }
 
   if (pc != 0) {
     // Continuation after the join (image from load_continuation): every kind
@@ -177,7 +239,75 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
   const uint32_t p0 = static_cast<uint32_t>(w23 >> 32);
   const uint32_t p1 = static_cast<uint32_t>(w45), p2 = static_cast<uint32_t>(w45 >> 32);
   const uint32_t p3 = static_cast<uint32_t>(w67), p4 = static_cast<uint32_t>(w67 >> 32);
-  if constexpr (kFmm) {
+  if constexpr (kExt) {
+    if (kind == TK_SORT) {
+      // sort(lo, n, dst): serial below the cutoff, else both halves into the
+      // other buffer first (resume point 1 merges them)
+      const uint32_t lo = p0, n = p1, dst = p2;
+      const uint32_t sc = static_cast<uint32_t>(job_arg(p, o.job, 3));
+      if (n <= sc) {
+        const uint32_t *X = reinterpret_cast<const uint32_t *>(job_arg(p, o.job, 0));
+        uint32_t *D = reinterpret_cast<uint32_t *>(job_arg(p, o.job, dst ? 1 : 0));
+        uint32_t v[kSortNet];
+#pragma unroll
+        for (uint32_t i = 0; i < kSortNet; ++i) v[i] = i < n ? co_ld32(X + lo + i) : 0xFFFFFFFFu;
+        sort_net64(v);
+#pragma unroll
+        for (uint32_t i = 0; i < kSortNet; ++i)
+          if (i < n) co_st32(D + lo + i, v[i]);
+        o.value = n;
+        return;
+      }
+      o.type = OUT_FORK;
+      o.nchild = 2;
+      o.ckind = TK_SORT;
+      o.d[0] = lo; o.d[1] = n; o.d[2] = dst;
+      return;
+    }
+    if (kind == TK_MERGE) {
+      // merge(A, B -> D): payload A = (p0, p1), B = (p2, p3), p4 = destination
+      // start | split pending << 29 | side << 30 | destination buffer << 31.
+      // A pending split first takes its side of the parent's ranges.
+      uint32_t a0 = p0, na = p1, b0 = p2, nb = p3;
+      const uint32_t dst = p4 >> 31;
+      uint32_t d0 = p4 & kMergeD;
+      const uint32_t *S = reinterpret_cast<const uint32_t *>(job_arg(p, o.job, dst ? 0 : 1));
+      uint32_t *D = reinterpret_cast<uint32_t *>(job_arg(p, o.job, dst ? 1 : 0));
+      if ((p4 >> 29) & 1u) {
+        const uint32_t ma = na / 2, mb = count_below(S + b0, nb, co_ld32(S + a0 + ma));
+        if ((p4 >> 30) & 1u) {
+          a0 += ma; na -= ma; b0 += mb; nb -= mb; d0 += ma + mb;
+        } else {
+          na = ma; nb = mb;
+        }
+      }
+      if (nb > na) {
+        const uint32_t t0 = a0, t1 = na;
+        a0 = b0; na = nb; b0 = t0; nb = t1;
+      }
+      const uint32_t mc = static_cast<uint32_t>(job_arg(p, o.job, 3) >> 32);
+      if (na + nb <= mc) {
+        uint32_t i = 0, j = 0, k = d0;
+        while (i < na && j < nb) {
+          const uint32_t x = co_ld32(S + a0 + i), y = co_ld32(S + b0 + j);
+          if (y < x) {
+            co_st32(D + k++, y);
+            ++j;
+          } else {
+            co_st32(D + k++, x);
+            ++i;
+          }
+        }
+        while (i < na) co_st32(D + k++, co_ld32(S + a0 + i++));
+        while (j < nb) co_st32(D + k++, co_ld32(S + b0 + j++));
+        return;
+      }
+      o.type = OUT_FORK;
+      o.nchild = 2;
+      o.ckind = TK_MERGE;
+      o.d[0] = a0; o.d[1] = na; o.d[2] = b0; o.d[3] = nb; o.d[4] = d0 | (dst << 31); o.d[5] = 1;
+      return;
+    }
     if (kind == TK_DTT) {
       // FMM cell pair (A, B) (Sec. 6.4.1): an accepted pair or a pair of
       // leaves goes to its list (the scheduler appends it, one atomic per
@@ -340,8 +470,21 @@ GTAP_DEV uint32_t bucket_of(const Params &p, uint32_t x) {
 // of its intersection and thus on its cost; a vertex task by its out-degree
 // (its candidate set is N+(v)); a vertex-range task, whose subtree spans many
 // vertices, by the highest class.
+template <bool kExt = false>
 GTAP_DEV uint32_t child_class(const Params &p, uint32_t job, uint32_t ckind, const ChildInit &c) {
   if (p.Q <= 1) return 0;
+  if constexpr (kExt) {
+    if (p.daq_policy == 3) {  // Cilksort: recursive 0, serial sort 1, serial merge 2
+      const uint64_t cut = job_arg(p, job, 3);
+      if (ckind == TK_SORT) return (c.p[1] <= static_cast<uint32_t>(cut) ? 1u : 0u) % p.Q;
+      if (ckind == TK_MERGE) {
+        const uint32_t m = c.p[1] + c.p[3];  // a pending split takes about half
+        const uint32_t est = ((c.p[4] >> 29) & 1u) ? m / 2 : m;
+        return (est <= static_cast<uint32_t>(cut >> 32) ? 2u : 0u) % p.Q;
+      }
+      return 0;
+    }
+  }
   switch (p.daq_policy) {
     case 1: {  // by kind
       const uint32_t k = ckind == TK_FIB ? 0u : ckind == TK_NQ ? 1u : ckind == TK_UTS ? 2u : 3u;
@@ -371,10 +514,22 @@ GTAP_DEV uint32_t nth_set_bit(uint32_t m, uint32_t j) {
 
 // Payload of child j of a forked parent with child kind `ckind` and
 // descriptor d.
-template <bool kFmm = false>
+template <bool kExt = false>
 GTAP_DEV void make_child(uint32_t ckind, const uint32_t *d, uint32_t j, ChildInit &c) {
   for (uint32_t i = 0; i < kPayloadWords; ++i) c.p[i] = 0;
-  if constexpr (kFmm) {
+  if constexpr (kExt) {
+    if (ckind == TK_SORT) {  // half j into the other buffer
+      const uint32_t h = d[1] / 2;
+      c.p[0] = d[0] + (j ? h : 0u);
+      c.p[1] = j ? d[1] - h : h;
+      c.p[2] = d[2] ^ 1u;
+      return;
+    }
+    if (ckind == TK_MERGE) {  // d[5] = 0: the merge of a sort; 1: side j of a split
+      c.p[0] = d[0]; c.p[1] = d[1]; c.p[2] = d[2]; c.p[3] = d[3];
+      c.p[4] = d[5] ? (d[4] | (1u << 29) | (j << 30)) : d[4];
+      return;
+    }
     if (ckind == TK_DTT) {  // pair (child j of the split cell, the other cell)
       const bool sa = (d[2] >> 31) != 0;
       const uint32_t c0 = d[2] & 0x7FFFFFFFu;

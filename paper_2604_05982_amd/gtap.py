@@ -39,6 +39,7 @@ GTAP_KIND_NQUEENS = 2
 GTAP_KIND_UTS = 3
 GTAP_KIND_KCLIQUE = 4
 GTAP_KIND_FMM = 5
+GTAP_KIND_CILKSORT = 6
 
 GTAP_FMM_TASKS = 0
 GTAP_FMM_LISTS = 1
@@ -47,6 +48,7 @@ GTAP_FMM_WORKLIST = 2
 GTAP_DAQ_NONE = 0
 GTAP_DAQ_BY_KIND = 1
 GTAP_DAQ_KCLIQUE = 2
+GTAP_DAQ_CILKSORT = 3
 
 # scheduler variants (config.flags): the scheduler comparison of Sec. 6.5
 GTAP_FLAG_NO_PRIVATE_STACK = 1
@@ -103,6 +105,11 @@ class gtap_fmm_args(ctypes.Structure):
                 ("leaf_max", ctypes.c_int32), ("theta_num", ctypes.c_int32), ("theta_den", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("traversal", ctypes.c_int32),
                 ("m2l_capacity", ctypes.c_uint64), ("p2p_capacity", ctypes.c_uint64)]
+
+
+class gtap_cilksort_args(ctypes.Structure):
+    _fields_ = [("keys_dev", ctypes.c_void_p), ("tmp_dev", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("sort_cutoff", ctypes.c_int32), ("merge_cutoff", ctypes.c_int32)]
 
 
 class gtap_fmm_result(ctypes.Structure):
@@ -443,6 +450,21 @@ class Runtime:
                            gtap_fmm_args(ts[0].data_ptr(), ts[1].data_ptr(), ts[2].data_ptr(), ts[3].data_ptr(),
                                          phi.data_ptr(), n, int(leaf_max), int(theta[0]), int(theta[1]),
                                          int(order), int(traversal), int(m2l_capacity), int(p2p_capacity)))
+
+    def submit_cilksort(self, keys, tmp=None, sort_cutoff: int = 64, merge_cutoff: int = 256) -> int:
+        """Cilksort job: keys is a contiguous uint32 (or int32 viewed as
+        unsigned) CUDA tensor sorted in place by run(); tmp a scratch tensor of
+        the same size (allocated here if not given), both kept alive until
+        run() returns.  The job's result is the number of keys."""
+        torch = self._torch
+        if not (keys.is_cuda and keys.is_contiguous() and keys.element_size() == 4):
+            raise ValueError("keys must be a contiguous 32-bit CUDA tensor")
+        if tmp is None:
+            tmp = torch.empty_like(keys)
+        self._keep.append((keys, tmp))
+        return gtap_submit(self.ctx, GTAP_KIND_CILKSORT,
+                           gtap_cilksort_args(keys.data_ptr(), tmp.data_ptr(), keys.numel(), int(sort_cutoff),
+                                              int(merge_cutoff)))
 
     def fmm_result(self, job_id: int) -> dict:
         r = gtap_fmm_result()

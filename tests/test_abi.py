@@ -38,7 +38,7 @@ def test_struct_layout_matches_header(tmp_path):
     import subprocess
     from paper_2604_05982_amd import gtap
     structs = [gtap.gtap_config, gtap.gtap_fib_args, gtap.gtap_nqueens_args, gtap.gtap_uts_args,
-               gtap.gtap_kclique_args, gtap.gtap_fmm_args, gtap.gtap_fmm_result, gtap.gtap_stats,
+               gtap.gtap_kclique_args, gtap.gtap_fmm_args, gtap.gtap_fmm_result, gtap.gtap_cilksort_args, gtap.gtap_stats,
                gtap.gtap_error_report, gtap.gtap_trace_job, gtap.gtap_trace_result, gtap.gtap_tune_space,
                gtap.gtap_tune_report]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gtap.h"', "int main(void){"]
