@@ -261,80 +261,89 @@ GTAP_DEV void taylor_coeffs(double d0, double d1, double d2, double *T) {
   }
 }
 
-constexpr uint32_t kM2LThreads = 256;
-constexpr uint32_t kM2LChunk = 32;
-constexpr uint32_t kM2LPer = (kM2LTerms + kM2LThreads - 1) / kM2LThreads;  // 4 terms per thread
+constexpr uint32_t kM2LThreads = 64;
 
-// M2L over the sorted list: workgroup = target cell a.  Per chunk of 32
-// sources, thread s < 32 computes source s's Taylor coefficients while all
-// threads stage the chunk's moments; then every thread adds its 4 of the 924
-// terms C(a+b, a) (-1)^|b| T_{a+b} Q_b over the chunk.  L[a] receives the sum
-// once.
-__global__ __launch_bounds__(kM2LThreads) void k_m2l_list(const int32_t *cell, const double *Q, double *L,
-                                                          const uint64_t *pairs, const uint64_t *seg_lo,
-                                                          const uint64_t *seg_hi) {
+GTAP_DEV double mfact(int t) {  // e_t! = e_x! e_y! e_z! of coefficient t
+  const double f[kP + 1] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0};
+  return f[kTab.e[t][0]] * f[kTab.e[t][1]] * f[kTab.e[t][2]];
+}
+
+// Moments scaled for the list M2L: Q'_b = (-1)^|b| Q_b / b! (in place; the
+// list pipeline reads the moments only in M2L).
+__global__ void k_scale_moments(double *Q, int64_t ncells) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= ncells * kNc) return;
+  const int t = static_cast<int>(i % kNc);
+  Q[i] *= ((kTab.deg[t] & 1) ? -1.0 : 1.0) / mfact(t);
+}
+
+// Scaled Taylor coefficients T'_g = g! T_g of 1/|d + h| at h = 0 (total degree
+// <= 6): the Coulomb three-term recurrence multiplied by g! becomes
+// T'_g = -[(2n-1) sum_i g_i d_i T'_{g-e_i} + (n-1) sum_i g_i (g_i - 1) T'_{g-2e_i}] / (n r^2),
+// n = |g|.  Fully unrolled, T' stays in registers.
+GTAP_DEV void taylor_scaled(double d0, double d1, double d2, double *T) {
+  const double inv_r2 = 1.0 / (d0 * d0 + d1 * d1 + d2 * d2);
+  T[0] = sqrt(inv_r2);
+  const double dd[3] = {d0, d1, d2};
+#pragma unroll
+  for (int t = 1; t < kNc; ++t) {
+    const double n = static_cast<double>(kTab.deg[t]);
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double gi = static_cast<double>(kTab.e[t][i]);
+      const uint8_t m1 = kTab.dm1[t][i], m2 = kTab.dm2[t][i];
+      if (m1 != 0xFF) s1 += gi * dd[i] * T[m1];
+      if (m2 != 0xFF) s2 += gi * (gi - 1.0) * T[m2];
+    }
+    T[t] = -((2.0 * n - 1.0) * s1 + (n - 1.0) * s2) * inv_r2 / n;
+  }
+}
+
+// M2L over the sorted list: one wavefront per target cell a, one source per
+// lane at a time.  With T' and Q' (above), L_a = (1/a!) sum_b T'_{a+b} Q'_b, so
+// a lane keeps the source's 84 coefficients T' and its own 84 sums in
+// registers and adds T'_{a+b} Q'_b for every (a, b) with |a| + |b| <= 6 --
+// 924 fused multiply-adds, all indices compile-time constants, no LDS.  The
+// 64 partial sums are combined by lane shuffles and added to L[a] once.
+__global__ __launch_bounds__(kM2LThreads) void k_m2l_list(const int32_t *__restrict__ cell,
+                                                          const double *__restrict__ Qs, double *L,
+                                                          const uint64_t *__restrict__ pairs,
+                                                          const uint64_t *__restrict__ seg_lo,
+                                                          const uint64_t *__restrict__ seg_hi) {
   const uint32_t a = blockIdx.x;
   const uint64_t lo = seg_lo[a], hi = seg_hi[a];
   if (lo == hi) return;
-  __shared__ double sT[kM2LChunk][kNc + 1];
-  __shared__ double sQ[kM2LChunk][kNc + 1];
-  __shared__ double lacc[kNc];
-  const uint32_t tx = threadIdx.x;
-  if (tx < static_cast<uint32_t>(kNc)) lacc[tx] = 0.0;
+  const uint32_t ln = threadIdx.x;
   int32_t A[kCellInts];
   load_cell(cell, a, A);
   const double cx = cell_centre(A[1], A[0]), cy = cell_centre(A[2], A[0]), cz = cell_centre(A[3], A[0]);
-  // this thread's terms tx, tx + 256, ...: the lanes of a wavefront read
-  // consecutive coefficients (no LDS bank conflicts)
-  double coef[kM2LPer], acc[kM2LPer];
-  uint32_t tg[kM2LPer], tb[kM2LPer], ta[kM2LPer];
+  double acc[kNc];
 #pragma unroll
-  for (uint32_t r = 0; r < kM2LPer; ++r) {
-    const uint32_t m = tx + r * kM2LThreads;
-    acc[r] = 0.0;
-    coef[r] = 0.0;
-    tg[r] = tb[r] = 0;
-    ta[r] = 0xFFu;
-    if (m < static_cast<uint32_t>(kM2LTerms)) {
-      coef[r] = kTab.m2l_c[m];
-      tg[r] = kTab.m2l_g[m];
-      tb[r] = kTab.m2l_b[m];
-      uint32_t t = 0;
-      while (kTab.m2l_first[t + 1] <= m) ++t;
-      ta[r] = t;
+  for (int t = 0; t < kNc; ++t) acc[t] = 0.0;
+  for (uint64_t s = lo + ln; s < hi; s += kM2LThreads) {
+    const uint32_t b = static_cast<uint32_t>(pairs[s]);
+    int32_t B[kCellInts];
+    load_cell(cell, b, B);
+    double T[kNc];
+    taylor_scaled(cx - cell_centre(B[1], B[0]), cy - cell_centre(B[2], B[0]), cz - cell_centre(B[3], B[0]), T);
+    const double *q = Qs + static_cast<size_t>(b) * kNc;
+#pragma unroll
+    for (int tb = 0; tb < kNc; ++tb) {
+      const double qb = q[tb];
+#pragma unroll
+      for (int ta = 0; ta < ncoef(kP - kTab.deg[tb]); ++ta)
+        acc[ta] += T[kTab.idx[kTab.e[ta][0] + kTab.e[tb][0]][kTab.e[ta][1] + kTab.e[tb][1]]
+                             [kTab.e[ta][2] + kTab.e[tb][2]]] * qb;
     }
   }
-  for (uint64_t s0 = lo; s0 < hi; s0 += kM2LChunk) {
-    const uint32_t ns = static_cast<uint32_t>(hi - s0 < kM2LChunk ? hi - s0 : kM2LChunk);
-    __syncthreads();  // the previous chunk's terms are done
-    for (uint32_t idx = tx; idx < ns * static_cast<uint32_t>(kNc); idx += kM2LThreads) {
-      const uint32_t s = idx / kNc, t = idx % kNc;
-      const uint32_t b = static_cast<uint32_t>(pairs[s0 + s]);
-      sQ[s][t] = Q[static_cast<size_t>(b) * kNc + t];
-    }
-    if (tx < ns) {
-      const uint32_t b = static_cast<uint32_t>(pairs[s0 + tx]);
-      int32_t B[kCellInts];
-      load_cell(cell, b, B);
-      double T[kNc];
-      taylor_coeffs(cx - cell_centre(B[1], B[0]), cy - cell_centre(B[2], B[0]), cz - cell_centre(B[3], B[0]), T);
 #pragma unroll
-      for (int t = 0; t < kNc; ++t) sT[tx][t] = T[t];
-    }
-    __syncthreads();
-    // (unrolled so that the LDS reads of several sources are in flight together)
-#pragma unroll 8
-    for (uint32_t s = 0; s < ns; ++s) {
+  for (int t = 0; t < kNc; ++t) {
+    double v = acc[t];
 #pragma unroll
-      for (uint32_t r = 0; r < kM2LPer; ++r) acc[r] += coef[r] * sT[s][tg[r]] * sQ[s][tb[r]];
-    }
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (ln == 0) L[static_cast<size_t>(a) * kNc + t] += v / mfact(t);
   }
-  __syncthreads();
-#pragma unroll
-  for (uint32_t r = 0; r < kM2LPer; ++r)
-    if (ta[r] != 0xFFu) atomicAdd(&lacc[ta[r]], acc[r]);
-  __syncthreads();
-  if (tx < static_cast<uint32_t>(kNc)) L[static_cast<size_t>(a) * kNc + tx] += lacc[tx];
 }
 
 constexpr uint32_t kP2PThreads = 256;

@@ -846,6 +846,8 @@ int fmm_eval_lists(gtap_ctx *c, FmmJobMem &m, uint64_t n_m2l, uint64_t n_p2p, gt
   if (hipEventRecord(m.lev[2], st) != hipSuccess) return GTAP_E_HIP;
   if ((rc = prepare(m.m2l, n_m2l, &D->m2l_hash, &D->m2l_pairs))) return rc;
   if (hipEventRecord(m.lev[3], st) != hipSuccess) return GTAP_E_HIP;
+  hipLaunchKernelGGL(fmm::k_scale_moments, dim3(nblk(static_cast<int64_t>(m.ncells) * fmm::kNc, 256)), dim3(256), 0,
+                     st, m.Q, static_cast<int64_t>(m.ncells));
   hipLaunchKernelGGL(fmm::k_m2l_list, dim3(m.ncells), dim3(fmm::kM2LThreads), 0, st, m.hdesc.cell, m.hdesc.Q,
                      m.hdesc.L, m.sorted, lo, hi);
   if (hipEventRecord(m.lev[4], st) != hipSuccess) return GTAP_E_HIP;
