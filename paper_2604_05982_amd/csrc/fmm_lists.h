@@ -358,11 +358,14 @@ GTAP_DEV double rsqrt_nr(double x) {
   return y;
 }
 
-// P2P over the sorted list: workgroup = target leaf a, lane = target point,
-// wavefront w takes the source leaves w, w + 4, ... of a's segment.  Every
-// lane of a wavefront reads the same source point at the same time, so the
-// sources come through scalar loads (no LDS staging, no barriers in the
-// loop); the four partial sums meet in LDS once per 64 targets.  phi[i]
+// P2P over the sorted list: workgroup = target leaf a; wavefront w takes the
+// source leaves w, w + 4, ... of a's segment.  A tile of at most 16 targets is
+// padded to a power of two P, and the wavefront's lanes form 64 / P groups of
+// P: lane = (target, group), group g takes the source points g, g + 64/P, ...
+// of each source leaf, so small leaves still keep most lanes busy; larger
+// tiles take one target per lane and read each source point as one
+// wavefront-uniform (scalar) load.  Partial
+// sums meet by lane shuffles, then across the four wavefronts in LDS; phi[i]
 // receives the sum once; interactions and coincident pairs are counted.
 __global__ __launch_bounds__(kP2PThreads) void k_p2p_list(const int32_t *__restrict__ cell,
                                                           const double *__restrict__ px,
@@ -384,28 +387,49 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p_list(const int32_t *__restr
   const int32_t ab = cell[static_cast<size_t>(a) * kCellInts + 4], ae = cell[static_cast<size_t>(a) * kCellInts + 5];
   uint64_t coinc = 0, inter = 0;
   for (int32_t t0 = ab; t0 < ae; t0 += kP2PTileL) {
-    const int32_t i = t0 + static_cast<int32_t>(ln);
-    const bool live = i < ae;
+    const int32_t nt = min(static_cast<int32_t>(kP2PTileL), ae - t0);
+    // (tiles of more than 16 targets keep one group: their lanes read the
+    // same source point, which the scalar loads serve best)
+    uint32_t P = 1;
+    while (P < static_cast<uint32_t>(nt)) P <<= 1;
+    if (P > 16) P = kWave;
+    const uint32_t ng = __builtin_amdgcn_readfirstlane(kWave / P), tl = ln % P, grp = ln / P;
+    const int32_t i = t0 + static_cast<int32_t>(tl);
+    const bool live = static_cast<int32_t>(tl) < nt;
     const double xi = live ? px[i] : 0.0, yi = live ? py[i] : 0.0, zi = live ? pz[i] : 0.0;
     double acc = 0.0;
     for (uint64_t s = lo + wv; s < hi; s += W) {
       const uint32_t b = static_cast<uint32_t>(pairs[s]);
       const int32_t bb = cell[static_cast<size_t>(b) * kCellInts + 4], be = cell[static_cast<size_t>(b) * kCellInts + 5];
       if (t0 == ab) inter += static_cast<uint64_t>(static_cast<int64_t>(ae - ab) * (be - bb) - (a == b ? ae - ab : 0));
+      if (ng == 1) {
+        // one group: every lane reads the same source point (scalar loads)
 #pragma unroll 4
-      for (int32_t j = bb; j < be; ++j) {
-        const double dx = xi - px[j], dy = yi - py[j], dz = zi - pz[j];
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 == 0.0) {
-          if (live && j != i) ++coinc;
-        } else {
-          acc += pq[j] * rsqrt_nr(r2);
+        for (int32_t j = bb; j < be; ++j) {
+          const double dx = xi - px[j], dy = yi - py[j], dz = zi - pz[j];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0) {
+            if (live && j != i) ++coinc;
+          } else {
+            acc += pq[j] * rsqrt_nr(r2);
+          }
+        }
+      } else {
+        for (int32_t j = bb + static_cast<int32_t>(grp); j < be; j += static_cast<int32_t>(ng)) {
+          const double dx = xi - px[j], dy = yi - py[j], dz = zi - pz[j];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0) {
+            if (live && j != i) ++coinc;
+          } else {
+            acc += pq[j] * rsqrt_nr(r2);
+          }
         }
       }
     }
+    for (uint32_t d = P; d < kWave; d <<= 1) acc += __shfl_xor(acc, static_cast<int>(d), 64);
     red[wv][ln] = acc;
     __syncthreads();
-    if (wv == 0 && live) {
+    if (wv == 0 && live && grp == 0) {
       double sum = 0.0;
 #pragma unroll
       for (uint32_t g = 0; g < W; ++g) sum += red[g][ln];
