@@ -581,14 +581,15 @@ bool dev_alloc(T **p, size_t count) {
 unsigned nblk(int64_t n, unsigned b) { return static_cast<unsigned>(std::max<int64_t>((n + b - 1) / b, 1)); }
 
 // Interaction-list capacities: the caller's, else an estimate from the number
-// of cells and theta (about 200 M2L and 30 P2P pairs per cell at theta = 1,
-// growing as theta^-3; every leaf pair when theta = 0).
+// of cells and theta (100 M2L and 30 P2P pairs per cell at theta = 1, growing
+// as theta^-3: above what uniform points need, below clustered ones, whose
+// lists then grow once; every leaf pair when theta = 0).
 void fmm_list_caps(const gtap_fmm_args &a, int32_t ncells, uint64_t &m2l, uint64_t &p2p) {
   const double nc = static_cast<double>(ncells);
   double em = 0.0, ep = nc * nc;
   if (a.theta_num > 0) {
     const double s = static_cast<double>(a.theta_den) / a.theta_num;
-    em = nc * 200.0 * s * s * s;
+    em = nc * 100.0 * s * s * s;
     ep = nc * 30.0 * s * s * s;
   }
   em = std::min(std::max(em, 65536.0), 4.0e9);
@@ -759,7 +760,7 @@ int fmm_worklist(gtap_ctx *c, FmmJobMem &m) {
   for (hipEvent_t &e : m.lev)
     if (!e && hipEventCreate(&e) != hipSuccess) return GTAP_E_HIP;
   if (!m.front) {
-    // a frontier holds the pairs of one level: at most half of all pairs
+    // a frontier holds the pairs of one level (grown and re-run if not)
     m.front_cap = std::max<uint64_t>(1u << 20, (m.m2l_cap + m.p2p_cap) / 2);
     if (!dev_alloc(&m.front, 2 * m.front_cap + 1)) return GTAP_E_NOMEM;
   }
