@@ -175,3 +175,38 @@ def test_fmm_lists_plummer_1m_sampled(gtap):
     check_phi(got[tg], fmm_oracle)
     err = got[tg] - direct
     assert np.linalg.norm(err) / np.linalg.norm(direct) < 1e-4
+
+
+def test_fmm_lists_several_jobs_in_one_launch(gtap):
+    """Three list-building FMM jobs (two task traversals, whose wavefronts
+    switch chunk owners between descriptors, and one worklist), a Cilksort job
+    and fib jobs share one launch; each FMM job's lists and potentials match
+    its own oracle run."""
+    import torch
+    rt = gtap.Runtime(mode=gtap.GTAP_MODE_THREAD, waves_per_group=4, small_frames=1 << 24, big_frames=1 << 10,
+                      timeout_ms=60000)
+    try:
+        jobs = []
+        for seed, n, tr in ((21, 8000, gtap.GTAP_FMM_LISTS), (22, 12000, gtap.GTAP_FMM_LISTS),
+                            (23, 5000, gtap.GTAP_FMM_WORKLIST)):
+            x, y, z, q = points.plummer(n, seed)
+            ts = [torch.as_tensor(np.asarray(a, dtype=np.float64)).cuda() for a in (x, y, z, q)]
+            phi = torch.zeros_like(ts[0])
+            jid = rt.submit_fmm(*ts, phi, traversal=tr)
+            jobs.append((jid, (x, y, z, q), ts, phi))
+        keys = np.random.default_rng(2).integers(0, 2**32, size=30000, dtype=np.uint32)
+        kt = torch.from_numpy(keys.view(np.int32)).cuda()
+        js = rt.submit_cilksort(kt)
+        fibs = [(rt.submit_fib(n), oracle.fib(n).value) for n in (12, 21)]
+        say("three FMM jobs, a Cilksort job and fib jobs in one launch")
+        rt.run()
+        for jid, (x, y, z, q), _, phi in jobs:
+            res = rt.fmm_result(jid)
+            want = oracle.fmm(x, y, z, q)
+            check_lists(res, want)
+            check_phi(phi.cpu().numpy(), want.phi)
+        assert np.array_equal(kt.cpu().numpy().view(np.uint32), np.sort(keys)) and rt.result(js) == keys.size
+        for j, v in fibs:
+            assert rt.result(j) == v
+    finally:
+        rt.close()
