@@ -65,6 +65,9 @@ def _load():
     lib.orc_cilksort.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                  ctypes.c_int64, P(_Counts)]
     lib.orc_cilksort.restype = ctypes.c_int64
+    lib.orc_kclique_split.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                      ctypes.c_int64, ctypes.c_int, ctypes.c_int, P(_Counts)]
+    lib.orc_kclique_split.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -231,6 +234,27 @@ def direct(x, y, z, q, targets) -> np.ndarray:
     _fmm_lib().orc_direct(x.size, x.ctypes.data, y.ctypes.data, z.ctypes.data, q.ctypes.data, tg.ctypes.data,
                           tg.size, phi.ctypes.data)
     return phi[: tg.size]
+
+
+KCLIQUE_ALGORITHMS = {"orient": 0, "pivot": 1}
+
+
+def kclique_split(row_ptr, col, k: int, range_leaf: int = 64, threshold: int = 32,
+                  algorithm: str = "orient") -> OracleResult:
+    """k-clique count with cost-threshold task splitting (Sec. 6.4.2), by the
+    orientation or the pivoting algorithm.  The task tree -- vertex ranges,
+    vertices, edges, and the child tasks of every node whose candidate set is
+    larger than ``threshold`` -- is written out in ``oracle/kclique_split.c``;
+    counts.aux is the number of nodes that split."""
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    cl = np.ascontiguousarray(np.asarray(col, dtype=np.int32))
+    n = rp.shape[0] - 1
+    c = _Counts()
+    v = _load().orc_kclique_split(rp.ctypes.data, cl.ctypes.data if cl.size else None, n, int(k),
+                                  int(range_leaf), int(threshold), KCLIQUE_ALGORITHMS[algorithm], ctypes.byref(c))
+    if v < 0:
+        raise ValueError("oracle kclique_split: invalid arguments" if v == -1 else "oracle kclique_split: no memory")
+    return _res(v, c)
 
 
 def cilksort(keys, sort_cutoff: int = 64, merge_cutoff: int = 256):

@@ -4,7 +4,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "fmm.c"), os.path.join(HERE, "cilksort.c")]
+SRCS = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "fmm.c"), os.path.join(HERE, "cilksort.c"),
+        os.path.join(HERE, "kclique_split.c")]
 OUT = os.path.join(HERE, "liboracle.so")
 
 
