@@ -19,8 +19,11 @@
  *             mid = lo + (hi-lo)/2; otherwise one V(v) per vertex.
  *   V(v)      k = 1 -> 1; k = 2 -> |N+(v)|; N+(v) empty -> 0; otherwise one
  *             E(v, w) per w in N+(v), in list order.
- *   E(u,v)    C = C(u,v), c = |C|.  k' = 1 -> c; c < k' -> 0; otherwise the
- *             root node of the chosen algorithm on C.
+ *   E(u,v)    C = C(u,v), c = |C|.  k' = 1 -> c; c < k' -> 0; c <= t -> the
+ *             root node of the chosen algorithm on C, counted in place;
+ *             otherwise one child H(u,v).
+ *   H(u,v)    the root node of the chosen algorithm on C as a task of its own
+ *             (it holds the encoded candidate subgraph its children share).
  * Orientation (cost estimate: the candidate count):
  *   O(S, l)   counts l-cliques of the DAG induced on S (l >= 2, |S| >= l).
  *             l = 2 or |S| <= t: counted in place by
@@ -41,6 +44,7 @@
  *               P(Q_i /\ N(w_i), h+1, q) for the members w_1 < w_2 < ... of
  *               Q \ N(p) other than p, Q_i = Q minus p, w_1, ..., w_{i-1}.
  *             Done in place, the children are recursive calls instead.
+ *             (Adjacency inside C is tabulated once per edge.)
  * Every child listed is one task; a task with children suspends once
  * (conts).  aux counts the nodes that split (O or P nodes with children,
  * the edge's root node included).
@@ -62,6 +66,8 @@ typedef struct {
     int pivot;      /* 0: orientation, 1: pivoting */
     int bad;        /* allocation failure */
     ks_counts *c;
+    const char *adj;  /* pivoting: c x c adjacency of the current edge's candidates */
+    int64_t nadj;
 } ks_ctx;
 
 static int64_t ks_isect(const int32_t *a, int64_t na, const int32_t *b, int64_t nb, int32_t *out)
@@ -179,8 +185,11 @@ static int64_t ks_B(ks_ctx *x, const int32_t *S, int64_t ns, int l)
 
 /* ---- pivoting ------------------------------------------------------------- */
 
-/* One node of the clique tree.  `task` = 1 when the node is a task of its
- * own (then its children may be tasks too); in place otherwise. */
+/* One node of the clique tree.  Q holds positions in the edge's candidate
+ * list (ascending), adjacency comes from x->adj.  `task` = 1 when the node is
+ * a task of its own (then its children may be tasks too); in place otherwise. */
+static int ks_nb(const ks_ctx *x, int32_t a, int32_t b) { return x->adj[(int64_t)a * x->nadj + b]; }
+
 static int64_t ks_P(ks_ctx *x, const int32_t *Q, int64_t nq, int h, int q, int task)
 {
     const int kk = x->kk;
@@ -193,7 +202,7 @@ static int64_t ks_P(ks_ctx *x, const int32_t *Q, int64_t nq, int h, int q, int t
     for (int64_t i = 0; i < nq; i++) {
         int64_t d = 0;
         for (int64_t j = 0; j < nq; j++)
-            if (j != i && ks_adj(x, Q[i], Q[j])) d++;
+            if (j != i && ks_nb(x, Q[i], Q[j])) d++;
         if (d > best) {
             best = d;
             pbest = i;
@@ -207,13 +216,12 @@ static int64_t ks_P(ks_ctx *x, const int32_t *Q, int64_t nq, int h, int q, int t
         free(gone);
         return 0;
     }
-    memset(gone, 0, (size_t)nq);
     if (split) x->c->aux++;
     int64_t sum = 0;
     /* p as pivot */
     int64_t nt = 0;
     for (int64_t j = 0; j < nq; j++)
-        if (j != pbest && ks_adj(x, p, Q[j])) T[nt++] = Q[j];
+        if (j != pbest && ks_nb(x, p, Q[j])) T[nt++] = Q[j];
     if (split) x->c->tasks++;
     int64_t before = x->c->conts;
     sum += ks_P(x, T, nt, h, q + 1, split);
@@ -221,10 +229,10 @@ static int64_t ks_P(ks_ctx *x, const int32_t *Q, int64_t nq, int h, int q, int t
     gone[pbest] = 1;
     /* the non-neighbours of p, each held, in ascending order */
     for (int64_t i = 0; i < nq; i++) {
-        if (i == pbest || ks_adj(x, p, Q[i])) continue;
+        if (i == pbest || ks_nb(x, p, Q[i])) continue;
         nt = 0;
         for (int64_t j = 0; j < nq; j++)
-            if (!gone[j] && j != i && ks_adj(x, Q[i], Q[j])) T[nt++] = Q[j];
+            if (!gone[j] && j != i && ks_nb(x, Q[i], Q[j])) T[nt++] = Q[j];
         if (split) x->c->tasks++;
         before = x->c->conts;
         sum += ks_P(x, T, nt, h + 1, q, split);
@@ -239,6 +247,29 @@ static int64_t ks_P(ks_ctx *x, const int32_t *Q, int64_t nq, int h, int q, int t
 
 /* ---- task tree above the algorithms --------------------------------------- */
 
+/* root node of an edge's search; task = 1 when it is a task of its own.
+ * Pivoting works on candidate positions 0..c-1 with the undirected adjacency
+ * of the candidates tabulated first. */
+static int64_t ks_root(ks_ctx *x, const int32_t *C, int64_t c, int task)
+{
+    if (!x->pivot) return task ? ks_O(x, C, c, x->kk) : ks_K(x, C, c, x->kk);
+    char *adj = ks_alloc(x, (size_t)(c * c));
+    int32_t *Q = ks_alloc(x, sizeof(int32_t) * (size_t)c);
+    int64_t r = 0;
+    if (adj && Q) {
+        for (int64_t i = 0; i < c; i++) {
+            Q[i] = (int32_t)i;
+            for (int64_t j = 0; j < c; j++) adj[i * c + j] = (char)(i != j && ks_adj(x, C[i], C[j]));
+        }
+        x->adj = adj;
+        x->nadj = c;
+        r = ks_P(x, Q, c, 0, 0, task);
+    }
+    free(adj);
+    free(Q);
+    return r;
+}
+
 static int64_t ks_E(ks_ctx *x, int32_t u, int32_t v)
 {
     x->c->tasks++;
@@ -248,12 +279,20 @@ static int64_t ks_E(ks_ctx *x, int32_t u, int32_t v)
     if (!C) return 0;
     int64_t c = ks_isect(ou, nu, ov, nv, C);
     int64_t r;
-    int64_t before = x->c->conts;
     if (x->kk == 1) r = c;
     else if (c < x->kk) r = 0;
-    else if (x->pivot) r = ks_P(x, C, c, 0, 0, 1);
-    else r = ks_O(x, C, c, x->kk);
-    if (x->c->conts == before) x->c->leaves++;
+    else if (c <= x->thr) r = ks_root(x, C, c, 0);
+    else {
+        /* H(u, v) */
+        x->c->tasks++;
+        int64_t before = x->c->conts;
+        r = ks_root(x, C, c, 1);
+        if (x->c->conts == before) x->c->leaves++;
+        x->c->conts++;
+        free(C);
+        return r;
+    }
+    x->c->leaves++;
     free(C);
     return r;
 }
@@ -303,7 +342,7 @@ int64_t orc_kclique_split(const int64_t *row_ptr, const int32_t *col, int64_t n,
 {
     memset(c, 0, sizeof(*c));
     if (k < 1 || n < 0 || range_leaf < 1 || threshold < 0 || (algorithm != 0 && algorithm != 1)) return -1;
-    ks_ctx x = {row_ptr, col, k, k - 2, threshold, algorithm, 0, c};
+    ks_ctx x = {row_ptr, col, k, k - 2, threshold, algorithm, 0, c, NULL, 0};
     int64_t v = ks_R(&x, 0, n, range_leaf);
     return x.bad ? -2 : v;
 }

@@ -90,9 +90,10 @@ def _orient_tree(s, l, thr):
 @pytest.mark.parametrize("n", [9, 16, 24])
 def test_split_complete_graph_counts_and_trees(n):
     """K_n oriented by id: C(n, k) cliques; edge (i, j) has the n-1-j later
-    vertices as candidates.  Pivoting on a clique always picks the first
-    candidate and has no non-neighbours, so every edge with c >= k-2 spawns a
-    chain of c pivot tasks when the threshold is 0."""
+    vertices as candidates.  An edge with c > t candidates hands its search to
+    one child task; pivoting on a clique always picks the first candidate and
+    has no non-neighbours, so that child splits into a chain of c - t pivot
+    tasks."""
     edges = [(i, j) for i in range(n) for j in range(i + 1, n)]
     g = graphs.oriented_from_edges(n, edges, "id")
     m = len(edges)
@@ -104,16 +105,17 @@ def test_split_complete_graph_counts_and_trees(n):
             for thr in (0, 3, 1000):
                 r = oracle.kclique_split(g.row_ptr, g.col, k, threshold=thr, algorithm=alg)
                 assert r.value == math.comb(n, k)
+                # an edge with more than thr candidates hands its search to one child
+                heavy = [c for c in cs if kk >= 2 and c >= kk and c > thr]
                 if alg == "pivot":
-                    extra = sum(max(c - thr, 0) for c in cs if c >= kk) if kk >= 2 else 0
-                    splits = extra
+                    splits = sum(c - thr for c in heavy)
+                    extra = len(heavy) + splits
                 else:
-                    extra = splits = 0
-                    for c in cs:
-                        if kk >= 2 and c >= kk:
-                            t, sp = _orient_tree(c, kk, thr)
-                            extra += t
-                            splits += sp
+                    extra, splits = len(heavy), 0
+                    for c in heavy:
+                        t, sp = _orient_tree(c, kk, thr)
+                        extra += t
+                        splits += sp
                 assert r.tasks == base + extra, (k, alg, thr)
                 assert r.aux == splits, (k, alg, thr)
 
