@@ -61,7 +61,8 @@ enum gtap_kind {
     GTAP_KIND_KCLIQUE = 4,  /* gtap_kclique_args                               */
     GTAP_KIND_FMM = 5,      /* gtap_fmm_args (traversal TASKS: block mode;
                                LISTS, WORKLIST: thread mode)                  */
-    GTAP_KIND_CILKSORT = 6  /* gtap_cilksort_args (thread mode)                */
+    GTAP_KIND_CILKSORT = 6, /* gtap_cilksort_args (thread mode)                */
+    GTAP_KIND_KCLIQUE_SPLIT = 7  /* gtap_kclique_split_args (thread mode)      */
 };
 
 /* Fibonacci with a task at every call (Sec. 6.3, microbenchmarks): result is
@@ -93,6 +94,39 @@ typedef struct {
     int32_t range_leaf;
     int32_t max_outdeg;
 } gtap_kclique_args;
+
+/* k-clique count with bitset-encoded candidate subgraphs and cost-threshold
+ * task splitting (Sec. 6.4.2: the orientation and the pivoting algorithms).
+ * The vertex range splits as for GTAP_KIND_KCLIQUE; a vertex task forks one
+ * edge task per out-neighbour.  Edge (u, v) encodes the subgraph induced on
+ * its candidates N+(u) /\ N+(v) as a bit matrix in its big frame and counts
+ * the (k-2)-cliques in it.  A search node whose candidate set has more than
+ * `threshold` members splits into one child task per branch -- per candidate
+ * for the orientation algorithm; the pivot and each of its non-neighbours for
+ * pivoting -- and every child applies the same test; smaller nodes are
+ * counted in place by one lane.  Same graph contract as gtap_kclique_args
+ * (row_ptr_dev/col_dev borrowed until gtap_run returns, sorted acyclic
+ * out-lists); the library reads row_ptr once at submit and rejects a graph
+ * whose largest out-degree exceeds max_outdeg or 1024.  Needs thread mode,
+ * waves_per_group 4, flags 0, 1 <= k <= 32, 0 <= threshold <= 64 and, for
+ * k >= 4, big frames of at least gtap_kclique_split_buffer_ints(max_outdeg)
+ * ints.  The result is the number of k-cliques. */
+typedef struct {
+    const int32_t *row_ptr_dev;
+    const int32_t *col_dev;
+    int32_t n;
+    int32_t k;
+    int32_t range_leaf;
+    int32_t max_outdeg;
+    int32_t threshold;      /* split when a node has more candidates than this */
+    int32_t algorithm;      /* gtap_kclique_algorithm                          */
+} gtap_kclique_split_args;
+
+enum gtap_kclique_algorithm { GTAP_KCLIQUE_ORIENT = 0, GTAP_KCLIQUE_PIVOT = 1 };
+
+/* Big-frame buffer ints a GTAP_KIND_KCLIQUE_SPLIT job needs for out-degrees up
+ * to max_outdeg (0 if max_outdeg is negative or above 1024). */
+int32_t gtap_kclique_split_buffer_ints(int32_t max_outdeg);
 
 /* 3D Laplace FMM whose interaction phase is a dual-tree traversal run as
  * block-mode tasks (Sec. 6.4.1, "FMM Dual-Tree Traversal").  The library builds

@@ -64,6 +64,11 @@ enum TaskKind : uint32_t {
   TK_DTT = 8,       // thread mode: FMM cell pair (A, B) that only builds the interaction lists
   TK_SORT = 9,      // Cilksort: sort a range into a buffer
   TK_MERGE = 10,    // Cilksort: merge two sorted ranges
+  TK_KS_RANGE = 11,   // k-clique with splitting: vertex range
+  TK_KS_VERTEX = 12,  //   vertex: one edge task per out-neighbour
+  TK_KS_EDGE = 13,    //   edge (u, v): candidates N+(u) /\ N+(v), counted in place if few
+  TK_KS_HEAVY = 14,   //   edge with many candidates: their bit matrix, the search's root
+  TK_KS_NODE = 15,    //   branch of a node that split
 };
 
 struct alignas(128) DequeMeta {

@@ -20,6 +20,7 @@
 #include "../../include/gtap.h"
 #include "fmm.h"
 #include "fmm_lists.h"
+#include "kclique_bits.h"
 #include "layout.h"
 #include "sched_block.h"
 #include "sched_thread.h"
@@ -342,6 +343,11 @@ int gtap_init(const gtap_config *cfg, gtap_ctx **out) {
 
 }  // extern "C"
 
+extern "C" int32_t gtap_kclique_split_buffer_ints(int32_t max_outdeg) {
+  if (max_outdeg < 0 || max_outdeg > static_cast<int32_t>(kcs::kMaxW * 64)) return 0;
+  return static_cast<int32_t>(kcs::buffer_ints(static_cast<uint32_t>(max_outdeg)));
+}
+
 // Validate a root task's arguments and pack them into a job slot.
 static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, JobSlot &J) {
   if (!args) return GTAP_E_INVAL;
@@ -395,6 +401,40 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
       J.a[3] = static_cast<uint64_t>(a.k);
       J.a[4] = static_cast<uint64_t>(a.range_leaf);
       J.a[5] = static_cast<uint64_t>(a.max_outdeg);
+      return GTAP_OK;
+    }
+    case GTAP_KIND_KCLIQUE_SPLIT: {
+      if (args_bytes != sizeof(gtap_kclique_split_args)) return GTAP_E_INVAL;
+      gtap_kclique_split_args a;
+      std::memcpy(&a, args, sizeof(a));
+      if (block || c->cfg.waves_per_group != 4 || c->cfg.flags != 0) return GTAP_E_INVAL;
+      if (a.n < 0 || a.k < 1 || a.k > static_cast<int32_t>(kcs::kMaxK) || a.range_leaf < 1 ||
+          static_cast<uint32_t>(a.range_leaf) > kMaxChildren || a.max_outdeg < 0 ||
+          a.max_outdeg > static_cast<int32_t>(kcs::kMaxW * 64) || a.threshold < 0 ||
+          a.threshold > static_cast<int32_t>(kcs::kMaxThr) ||
+          (a.algorithm != GTAP_KCLIQUE_ORIENT && a.algorithm != GTAP_KCLIQUE_PIVOT))
+        return GTAP_E_INVAL;
+      if (a.n > 0 && (!a.row_ptr_dev || !a.col_dev)) return GTAP_E_INVAL;
+      if (a.k >= 4 && (c->cfg.big_frames == 0 ||
+                       kcs::buffer_ints(static_cast<uint32_t>(a.max_outdeg)) > c->cfg.big_frame_ints))
+        return GTAP_E_INVAL;
+      // the frame buffers are sized from max_outdeg: check it against the graph
+      if (a.n > 0) {
+        std::vector<int32_t> rp(static_cast<size_t>(a.n) + 1);
+        if (hipMemcpyAsync(rp.data(), a.row_ptr_dev, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+          return GTAP_E_HIP;
+        for (int32_t v = 0; v < a.n; ++v)
+          if (rp[v + 1] < rp[v] || rp[v + 1] - rp[v] > a.max_outdeg) return GTAP_E_INVAL;
+      }
+      J.a[0] = reinterpret_cast<uint64_t>(a.row_ptr_dev);
+      J.a[1] = reinterpret_cast<uint64_t>(a.col_dev);
+      J.a[2] = static_cast<uint64_t>(a.n);
+      J.a[3] = static_cast<uint64_t>(a.k);
+      J.a[4] = static_cast<uint64_t>(a.range_leaf);
+      J.a[5] = static_cast<uint64_t>(a.max_outdeg);
+      J.a[6] = static_cast<uint64_t>(a.threshold) | (static_cast<uint64_t>(a.algorithm) << 8);
       return GTAP_OK;
     }
     case GTAP_KIND_CILKSORT: {
@@ -931,7 +971,8 @@ int gtap_run(gtap_ctx *c) {
   bool any_fmm = false, any_ext = false;
   for (size_t j = 0; j < nj; ++j) {
     any_fmm |= c->pending[j].kind == GTAP_KIND_FMM;
-    any_ext |= c->pending[j].kind == GTAP_KIND_FMM || c->pending[j].kind == GTAP_KIND_CILKSORT;
+    any_ext |= c->pending[j].kind == GTAP_KIND_FMM || c->pending[j].kind == GTAP_KIND_CILKSORT ||
+               c->pending[j].kind == GTAP_KIND_KCLIQUE_SPLIT;
   }
   auto drop_pending = [&]() {
     for (FmmJobMem &m : fm) fmm_free(m);
@@ -1099,8 +1140,9 @@ int gtap_serve_start(gtap_ctx *c, uint32_t max_inflight, uint32_t headroom_small
 int gtap_serve_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, uint64_t *ticket) {
   if (!c || !ticket) return GTAP_E_INVAL;
   if (!c->serving) return GTAP_E_STATE;
-  // the serving kernel runs the scheduler as designed: no FMM, no Cilksort
-  if (kind == GTAP_KIND_FMM || kind == GTAP_KIND_CILKSORT) return GTAP_E_INVAL;
+  // the serving kernel runs the scheduler as designed: no FMM, no Cilksort,
+  // no split k-clique search
+  if (kind == GTAP_KIND_FMM || kind == GTAP_KIND_CILKSORT || kind == GTAP_KIND_KCLIQUE_SPLIT) return GTAP_E_INVAL;
   JobSlot J;
   const int rc = pack_job(c, kind, args, args_bytes, J);
   if (rc) return rc;

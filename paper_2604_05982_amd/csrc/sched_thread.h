@@ -636,6 +636,11 @@ GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
       break;
   }
   if constexpr (kExt) {
+    if (jkind == 7) {  // k-clique with splitting: the whole vertex range
+      kind = TK_KS_RANGE;
+      c.p[0] = 0;
+      c.p[1] = static_cast<uint32_t>(job_arg(p, j, 2));
+    }
     if (jkind == 6) {  // Cilksort: sort the whole array into the key buffer
       kind = TK_SORT;
       c.p[0] = 0;

@@ -17,6 +17,7 @@
 // parent always completes after all of its children.
 #pragma once
 #include "fmm_lists.h"
+#include "kclique_bits.h"
 #include "layout.h"
 #include "wave.h"
 
@@ -184,6 +185,249 @@ GTAP_DEV uint32_t count_below(const uint32_t *s, uint32_t n, uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------
+// k-clique counting with bitset candidate subgraphs and cost-threshold
+// splitting (Sec. 6.4.2); the encoding is described in kclique_bits.h.  Job
+// arguments: 0 row_ptr, 1 col, 2 n, 3 k, 4 range_leaf, 5 max out-degree,
+// 6 threshold | algorithm << 8 (0 orientation, 1 pivoting).
+struct KsJob {
+  const int32_t *rp;
+  const int32_t *col;
+  uint32_t kk;     // k - 2: clique size inside an edge's candidate set
+  uint32_t thr;
+  bool pivot;
+};
+GTAP_DEV KsJob ks_job(const Params &p, uint32_t job) {
+  const uint64_t a6 = job_arg(p, job, 6);
+  return KsJob{reinterpret_cast<const int32_t *>(job_arg(p, job, 0)),
+               reinterpret_cast<const int32_t *>(job_arg(p, job, 1)),
+               static_cast<uint32_t>(job_arg(p, job, 3)) - 2, static_cast<uint32_t>(a6 & 0xFFu),
+               ((a6 >> 8) & 1u) != 0};
+}
+
+// Store a node's state at buf (device-coherent: its children read it).
+GTAP_DEV void ks_store_node(uint32_t *buf, uint64_t meta, const uint64_t *P, const uint64_t *R, uint32_t W,
+                            bool with_r) {
+  uint64_t *b = reinterpret_cast<uint64_t *>(buf);
+  co_st64(b, meta);
+  for (uint32_t w = 0; w < W; ++w) co_st64(b + 1 + w, P[w]);
+  if (with_r)
+    for (uint32_t w = 0; w < W; ++w) co_st64(b + 1 + W + w, R[w]);
+}
+
+// Pivot of a split pivoting node: the member of P with the most neighbours in
+// P, the lowest on ties; R receives its non-neighbours other than itself.
+GTAP_DEV uint32_t ks_pivot(const uint64_t *rows, uint32_t W, const uint64_t *P, uint64_t *R) {
+  uint32_t best = 0;
+  int32_t bd = -1;
+  for (uint32_t w = 0; w < W; ++w) {
+    for (uint64_t t = P[w]; t; t &= t - 1) {
+      const uint32_t x = w * 64 + __builtin_ctzll(t);
+      int32_t d = 0;
+      for (uint32_t v = 0; v < W; ++v) d += __popcll(P[v] & co_ld64(rows + static_cast<size_t>(x) * W + v));
+      if (d > bd) {
+        bd = d;
+        best = x;
+      }
+    }
+  }
+  for (uint32_t v = 0; v < W; ++v) R[v] = P[v] & ~co_ld64(rows + static_cast<size_t>(best) * W + v);
+  R[best >> 6] &= ~(1ull << (best & 63));
+  return best;
+}
+
+// Edge task (u, the j-th out-neighbour v of u).  Few candidates: the whole
+// search in place, from a private candidate list (no frame needed); more than
+// the threshold: one child task takes the search over in a big frame.
+GTAP_DEV void ks_edge(const Params &p, Outcome &o, uint32_t u, uint32_t j) {
+  const KsJob J = ks_job(p, o.job);
+  const int32_t s0 = J.rp[u];
+  const uint32_t du = static_cast<uint32_t>(J.rp[u + 1] - s0);
+  const int32_t v = J.col[s0 + j];
+  const int32_t s1 = J.rp[v];
+  const uint32_t dv = static_cast<uint32_t>(J.rp[v + 1] - s1);
+  int32_t C[kcs::kMaxThr];
+  const uint32_t c = kcs::isect(J.col + s0, du, J.col + s1, dv, C, J.kk == 1 ? 0u : J.thr);
+  if (J.kk == 1) {
+    o.value = c;
+    return;
+  }
+  if (c < J.kk) return;
+  if (c > J.thr) {
+    o.type = OUT_FORK;
+    o.nchild = 1;
+    o.ckind = TK_KS_HEAVY;
+    o.big = 1;
+    o.d[0] = u;
+    o.d[1] = j;
+    return;
+  }
+  uint64_t A[kcs::kMaxThr];
+  for (uint32_t i = 0; i < c; ++i) {
+    const int32_t x = C[i];
+    A[i] = kcs::row_word(J.col + J.rp[x], static_cast<uint32_t>(J.rp[x + 1] - J.rp[x]), C, c);
+  }
+  if (J.pivot) {  // undirected closure, in place
+    for (uint32_t i = 0; i < c; ++i)
+      for (uint64_t t = A[i]; t; t &= t - 1) A[__builtin_ctzll(t)] |= 1ull << i;
+  }
+  const uint64_t all = kcs::low_mask(c);
+  o.value = J.pivot ? kcs::sct_count(A, all, 0, 0, J.kk) : kcs::dag_count(A, all, J.kk);
+}
+
+// Root node of a heavy edge's search, in a big frame: the candidate list and
+// the bit matrix go to the buffer, then one task per branch (the orientation
+// algorithm counts in place when only pairs remain: k = 4).
+GTAP_DEV void ks_heavy(const Params &p, uint32_t tid, uint32_t *f, Outcome &o, uint32_t u, uint32_t j) {
+  const KsJob J = ks_job(p, o.job);
+  const int32_t s0 = J.rp[u];
+  const uint32_t du = static_cast<uint32_t>(J.rp[u + 1] - s0);
+  const int32_t v = J.col[s0 + j];
+  const int32_t s1 = J.rp[v];
+  const uint32_t dv = static_cast<uint32_t>(J.rp[v + 1] - s1);
+  uint32_t *buf = f + FW_BUF;
+  int32_t *C = reinterpret_cast<int32_t *>(buf + kcs::EB_LIST);
+  const uint32_t c = kcs::isect(J.col + s0, du, J.col + s1, dv, C, 0xFFFFFFFFu);
+  if (!J.pivot && J.kk == 2) {  // directed edges inside C
+    int64_t e = 0;
+    for (uint32_t i = 0; i < c; ++i) {
+      const int32_t x = C[i];
+      e += kcs::isect(J.col + J.rp[x], static_cast<uint32_t>(J.rp[x + 1] - J.rp[x]), C, c, nullptr, 0);
+    }
+    o.value = e;
+    return;
+  }
+  // heavy: the whole matrix in the frame, then one task per branch
+  const uint32_t W = (c + 63) / 64;
+  const uint32_t rows_off = kcs::EB_LIST + ((c + 1) & ~1u);
+  const uint32_t ns = rows_off + 2 * c * W;
+  uint64_t *rows = reinterpret_cast<uint64_t *>(buf + rows_off);
+  for (uint32_t i = 0; i < c; ++i) {
+    const int32_t x = C[i];
+    kcs::build_row(J.col + J.rp[x], static_cast<uint32_t>(J.rp[x + 1] - J.rp[x]), C, c,
+                   rows + static_cast<size_t>(i) * W, W);
+  }
+  if (J.pivot) {  // undirected closure, in place
+    for (uint32_t i = 0; i < c; ++i)
+      for (uint32_t w = 0; w < W; ++w)
+        for (uint64_t t = rows[static_cast<size_t>(i) * W + w]; t; t &= t - 1) {
+          const uint32_t y = w * 64 + __builtin_ctzll(t);
+          rows[static_cast<size_t>(y) * W + (i >> 6)] |= 1ull << (i & 63);
+        }
+  }
+  for (uint32_t x = 0; x < c * W; ++x) co_st64(rows + x, rows[x]);
+  co_st32(buf + kcs::EB_C, c);
+  co_st32(buf + kcs::EB_W, W);
+  co_st32(buf + kcs::EB_ROWS, rows_off);
+  co_st32(buf + kcs::EB_NS, ns);
+  uint64_t P[kcs::kMaxW], R[kcs::kMaxW];
+  for (uint32_t w = 0; w < W; ++w) P[w] = kcs::low_mask(c > w * 64 ? c - w * 64 : 0);
+  uint64_t meta = J.kk;
+  uint32_t nchild = c;
+  if (J.pivot) {
+    const uint32_t piv = ks_pivot(rows, W, P, R);
+    meta = static_cast<uint64_t>(piv) << 32;  // no held vertices, no pivots yet
+    nchild = 1;
+    for (uint32_t w = 0; w < W; ++w) nchild += __popcll(R[w]);
+  }
+  ks_store_node(buf + ns, meta, P, R, W, J.pivot);
+  o.type = OUT_FORK;
+  o.nchild = nchild;
+  o.ckind = TK_KS_NODE;
+  o.big = (J.pivot || J.kk - 1 >= 3) ? 1u : 0u;  // children that may split keep state in a big frame
+  o.d[0] = tid;
+  o.d[1] = ns;
+}
+
+// Branch j of a node that split: E is the edge task's frame, ns the node
+// state's offset in the parent's buffer.
+GTAP_DEV void ks_node(const Params &p, uint32_t tid, uint32_t *f, Outcome &o, uint32_t E, uint32_t j, uint32_t ns) {
+  const KsJob J = ks_job(p, o.job);
+  const uint32_t *eb = frame_ptr(p, E) + FW_BUF;
+  const uint32_t W = co_ld32(eb + kcs::EB_W);
+  const uint64_t *rows = reinterpret_cast<const uint64_t *>(eb + co_ld32(eb + kcs::EB_ROWS));
+  const uint64_t *pb = reinterpret_cast<const uint64_t *>(frame_ptr(p, o.parent) + FW_BUF + ns);
+  const uint64_t meta = co_ld64(pb);
+  uint64_t P[kcs::kMaxW], S[kcs::kMaxW], R[kcs::kMaxW];
+  for (uint32_t w = 0; w < W; ++w) P[w] = co_ld64(pb + 1 + w);
+  uint32_t m = 0;
+  uint64_t A[kcs::kMaxThr];
+  if (!J.pivot) {
+    const uint32_t l = static_cast<uint32_t>(meta & 0xFFFFu) - 1;
+    const uint32_t x = kcs::select_bit(P, W, j);
+    for (uint32_t w = 0; w < W; ++w) {
+      S[w] = P[w] & co_ld64(rows + static_cast<size_t>(x) * W + w);
+      m += __popcll(S[w]);
+    }
+    if (l == 1) {
+      o.value = m;
+      return;
+    }
+    if (m < l) return;
+    if (l == 2) {  // directed edges inside S
+      int64_t e = 0;
+      for (uint32_t w = 0; w < W; ++w)
+        for (uint64_t t = S[w]; t; t &= t - 1) {
+          const uint32_t y = w * 64 + __builtin_ctzll(t);
+          for (uint32_t v = 0; v < W; ++v) e += __popcll(S[v] & co_ld64(rows + static_cast<size_t>(y) * W + v));
+        }
+      o.value = e;
+      return;
+    }
+    if (m <= J.thr) {
+      kcs::compact(rows, W, S, A);
+      o.value = kcs::dag_count(A, kcs::low_mask(m), l);
+      return;
+    }
+    ks_store_node(f + FW_BUF, l, S, S, W, false);
+    o.type = OUT_FORK;
+    o.nchild = m;
+    o.big = l - 1 >= 3 ? 1u : 0u;  // level <= 2 is always counted in place
+  } else {
+    uint32_t h = static_cast<uint32_t>(meta & 0xFFFFu), q = static_cast<uint32_t>((meta >> 16) & 0xFFFFu);
+    const uint32_t piv = static_cast<uint32_t>(meta >> 32);
+    if (j == 0) {  // the pivot branch
+      for (uint32_t w = 0; w < W; ++w) S[w] = P[w] & co_ld64(rows + static_cast<size_t>(piv) * W + w);
+      q += 1;
+    } else {  // the (j-1)-th non-neighbour of the pivot, held
+      for (uint32_t w = 0; w < W; ++w) R[w] = co_ld64(pb + 1 + W + w);
+      const uint32_t x = kcs::select_bit(R, W, j - 1);
+      for (uint32_t w = 0; w < W; ++w) {
+        const uint64_t before = w < (x >> 6) ? R[w] : w == (x >> 6) ? (R[w] & kcs::low_mask(x & 63)) : 0ull;
+        S[w] = P[w] & ~before & co_ld64(rows + static_cast<size_t>(x) * W + w);
+      }
+      S[piv >> 6] &= ~(1ull << (piv & 63));
+      h += 1;
+    }
+    for (uint32_t w = 0; w < W; ++w) m += __popcll(S[w]);
+    if (h == J.kk) {
+      o.value = 1;
+      return;
+    }
+    if (m == 0) {
+      o.value = kcs::binom(q, J.kk - h);
+      return;
+    }
+    if (m + q < J.kk - h) return;
+    if (m <= J.thr) {
+      kcs::compact(rows, W, S, A);
+      o.value = kcs::sct_count(A, kcs::low_mask(m), h, q, J.kk);
+      return;
+    }
+    const uint32_t np = ks_pivot(rows, W, S, R);
+    ks_store_node(f + FW_BUF, h | (static_cast<uint64_t>(q) << 16) | (static_cast<uint64_t>(np) << 32), S, R, W,
+                  true);
+    uint32_t nchild = 1;
+    for (uint32_t w = 0; w < W; ++w) nchild += __popcll(R[w]);
+    o.type = OUT_FORK;
+    o.nchild = nchild;
+    o.big = 1;
+  }
+  o.ckind = TK_KS_NODE;
+  o.d[0] = E;
+  o.d[1] = 0;
+}
+
+// ---------------------------------------------------------------------------
 // Execute one task on this lane.  tid is its frame, or kNone for a task
 // without one (then it runs at resume point 0 and needs no buffer).  kExt
 // adds the list-building FMM cell-pair task (instantiated separately, so the
@@ -306,6 +550,43 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
       o.nchild = 2;
       o.ckind = TK_MERGE;
       o.d[0] = a0; o.d[1] = na; o.d[2] = b0; o.d[3] = nb; o.d[4] = d0 | (dst << 31); o.d[5] = 1;
+      return;
+    }
+    if (kind == TK_KS_RANGE) {  // vertex range: halves, then one vertex task per vertex
+      const uint32_t lo = p0, hi = p1;
+      const uint32_t leaf = static_cast<uint32_t>(job_arg(p, o.job, 4));
+      if (hi <= lo) return;
+      o.type = OUT_FORK;
+      o.d[0] = lo; o.d[1] = hi;
+      o.nchild = hi - lo > leaf ? 2 : hi - lo;
+      o.ckind = hi - lo > leaf ? TK_KS_RANGE : TK_KS_VERTEX;
+      return;
+    }
+    if (kind == TK_KS_VERTEX) {  // one edge task per out-neighbour
+      const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 0));
+      const uint32_t k = static_cast<uint32_t>(job_arg(p, o.job, 3));
+      const uint32_t deg = static_cast<uint32_t>(rp[p0 + 1] - rp[p0]);
+      if (k <= 2) {
+        o.value = k == 1 ? 1 : deg;
+        return;
+      }
+      if (deg == 0) return;
+      o.type = OUT_FORK;
+      o.nchild = deg;
+      o.ckind = TK_KS_EDGE;
+      o.d[0] = p0;
+      return;
+    }
+    if (kind == TK_KS_EDGE) {
+      ks_edge(p, o, p0, p1);
+      return;
+    }
+    if (kind == TK_KS_HEAVY) {
+      ks_heavy(p, tid, f, o, p0, p1);
+      return;
+    }
+    if (kind == TK_KS_NODE) {
+      ks_node(p, tid, f, o, p0, p1, p2);
       return;
     }
     if (kind == TK_DTT) {
@@ -528,6 +809,32 @@ GTAP_DEV void make_child(uint32_t ckind, const uint32_t *d, uint32_t j, ChildIni
     if (ckind == TK_MERGE) {  // d[5] = 0: the merge of a sort; 1: side j of a split
       c.p[0] = d[0]; c.p[1] = d[1]; c.p[2] = d[2]; c.p[3] = d[3];
       c.p[4] = d[5] ? (d[4] | (1u << 29) | (j << 30)) : d[4];
+      return;
+    }
+    if (ckind == TK_KS_RANGE) {
+      const uint32_t lo = d[0], hi = d[1], mid = lo + (hi - lo) / 2;
+      c.p[0] = j == 0 ? lo : mid;
+      c.p[1] = j == 0 ? mid : hi;
+      return;
+    }
+    if (ckind == TK_KS_VERTEX) {
+      c.p[0] = d[0] + j;
+      return;
+    }
+    if (ckind == TK_KS_EDGE) {  // (u, index of the out-neighbour)
+      c.p[0] = d[0];
+      c.p[1] = j;
+      return;
+    }
+    if (ckind == TK_KS_HEAVY) {  // the only child: the forking edge's own (u, index)
+      c.p[0] = d[0];
+      c.p[1] = d[1];
+      return;
+    }
+    if (ckind == TK_KS_NODE) {  // (edge frame, branch, parent's node-state offset)
+      c.p[0] = d[0];
+      c.p[1] = j;
+      c.p[2] = d[1];
       return;
     }
     if (ckind == TK_DTT) {  // pair (child j of the split cell, the other cell)

@@ -40,6 +40,10 @@ GTAP_KIND_UTS = 3
 GTAP_KIND_KCLIQUE = 4
 GTAP_KIND_FMM = 5
 GTAP_KIND_CILKSORT = 6
+GTAP_KIND_KCLIQUE_SPLIT = 7
+
+GTAP_KCLIQUE_ORIENT = 0
+GTAP_KCLIQUE_PIVOT = 1
 
 GTAP_FMM_TASKS = 0
 GTAP_FMM_LISTS = 1
@@ -97,6 +101,13 @@ class gtap_kclique_args(ctypes.Structure):
     _fields_ = [("row_ptr_dev", ctypes.c_void_p), ("col_dev", ctypes.c_void_p),
                 ("n", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("range_leaf", ctypes.c_int32), ("max_outdeg", ctypes.c_int32)]
+
+
+class gtap_kclique_split_args(ctypes.Structure):
+    _fields_ = [("row_ptr_dev", ctypes.c_void_p), ("col_dev", ctypes.c_void_p),
+                ("n", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("range_leaf", ctypes.c_int32), ("max_outdeg", ctypes.c_int32),
+                ("threshold", ctypes.c_int32), ("algorithm", ctypes.c_int32)]
 
 
 class gtap_fmm_args(ctypes.Structure):
@@ -188,6 +199,8 @@ def _load() -> ctypes.CDLL:
     lib.gtap_init.argtypes = [P(gtap_config), P(vp)]
     lib.gtap_submit.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_size_t, P(ctypes.c_uint64)]
     lib.gtap_run.argtypes = [vp]
+    lib.gtap_kclique_split_buffer_ints.argtypes = [ctypes.c_int32]
+    lib.gtap_kclique_split_buffer_ints.restype = ctypes.c_int32
     lib.gtap_result.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t]
     lib.gtap_finalize.argtypes = [vp]
     lib.gtap_stats_get.argtypes = [vp, P(gtap_stats)]
@@ -217,7 +230,8 @@ _lib = _load()
 EXPORTED = ("gtap_config_default", "gtap_workspace_size", "gtap_init", "gtap_submit", "gtap_run",
             "gtap_result", "gtap_finalize", "gtap_stats_get", "gtap_last_error",
             "gtap_status_string", "gtap_serve_start", "gtap_serve_submit", "gtap_serve_poll",
-            "gtap_serve_stop", "gtap_trace_run", "gtap_trace_run_plain", "gtap_autotune")
+            "gtap_serve_stop", "gtap_trace_run", "gtap_trace_run_plain", "gtap_autotune",
+            "gtap_kclique_split_buffer_ints")
 
 
 class GtapError(RuntimeError):
@@ -232,6 +246,11 @@ class GtapError(RuntimeError):
 
 def gtap_status_string(code: int) -> str:
     return _lib.gtap_status_string(int(code)).decode()
+
+
+def kclique_split_buffer_ints(max_outdeg: int) -> int:
+    """Big-frame buffer ints a split k-clique job needs (0 = out of range)."""
+    return int(_lib.gtap_kclique_split_buffer_ints(int(max_outdeg)))
 
 
 def gtap_config_default() -> gtap_config:
@@ -433,6 +452,28 @@ class Runtime:
         return gtap_submit(self.ctx, GTAP_KIND_KCLIQUE,
                            gtap_kclique_args(rp.data_ptr(), cl.data_ptr(), n, int(k),
                                              int(range_leaf), int(max_outdeg)))
+
+    def submit_kclique_split(self, row_ptr, col, k: int, threshold: int = 16,
+                             algorithm: int = GTAP_KCLIQUE_ORIENT, range_leaf: int = 64,
+                             max_outdeg: Optional[int] = None) -> int:
+        """k-clique job with bitset candidate subgraphs and cost-threshold
+        splitting (orientation or pivoting); needs a thread-mode runtime with
+        waves_per_group 4 and, for k >= 4, big frames of at least
+        kclique_split_buffer_ints(max_outdeg) ints."""
+        torch = self._torch
+        rp = row_ptr if isinstance(row_ptr, torch.Tensor) else torch.as_tensor(row_ptr)
+        cl = col if isinstance(col, torch.Tensor) else torch.as_tensor(col)
+        rp = rp.to(device="cuda", dtype=torch.int32).contiguous()
+        cl = cl.to(device="cuda", dtype=torch.int32).contiguous()
+        if cl.numel() == 0:
+            cl = torch.zeros(1, dtype=torch.int32, device="cuda")
+        n = rp.numel() - 1
+        if max_outdeg is None:
+            max_outdeg = int((rp[1:] - rp[:-1]).max().item()) if n > 0 else 0
+        self._keep.append((rp, cl))
+        return gtap_submit(self.ctx, GTAP_KIND_KCLIQUE_SPLIT,
+                           gtap_kclique_split_args(rp.data_ptr(), cl.data_ptr(), n, int(k), int(range_leaf),
+                                                   int(max_outdeg), int(threshold), int(algorithm)))
 
     def submit_fmm(self, x, y, z, q, phi, leaf_max: int = 64, theta=(1, 2), order: int = 6,
                    traversal: int = GTAP_FMM_TASKS, m2l_capacity: int = 0, p2p_capacity: int = 0) -> int:

@@ -38,7 +38,8 @@ def test_struct_layout_matches_header(tmp_path):
     import subprocess
     from paper_2604_05982_amd import gtap
     structs = [gtap.gtap_config, gtap.gtap_fib_args, gtap.gtap_nqueens_args, gtap.gtap_uts_args,
-               gtap.gtap_kclique_args, gtap.gtap_fmm_args, gtap.gtap_fmm_result, gtap.gtap_cilksort_args, gtap.gtap_stats,
+               gtap.gtap_kclique_args, gtap.gtap_kclique_split_args, gtap.gtap_fmm_args, gtap.gtap_fmm_result,
+               gtap.gtap_cilksort_args, gtap.gtap_stats,
                gtap.gtap_error_report, gtap.gtap_trace_job, gtap.gtap_trace_result, gtap.gtap_tune_space,
                gtap.gtap_tune_report]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gtap.h"', "int main(void){"]
@@ -80,3 +81,13 @@ def test_enum_values_match_header(tmp_path):
     assert not missing, missing
     for n in names:
         assert getattr(gtap, n) == int(got[n]), n
+
+
+def test_kclique_split_buffer_size_without_device():
+    """Buffer ints of a split k-clique job: list, bit matrix and node state
+    for out-degree D (W = ceil(D/64) words per row); 0 outside [0, 1024]."""
+    from paper_2604_05982_amd import gtap
+    for d in (0, 1, 40, 64, 65, 313, 1024):
+        w = max((d + 63) // 64, 1)
+        assert gtap.kclique_split_buffer_ints(d) == max(4 + ((d + 1) & ~1) + 2 * d * w + 2 + 4 * w, 2 + 4 * w)
+    assert gtap.kclique_split_buffer_ints(-1) == 0 and gtap.kclique_split_buffer_ints(1025) == 0
