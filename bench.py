@@ -128,20 +128,32 @@ def bench_kclique7(args, gtap) -> int:
     opts = dict(num_waves=args.num_waves, waves_per_group=args.waves_per_group, deque_capacity=1 << 17,
                 small_frames=1 << 25, big_frames=1 << 23, big_frame_ints=max(320, g.max_outdeg),
                 timeout_ms=60000, steal_below=args.steal_below)
+    split = args.kclique_split != "none"
+    if split:  # bit-matrix frames for heavy edges and the nodes that split
+        opts.update(waves_per_group=4, big_frames=1 << 20,
+                    big_frame_ints=gtap.kclique_split_buffer_ints(g.max_outdeg))
     if args.queues > 1:
         opts.update(num_queues=args.queues, daq_policy=2, daq_bounds=[8, 32, 128][: args.queues - 1],
                     deque_capacity=1 << 19, big_frames=1 << 24)
     rt = gtap.Runtime(**opts)
     rp = torch.as_tensor(g.row_ptr32).cuda()
     col = torch.as_tensor(g.col).cuda()
+    alg = gtap.GTAP_KCLIQUE_PIVOT if args.kclique_split == "pivot" else gtap.GTAP_KCLIQUE_ORIENT
+
+    def submit():
+        if split:
+            return rt.submit_kclique_split(rp, col, 7, threshold=args.split_threshold, algorithm=alg,
+                                           max_outdeg=g.max_outdeg)
+        return rt.submit_kclique(rp, col, 7, max_outdeg=g.max_outdeg)
+
     for _ in range(args.warmup):
-        j = rt.submit_kclique(rp, col, 7, max_outdeg=g.max_outdeg)
+        j = submit()
         rt.run()
     torch.cuda.synchronize()
     tot, kms = {}, []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        j = rt.submit_kclique(rp, col, 7, max_outdeg=g.max_outdeg)
+        j = submit()
         rt.run()
         st = rt.stats()
         kms.append(st["kernel_ms"])
@@ -155,6 +167,8 @@ def bench_kclique7(args, gtap) -> int:
     out = {"metric": METRIC, "value": count * args.steps / el, "unit": "k-cliques/s",
            "tasks_per_s": tot["tasks"] / el, "kernel_ms": sum(kms) / len(kms), "count": count,
            "matches_oracle": ok, "queues": args.queues, "waves": st["num_waves"],
+           "search": ({"algorithm": args.kclique_split, "split_threshold": args.split_threshold}
+                      if split else {"algorithm": "orientation, one task per candidate"}),
            "steps": args.steps, "warmup": args.warmup, "dtype": "int64", "data": "synthetic",
            "config": {"workload": "7-cliques, Chung-Lu n=1e6, mean degree 40, exponent 2.1, cap 0.6, seed 2",
                       "graph_edges": g.m_undirected, "max_outdeg": g.max_outdeg},
@@ -631,6 +645,10 @@ def main() -> int:
     ap.add_argument("--calib-jobs", type=int, default=400, help="serving: autotuner calibration jobs")
     ap.add_argument("--sweep", action="store_true", help="serving: also rho 0.3/0.5/0.7/0.9")
     ap.add_argument("--queues", type=int, default=1, help="kclique7: DAQ queues (1 = off)")
+    ap.add_argument("--kclique-split", default="none", choices=("none", "orient", "pivot"),
+                    help="kclique7: bitset candidate subgraphs with cost-threshold splitting")
+    ap.add_argument("--split-threshold", type=int, default=16,
+                    help="kclique7 with --kclique-split: split nodes with more candidates than this")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
