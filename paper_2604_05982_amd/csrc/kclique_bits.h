@@ -103,11 +103,46 @@ GTAP_DEV int64_t binom(uint32_t n, uint32_t r) {
   return static_cast<int64_t>(v);
 }
 
+// First index in the ascending b[lo, nb) whose element is >= x: a galloping
+// search from lo (doubling steps, then bisection), cheap when the answer is
+// near lo.
+GTAP_DEV uint32_t gallop(const int32_t *b, uint32_t lo, uint32_t nb, int32_t x) {
+  if (lo >= nb || b[lo] >= x) return lo;
+  uint32_t step = 1, prev = lo;  // b[prev] < x
+  while (prev + step < nb && b[prev + step] < x) {
+    prev += step;
+    step <<= 1;
+  }
+  uint32_t l = prev + 1, h = prev + step < nb ? prev + step : nb;  // answer in [l, h]
+  while (l < h) {
+    const uint32_t mid = l + (h - l) / 2;
+    if (b[mid] < x) l = mid + 1;
+    else h = mid;
+  }
+  return l;
+}
+
 // Size of the intersection of two ascending lists (read-only graph data);
-// the first `cap` common elements go to out.
+// the first `cap` common elements go to out (ascending).  Lists of very
+// different lengths: each element of the short one is galloped to in the long
+// one; otherwise a merge.
 GTAP_DEV uint32_t isect(const int32_t *a, uint32_t na, const int32_t *b, uint32_t nb, int32_t *out, uint32_t cap) {
   uint32_t i = 0, j = 0, o = 0;
   if (na == 0 || nb == 0) return 0;
+  if (na * 4 < nb || nb * 4 < na) {
+    const int32_t *s = na < nb ? a : b, *l = na < nb ? b : a;
+    const uint32_t ns = na < nb ? na : nb, nl = na < nb ? nb : na;
+    for (; i < ns && j < nl; ++i) {
+      const int32_t x = s[i];
+      j = gallop(l, j, nl, x);
+      if (j < nl && l[j] == x) {
+        if (o < cap) out[o] = x;
+        ++o;
+        ++j;
+      }
+    }
+    return o;
+  }
   int32_t x = a[0], y = b[0];
   for (;;) {
     if (x < y) {
@@ -159,11 +194,22 @@ GTAP_DEV void build_row(const int32_t *a, uint32_t na, const int32_t *C, uint32_
   }
 }
 
-// One-word row of a light edge (c <= 64).
+// One-word row of a light edge (c <= 64): the candidates C[0, c) (private,
+// ascending) that are in the out-list a[0, na).
 GTAP_DEV uint64_t row_word(const int32_t *a, uint32_t na, const int32_t *C, uint32_t c) {
   uint32_t i = 0, j = 0;
   uint64_t acc = 0;
   if (na == 0 || c == 0) return 0;
+  if (c * 4 < na) {  // gallop to each candidate in the long out-list
+    for (; j < c && i < na; ++j) {
+      i = gallop(a, i, na, C[j]);
+      if (i < na && a[i] == C[j]) {
+        acc |= 1ull << j;
+        ++i;
+      }
+    }
+    return acc;
+  }
   int32_t x = a[0], y = C[0];
   for (;;) {
     if (x < y) {

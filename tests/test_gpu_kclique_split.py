@@ -198,3 +198,18 @@ def test_split_full_size_chung_lu_1m(gtap, alg):
         got, st = run_split(rt, g, 7, 16, alg, gtap)
         say(f"  count {got}, tasks {st['tasks']}, kernel {st['kernel_ms']:.1f} ms")
         assert got == want[1]
+
+
+@pytest.mark.parametrize("alg", ALGS)
+def test_split_with_daq_queues(gtap, alg):
+    """Divergence-aware queueing (4 classes by the out-degree bound of a
+    vertex's or an edge's candidate set): same counts and task trees."""
+    g = graphs.chung_lu(4000, 18, 2.3, 1.0, 5)
+    with make_rt(gtap, g.max_outdeg, big_frames=1 << 18, num_queues=4, daq_policy=gtap.GTAP_DAQ_KCLIQUE,
+                 daq_bounds=[8, 32, 128], deque_capacity=1 << 16) as rt:
+        for k, thr in ((4, 8), (6, 16), (7, 64)):
+            say(f"split k-clique {alg} with 4 DAQ queues, k={k} thr={thr}")
+            got, st = run_split(rt, g, k, thr, alg, gtap)
+            want = oracle.kclique_split(g.row_ptr, g.col, k, threshold=thr, algorithm=alg)
+            assert got == want.value
+            assert (st["tasks"], st["conts"]) == (want.tasks, want.conts), (k, thr)
