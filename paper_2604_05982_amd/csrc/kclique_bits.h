@@ -123,40 +123,21 @@ GTAP_DEV uint32_t gallop(const int32_t *b, uint32_t lo, uint32_t nb, int32_t x) 
 }
 
 // Size of the intersection of two ascending lists (read-only graph data);
-// the first `cap` common elements go to out (ascending).  Lists of very
-// different lengths: each element of the short one is galloped to in the long
-// one; otherwise a merge.
+// the first `cap` common elements go to out (ascending).  Each element of the
+// shorter list is galloped to in the longer one: a lane's search is a chain of
+// dependent loads, and on the skewed degrees of power-law graphs galloping
+// needs far fewer of them than a merge.
 GTAP_DEV uint32_t isect(const int32_t *a, uint32_t na, const int32_t *b, uint32_t nb, int32_t *out, uint32_t cap) {
-  uint32_t i = 0, j = 0, o = 0;
-  if (na == 0 || nb == 0) return 0;
-  if (na * 4 < nb || nb * 4 < na) {
-    const int32_t *s = na < nb ? a : b, *l = na < nb ? b : a;
-    const uint32_t ns = na < nb ? na : nb, nl = na < nb ? nb : na;
-    for (; i < ns && j < nl; ++i) {
-      const int32_t x = s[i];
-      j = gallop(l, j, nl, x);
-      if (j < nl && l[j] == x) {
-        if (o < cap) out[o] = x;
-        ++o;
-        ++j;
-      }
-    }
-    return o;
-  }
-  int32_t x = a[0], y = b[0];
-  for (;;) {
-    if (x < y) {
-      if (++i == na) break;
-      x = a[i];
-    } else if (x > y) {
-      if (++j == nb) break;
-      y = b[j];
-    } else {
+  const int32_t *s = na < nb ? a : b, *l = na < nb ? b : a;
+  const uint32_t ns = na < nb ? na : nb, nl = na < nb ? nb : na;
+  uint32_t j = 0, o = 0;
+  for (uint32_t i = 0; i < ns && j < nl; ++i) {
+    const int32_t x = s[i];
+    j = gallop(l, j, nl, x);
+    if (j < nl && l[j] == x) {
       if (o < cap) out[o] = x;
       ++o;
-      if (++i == na || ++j == nb) break;
-      x = a[i];
-      y = b[j];
+      ++j;
     }
   }
   return o;
@@ -195,34 +176,15 @@ GTAP_DEV void build_row(const int32_t *a, uint32_t na, const int32_t *C, uint32_
 }
 
 // One-word row of a light edge (c <= 64): the candidates C[0, c) (private,
-// ascending) that are in the out-list a[0, na).
+// ascending) that are in the out-list a[0, na), each galloped to.
 GTAP_DEV uint64_t row_word(const int32_t *a, uint32_t na, const int32_t *C, uint32_t c) {
-  uint32_t i = 0, j = 0;
   uint64_t acc = 0;
-  if (na == 0 || c == 0) return 0;
-  if (c * 4 < na) {  // gallop to each candidate in the long out-list
-    for (; j < c && i < na; ++j) {
-      i = gallop(a, i, na, C[j]);
-      if (i < na && a[i] == C[j]) {
-        acc |= 1ull << j;
-        ++i;
-      }
-    }
-    return acc;
-  }
-  int32_t x = a[0], y = C[0];
-  for (;;) {
-    if (x < y) {
-      if (++i == na) break;
-      x = a[i];
-    } else if (x > y) {
-      if (++j == c) break;
-      y = C[j];
-    } else {
+  uint32_t i = 0;
+  for (uint32_t j = 0; j < c && i < na; ++j) {
+    i = gallop(a, i, na, C[j]);
+    if (i < na && a[i] == C[j]) {
       acc |= 1ull << j;
-      if (++i == na || ++j == c) break;
-      x = a[i];
-      y = C[j];
+      ++i;
     }
   }
   return acc;
