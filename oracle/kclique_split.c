@@ -1,8 +1,9 @@
 /*
  * kclique_split.c -- CPU oracle of k-clique counting with cost-threshold task
  * splitting (GTaP Sec. 6.4.2, k-Clique Counting): the orientation algorithm
- * and the pivoting algorithm, with the task tree a runtime builds when a task
- * splits only if a cheap estimate of its subtree cost exceeds a threshold.
+ * and the pivoting algorithm, with the task tree a runtime builds when a node
+ * of the search becomes tasks only while its candidate set is larger than a
+ * threshold.
  *
  * TEST INFRASTRUCTURE. Only tests/, __graft_entry__.smoke() and the
  * cpu_baseline leg of bench.py may load this library.  The HIP runtime never

@@ -28,7 +28,7 @@ typedef struct {
 
 /* ---------------------------------------------------------------------------
  * Fibonacci, one task per call, no cutoff (Sec. 6.3, Fibonacci microbenchmark:
- * "disables the cutoff and spawns a task at every recursive call").
+ * in the comparison every recursive call is a task of its own).
  * fib(n) = n for n < 2, else fib(n-1) + fib(n-2).
  * ------------------------------------------------------------------------- */
 static int64_t fib_rec(int n, orc_counts *c)
