@@ -18,11 +18,15 @@
  * Task tree (k' = k - 2; t = the split threshold):
  *   R(lo,hi)  vertex range: more than `leaf` vertices -> R(lo,mid), R(mid,hi),
  *             mid = lo + (hi-lo)/2; otherwise one V(v) per vertex.
- *   V(v)      k = 1 -> 1; k = 2 -> |N+(v)|; N+(v) empty -> 0; otherwise one
- *             E(v, w) per w in N+(v), in list order.
- *   E(u,v)    C = C(u,v), c = |C|.  k' = 1 -> c; c < k' -> 0; c <= t -> the
- *             root node of the chosen algorithm on C, counted in place;
- *             otherwise one child H(u,v).
+ *   V(v)      k = 1 -> 1; k = 2 -> |N+(v)|; N+(v) empty -> 0; k = 3 -> one
+ *             E(v, w) per w in N+(v).  k >= 4: fewer than k-1 out-neighbours
+ *             -> 0; otherwise first one row task per w in N+(v) (it encodes
+ *             which members of N+(v) are out-neighbours of w: the vertex's bit
+ *             matrix), then, resumed, one E(v, w) per w, then, resumed again,
+ *             the sum.
+ *   E(u,v)    C = C(u,v), c = |C|.  k' = 1 -> c; c < k' -> 0; the orientation
+ *             algorithm with k' = 2, or c <= t -> the root node of the chosen
+ *             algorithm on C, counted in place; otherwise one child H(u,v).
  *   H(u,v)    the root node of the chosen algorithm on C as a task of its own
  *             (it holds the encoded candidate subgraph its children share).
  * Orientation (cost estimate: the candidate count):
@@ -282,7 +286,7 @@ static int64_t ks_E(ks_ctx *x, int32_t u, int32_t v)
     int64_t r;
     if (x->kk == 1) r = c;
     else if (c < x->kk) r = 0;
-    else if (c <= x->thr) r = ks_root(x, C, c, 0);
+    else if (c <= x->thr || (!x->pivot && x->kk == 2)) r = ks_root(x, C, c, 0);
     else {
         /* H(u, v) */
         x->c->tasks++;
@@ -307,9 +311,14 @@ static int64_t ks_V(ks_ctx *x, int32_t v)
         x->c->leaves++;
         return 1;
     }
-    if (x->k == 2 || nv == 0) {
+    if (x->k == 2 || nv == 0 || (x->k >= 4 && nv < x->k - 1)) {
         x->c->leaves++;
         return x->k == 2 ? nv : 0;
+    }
+    if (x->k >= 4) {  /* the row tasks, then a resumption */
+        x->c->tasks += nv;
+        x->c->leaves += nv;
+        x->c->conts++;
     }
     int64_t sum = 0;
     for (int64_t i = 0; i < nv; i++) sum += ks_E(x, v, ov[i]);

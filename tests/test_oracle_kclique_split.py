@@ -93,20 +93,27 @@ def test_split_complete_graph_counts_and_trees(n):
     vertices as candidates.  An edge with c > t candidates hands its search to
     one child task; pivoting on a clique always picks the first candidate and
     has no non-neighbours, so that child splits into a chain of c - t pivot
-    tasks."""
+    tasks.  Vertices with fewer than k-1 out-neighbours fork nothing."""
     edges = [(i, j) for i in range(n) for j in range(i + 1, n)]
     g = graphs.oriented_from_edges(n, edges, "id")
-    m = len(edges)
-    base = _range_tasks(0, n, 64) + n + m
     for k in range(3, min(n, 9) + 1):
         kk = k - 2
-        cs = [n - 1 - j for i in range(n) for j in range(i + 1, n)]
+        # vertex i has n-1-i out-neighbours; for k >= 4 only vertices with at
+        # least k-1 of them fork, first one row task, then one edge task each
+        if k == 3:
+            base = _range_tasks(0, n, 64) + n + len(edges)
+            cs = [n - 1 - j for i in range(n) for j in range(i + 1, n)]
+        else:
+            live = [i for i in range(n) if n - 1 - i >= k - 1]
+            base = _range_tasks(0, n, 64) + n + 2 * sum(n - 1 - i for i in live)
+            cs = [n - 1 - j for i in live for j in range(i + 1, n)]
         for alg in ALGS:
             for thr in (0, 3, 1000):
                 r = oracle.kclique_split(g.row_ptr, g.col, k, threshold=thr, algorithm=alg)
                 assert r.value == math.comb(n, k)
-                # an edge with more than thr candidates hands its search to one child
-                heavy = [c for c in cs if kk >= 2 and c >= kk and c > thr]
+                # an edge with more than thr candidates hands its search to one
+                # child (the orientation algorithm counts k' = 2 in place)
+                heavy = [c for c in cs if kk >= 2 and c >= kk and c > thr and (alg == "pivot" or kk >= 3)]
                 if alg == "pivot":
                     splits = sum(c - thr for c in heavy)
                     extra = len(heavy) + splits
@@ -141,10 +148,15 @@ def test_split_no_split_tree_and_degenerate_cases():
         assert oracle.kclique_split(g.row_ptr, g.col, 1, range_leaf=8, algorithm=alg).value == 30
         r2 = oracle.kclique_split(g.row_ptr, g.col, 2, range_leaf=8, algorithm=alg)
         assert r2.value == m and r2.tasks == rt + 30
-        for k in (3, 4, 5):
+        r = oracle.kclique_split(g.row_ptr, g.col, 3, range_leaf=8, threshold=1000, algorithm=alg)
+        assert r.tasks == rt + 30 + m and r.aux == 0
+        assert r.conts == rt + int((deg > 0).sum())
+        for k in (4, 5):
+            # vertices with k-1 or more out-neighbours: row tasks, edge tasks, two resumptions
+            live = deg >= k - 1
             r = oracle.kclique_split(g.row_ptr, g.col, k, range_leaf=8, threshold=1000, algorithm=alg)
-            assert r.tasks == rt + 30 + m and r.aux == 0
-            assert r.conts == rt + int((deg > 0).sum())
+            assert r.tasks == rt + 30 + 2 * int(deg[live].sum()) and r.aux == 0
+            assert r.conts == rt + 2 * int(live.sum())
         e0 = graphs.oriented_from_edges(12, [], "id")
         assert oracle.kclique_split(e0.row_ptr, e0.col, 4, algorithm=alg).value == 0
         z = graphs.oriented_from_edges(0, [], "id")
