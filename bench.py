@@ -132,8 +132,8 @@ def bench_kclique7(args, gtap) -> int:
     if args.queues > 1:
         opts.update(num_queues=args.queues, daq_policy=2, daq_bounds=[8, 32, 128][: args.queues - 1],
                     deque_capacity=1 << 19, big_frames=1 << 24)
-    if split:  # bit-matrix frames for heavy edges and the nodes that split
-        opts.update(waves_per_group=4, big_frames=1 << 20,
+    if split:  # node-state frames for heavy edges and the nodes that split
+        opts.update(waves_per_group=4, big_frames=1 << 23,
                     big_frame_ints=gtap.kclique_split_buffer_ints(g.max_outdeg))
     rt = gtap.Runtime(**opts)
     rp = torch.as_tensor(g.row_ptr32).cuda()

@@ -97,10 +97,14 @@ typedef struct {
 
 /* k-clique count with bitset-encoded candidate subgraphs and cost-threshold
  * task splitting (Sec. 6.4.2: the orientation and the pivoting algorithms).
- * The vertex range splits as for GTAP_KIND_KCLIQUE; a vertex task forks one
- * edge task per out-neighbour.  Edge (u, v) encodes the subgraph induced on
- * its candidates N+(u) /\ N+(v) as a bit matrix in its big frame and counts
- * the (k-2)-cliques in it.  A search node whose candidate set has more than
+ * The vertex range splits as for GTAP_KIND_KCLIQUE.  For k >= 4 a vertex u
+ * with at least k-1 out-neighbours encodes the subgraph induced on N+(u) as a
+ * bit matrix (one row task per out-neighbour), then forks one edge task per
+ * out-neighbour v: the edge's candidates N+(u) /\ N+(v) are row v, and it
+ * counts the (k-2)-cliques among them (k = 3: the size of the intersection).
+ * gtap_run allocates the job's matrices for the run: sum over those vertices
+ * of d * ceil(d/64) * 8 bytes (twice that for pivoting), d = out-degree.
+ * A search node whose candidate set has more than
  * `threshold` members splits into one child task per branch -- per candidate
  * for the orientation algorithm; the pivot and each of its non-neighbours for
  * pivoting -- and every child applies the same test; smaller nodes are

@@ -240,27 +240,6 @@ __global__ __launch_bounds__(256) void k_list_hash(const uint64_t *pairs, uint64
   if (lane_id() == 0 && k) fetch_add_relaxed(count, k);
 }
 
-// Taylor coefficients T_g of 1/|d + h| at h = 0, total degree <= 6, by the
-// Coulomb three-term recurrence, fully unrolled so that T stays in registers.
-GTAP_DEV void taylor_coeffs(double d0, double d1, double d2, double *T) {
-  const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-  const double inv_r2 = 1.0 / r2;
-  T[0] = sqrt(inv_r2);
-  const double dd[3] = {d0, d1, d2};
-#pragma unroll
-  for (int t = 1; t < kNc; ++t) {
-    const double deg = static_cast<double>(kTab.deg[t]);
-    double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const uint8_t m1 = kTab.dm1[t][i], m2 = kTab.dm2[t][i];
-      if (m1 != 0xFF) s1 += dd[i] * T[m1];
-      if (m2 != 0xFF) s2 += T[m2];
-    }
-    T[t] = -((2.0 * deg - 1.0) * s1 + (deg - 1.0) * s2) * inv_r2 / deg;
-  }
-}
-
 constexpr uint32_t kM2LThreads = 64;
 
 GTAP_DEV double mfact(int t) {  // e_t! = e_x! e_y! e_z! of coefficient t

@@ -3,11 +3,13 @@
 //
 // Every k-clique is counted at the edge (u, v) between its two lowest vertices
 // in the orientation's order; its other k-2 vertices form a (k-2)-clique of
-// the edge's candidate set C = N+(u) /\ N+(v) (c vertices, ascending).  An
-// edge task numbers its candidates 0..c-1 and encodes their subgraph as a bit
-// matrix: row i holds the candidates adjacent to candidate i -- out-neighbours
-// for the orientation algorithm, neighbours in either direction for pivoting
-// -- in W = ceil(c/64) words.
+// the edge's candidate set C = N+(u) /\ N+(v).  A vertex task u encodes the
+// subgraph induced on N+(u) (d vertices, ascending) as a bit matrix: row i
+// holds the members of N+(u) that are out-neighbours of its i-th member, in
+// W = ceil(d/64) words; its row tasks build the rows in parallel.  Edge (u, v)
+// then finds C as v's row, and the adjacency inside C in the rows of C's
+// members -- out-neighbours for the orientation algorithm, neighbours in
+// either direction (a second matrix, U) for pivoting.
 //
 // A node of the search splits when its candidate set is larger than the
 // threshold t (the spawn-time cost estimate): it stores its state in its frame
@@ -26,17 +28,16 @@
 //                 ascending order as a held vertex, with the candidates that
 //                 remain after removing p and the earlier non-neighbours.
 //
-// Big-frame buffer of an edge task (int32 words from FW_BUF):
-//   [0] c  [1] W  [2] offset of the rows  [3] offset of the node state
-//   [4, 4+c) the candidate list, then the rows (c x W words), then the node
-//   state.  A node task's buffer holds only its node state, at offset 0.
-// Node state: one 64-bit meta word (level or held count | pivots << 16 |
-// pivot << 32), the candidate set P (W words), pivoting's branch set R (W
-// words: the pivot's non-neighbours other than the pivot).
-// Data another task reads (header, rows, node state) is stored with
-// device-coherent stores and read with device-coherent loads; what a lane only
-// reads back itself (the candidate list, rows before they are published) uses
-// plain accesses.
+// The bit matrices of all vertices of a job live in one device buffer the
+// library allocates per run, after n+1 per-vertex offsets (64-bit words)
+// computed on the host from row_ptr: vertex u's D, then for pivoting its U.
+// A node task's big-frame buffer holds only its node state: one 64-bit meta
+// word (level or held count | pivots << 16 | pivot << 32), the candidate set
+// P (W words), pivoting's branch set R (W words: the pivot's non-neighbours
+// other than the pivot).
+// Data another task reads (matrices, node state) is stored with
+// device-coherent stores (U by device-scope atomic ORs onto a cleared matrix)
+// and read with device-coherent loads.
 #pragma once
 #include "layout.h"
 #include "wave.h"
@@ -49,14 +50,11 @@ constexpr uint32_t kMaxThr = 64;          // in-place node sets fit one word
 constexpr uint32_t kMaxK = 32;            // clique size
 constexpr uint32_t kStack = kMaxThr + 2;  // in-place pivoting depth bound
 
-enum : uint32_t { EB_C = 0, EB_W = 1, EB_ROWS = 2, EB_NS = 3, EB_LIST = 4 };
-
-// Buffer ints an edge or node task needs for out-degree bound D.
+// Big-frame buffer ints of a node task (its node state) for out-degree
+// bound D.
 __host__ __device__ inline uint32_t buffer_ints(uint32_t D) {
   const uint32_t W = D > 0 ? (D + 63) / 64 : 1;
-  const uint32_t edge = EB_LIST + ((D + 1) & ~1u) + 2 * D * W + 2 + 4 * W;
-  const uint32_t node = 2 + 4 * W;
-  return edge > node ? edge : node;
+  return 2 + 4 * W;
 }
 
 GTAP_DEV uint64_t low_mask(uint32_t m) { return m >= 64 ? ~0ull : ((1ull << m) - 1); }
@@ -141,53 +139,6 @@ GTAP_DEV uint32_t isect(const int32_t *a, uint32_t na, const int32_t *b, uint32_
     }
   }
   return o;
-}
-
-// Candidates of C[0, c) in the out-list a[0, na), as a bit row; word w of the
-// row goes to row[w] (plain stores), all W words written.
-GTAP_DEV void build_row(const int32_t *a, uint32_t na, const int32_t *C, uint32_t c, uint64_t *row, uint32_t W) {
-  uint32_t i = 0, j = 0, cw = 0;
-  uint64_t acc = 0;
-  if (na > 0 && c > 0) {
-    int32_t x = a[0], y = C[0];
-    for (;;) {
-      if (x < y) {
-        if (++i == na) break;
-        x = a[i];
-      } else if (x > y) {
-        if (++j == c) break;
-        y = C[j];
-      } else {
-        while ((j >> 6) > cw) {
-          row[cw++] = acc;
-          acc = 0;
-        }
-        acc |= 1ull << (j & 63);
-        if (++i == na || ++j == c) break;
-        x = a[i];
-        y = C[j];
-      }
-    }
-  }
-  for (; cw < W; ++cw) {
-    row[cw] = acc;
-    acc = 0;
-  }
-}
-
-// One-word row of a light edge (c <= 64): the candidates C[0, c) (private,
-// ascending) that are in the out-list a[0, na), each galloped to.
-GTAP_DEV uint64_t row_word(const int32_t *a, uint32_t na, const int32_t *C, uint32_t c) {
-  uint64_t acc = 0;
-  uint32_t i = 0;
-  for (uint32_t j = 0; j < c && i < na; ++j) {
-    i = gallop(a, i, na, C[j]);
-    if (i < na && a[i] == C[j]) {
-      acc |= 1ull << j;
-      ++i;
-    }
-  }
-  return acc;
 }
 
 // l-cliques of the DAG with one-word rows A on the set S0 (orientation, in place).

@@ -69,6 +69,7 @@ enum TaskKind : uint32_t {
   TK_KS_EDGE = 13,    //   edge (u, v): candidates N+(u) /\ N+(v), counted in place if few
   TK_KS_HEAVY = 14,   //   edge with many candidates: their bit matrix, the search's root
   TK_KS_NODE = 15,    //   branch of a node that split
+  TK_KS_ROW = 16,     //   one row of a vertex's bit matrix
 };
 
 struct alignas(128) DequeMeta {

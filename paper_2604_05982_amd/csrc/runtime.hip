@@ -220,6 +220,9 @@ struct gtap_ctx {
   // FMM jobs: arguments by pending position, results by run position
   std::vector<gtap_fmm_args> pending_fmm;
   std::vector<gtap_fmm_result> done_fmm;
+  // split k-clique jobs: per pending job, each vertex's offset (in 64-bit
+  // words) into the job's bit-matrix buffer, n+1 entries (empty: no matrices)
+  std::vector<std::vector<uint64_t>> pending_ks;
   gtap_stats stats{};
   gtap_error_report err{};
 };
@@ -349,7 +352,8 @@ extern "C" int32_t gtap_kclique_split_buffer_ints(int32_t max_outdeg) {
 }
 
 // Validate a root task's arguments and pack them into a job slot.
-static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, JobSlot &J) {
+static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, JobSlot &J,
+                    std::vector<uint64_t> *ks_off = nullptr) {
   if (!args) return GTAP_E_INVAL;
   std::memset(&J, 0, sizeof(J));
   J.kind = static_cast<uint32_t>(kind);
@@ -427,6 +431,16 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
           return GTAP_E_HIP;
         for (int32_t v = 0; v < a.n; ++v)
           if (rp[v + 1] < rp[v] || rp[v + 1] - rp[v] > a.max_outdeg) return GTAP_E_INVAL;
+        // k >= 4: a vertex with at least k-1 out-neighbours gets its d x W bit
+        // matrix (two of them for pivoting) in the job's matrix buffer
+        if (ks_off && a.k >= 4) {
+          ks_off->assign(static_cast<size_t>(a.n) + 1, 0);
+          const uint64_t mats = a.algorithm == GTAP_KCLIQUE_PIVOT ? 2 : 1;
+          for (int32_t v = 0; v < a.n; ++v) {
+            const uint64_t d = static_cast<uint64_t>(rp[v + 1] - rp[v]);
+            (*ks_off)[v + 1] = (*ks_off)[v] + (d >= static_cast<uint64_t>(a.k - 1) ? mats * d * ((d + 63) / 64) : 0);
+          }
+        }
       }
       J.a[0] = reinterpret_cast<uint64_t>(a.row_ptr_dev);
       J.a[1] = reinterpret_cast<uint64_t>(a.col_dev);
@@ -477,16 +491,19 @@ extern "C" int gtap_submit(gtap_ctx *c, int32_t kind, const void *args, size_t a
   if (c->serving) return GTAP_E_STATE;
   if (c->pending.size() >= c->cfg.max_jobs) return GTAP_E_FULL;
   JobSlot J;
-  const int rc = pack_job(c, kind, args, args_bytes, J);
+  std::vector<uint64_t> ks_off;
+  const int rc = pack_job(c, kind, args, args_bytes, J, &ks_off);
   if (rc) return rc;
   if (c->pending.empty()) {
     c->pending_first = c->next_job_id;
     c->pending_fmm.clear();
+    c->pending_ks.clear();
   }
   c->pending.push_back(J);
   gtap_fmm_args fa{};
   if (kind == GTAP_KIND_FMM) std::memcpy(&fa, args, sizeof(fa));
   c->pending_fmm.push_back(fa);
+  c->pending_ks.push_back(std::move(ks_off));
   if (job_id) *job_id = c->next_job_id;
   c->next_job_id++;
   return GTAP_OK;
@@ -974,11 +991,32 @@ int gtap_run(gtap_ctx *c) {
     any_ext |= c->pending[j].kind == GTAP_KIND_FMM || c->pending[j].kind == GTAP_KIND_CILKSORT ||
                c->pending[j].kind == GTAP_KIND_KCLIQUE_SPLIT;
   }
+  std::vector<void *> ks_mem;
   auto drop_pending = [&]() {
     for (FmmJobMem &m : fm) fmm_free(m);
+    for (void *q : ks_mem) (void)hipFree(q);
     c->pending.clear();
     c->pending_fmm.clear();
+    c->pending_ks.clear();
   };
+  // split k-clique jobs: offsets and bit matrices in one device buffer
+  for (size_t j = 0; j < nj; ++j) {
+    const std::vector<uint64_t> &off = c->pending_ks[j];
+    if (c->pending[j].kind != GTAP_KIND_KCLIQUE_SPLIT || off.empty()) continue;
+    void *q = nullptr;
+    const size_t words = off.size() + off.back();
+    if (hipMalloc(&q, words * sizeof(uint64_t)) != hipSuccess) {
+      drop_pending();
+      return GTAP_E_NOMEM;
+    }
+    ks_mem.push_back(q);
+    if (hipMemcpyAsync(q, off.data(), off.size() * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream) !=
+        hipSuccess) {
+      drop_pending();
+      return GTAP_E_HIP;
+    }
+    c->pending[j].a[7] = reinterpret_cast<uint64_t>(q);
+  }
   if (any_fmm) {
     fm.resize(nj);
     for (size_t j = 0; j < nj; ++j) {

@@ -1056,9 +1056,10 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       }
     }
     if constexpr (kExt) {
-      // Cilksort: keys a task wrote are complete before its completion can
-      // resume the parent that hands them to the next task
-      if (ballot(done && (o.kind == TK_SORT || o.kind == TK_MERGE)) != 0ull) drain();
+      // Cilksort keys, rows of a vertex's k-clique bit matrix: what a task
+      // wrote is complete before its completion can resume the parent that
+      // hands it to the next tasks
+      if (ballot(done && (o.kind == TK_SORT || o.kind == TK_MERGE || o.kind == TK_KS_ROW)) != 0ull) drain();
     }
     const int64_t lim = static_cast<int64_t>(1) << kSmallValueBits;
     const bool big_val = tail && (run_val >= lim || run_val <= -lim);
@@ -1105,9 +1106,10 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       uint32_t *f = frame_ptr(p, self);
       if (need_self) co_st64(frame64(f), pack(o.parent, o.job));
       if constexpr (kExt) {
-        // Cilksort: a sort resumes twice and reads its range from the frame
+        // Cilksort sorts and k-clique vertices resume twice and read their
+        // arguments from the frame
         co_st32(f + FW_STATE, state_word(o.kind, o.pc_next, 0));
-        if (need_self && o.kind == TK_SORT) {
+        if (need_self && (o.kind == TK_SORT || o.kind == TK_KS_VERTEX)) {
           co_st32(f + FW_P0, o.d[0]);
           co_st32(f + FW_P0 + 1, o.d[1]);
           co_st32(f + FW_P0 + 2, o.d[2]);

@@ -192,6 +192,8 @@ GTAP_DEV uint32_t count_below(const uint32_t *s, uint32_t n, uint32_t v) {
 struct KsJob {
   const int32_t *rp;
   const int32_t *col;
+  uint64_t *mat;   // job argument 7: n+1 vertex offsets, then the bit matrices
+  uint32_t n;
   uint32_t kk;     // k - 2: clique size inside an edge's candidate set
   uint32_t thr;
   bool pivot;
@@ -200,8 +202,25 @@ GTAP_DEV KsJob ks_job(const Params &p, uint32_t job) {
   const uint64_t a6 = job_arg(p, job, 6);
   return KsJob{reinterpret_cast<const int32_t *>(job_arg(p, job, 0)),
                reinterpret_cast<const int32_t *>(job_arg(p, job, 1)),
+               reinterpret_cast<uint64_t *>(job_arg(p, job, 7)), static_cast<uint32_t>(job_arg(p, job, 2)),
                static_cast<uint32_t>(job_arg(p, job, 3)) - 2, static_cast<uint32_t>(a6 & 0xFFu),
                ((a6 >> 8) & 1u) != 0};
+}
+
+// Vertex u's bit matrices: D (row i: the members of N+(u) that are
+// out-neighbours of its i-th member), then for pivoting U (D or its
+// transpose); d x W words each.  The offsets are read coherently like all
+// job data.
+struct KsMat {
+  uint64_t *D;
+  uint64_t *rows;  // the rows the search uses: U for pivoting, else D
+  uint32_t d, W;
+};
+GTAP_DEV KsMat ks_mat(const KsJob &J, uint32_t u) {
+  const uint32_t d = static_cast<uint32_t>(J.rp[u + 1] - J.rp[u]);
+  const uint32_t W = (d + 63) / 64;
+  uint64_t *D = J.mat + (J.n + 1) + co_ld64(J.mat + u);
+  return KsMat{D, J.pivot ? D + static_cast<size_t>(d) * W : D, d, W};
 }
 
 // Store a node's state at buf (device-coherent: its children read it).
@@ -235,116 +254,137 @@ GTAP_DEV uint32_t ks_pivot(const uint64_t *rows, uint32_t W, const uint64_t *P, 
   return best;
 }
 
-// Edge task (u, the j-th out-neighbour v of u).  Few candidates: the whole
-// search in place, from a private candidate list (no frame needed); more than
-// the threshold: one child task takes the search over in a big frame.
-GTAP_DEV void ks_edge(const Params &p, Outcome &o, uint32_t u, uint32_t j) {
+// Row task (u, i): row i of u's matrix, from N+(u) /\ N+(x), x = N+(u)[i],
+// galloping from the shorter list; for pivoting also ORed into U both ways
+// (U was cleared by the vertex task).
+GTAP_DEV void ks_row(const Params &p, Outcome &o, uint32_t u, uint32_t i) {
   const KsJob J = ks_job(p, o.job);
-  const int32_t s0 = J.rp[u];
-  const uint32_t du = static_cast<uint32_t>(J.rp[u + 1] - s0);
-  const int32_t v = J.col[s0 + j];
-  const int32_t s1 = J.rp[v];
-  const uint32_t dv = static_cast<uint32_t>(J.rp[v + 1] - s1);
-  int32_t C[kcs::kMaxThr];
-  const uint32_t c = kcs::isect(J.col + s0, du, J.col + s1, dv, C, J.kk == 1 ? 0u : J.thr);
+  const KsMat M = ks_mat(J, u);
+  const uint32_t d = M.d, W = M.W;
+  const int32_t *nu = J.col + J.rp[u];
+  const int32_t x = nu[i];
+  const int32_t *nx = J.col + J.rp[x];
+  const uint32_t dx = static_cast<uint32_t>(J.rp[x + 1] - J.rp[x]);
+  uint64_t *D = M.D + static_cast<size_t>(i) * W;
+  uint64_t *U = M.rows;
+  uint32_t cw = 0;
+  uint64_t acc = 0;
+  auto flush = [&]() {  // word cw of row i is complete
+    co_st64(D + cw, acc);
+    if (J.pivot && acc) fetch_or_relaxed(U + static_cast<size_t>(i) * W + cw, acc);
+    ++cw;
+    acc = 0;
+  };
+  auto hit = [&](uint32_t j) {  // j ascending
+    while ((j >> 6) > cw) flush();
+    acc |= 1ull << (j & 63);
+    if (J.pivot) fetch_or_relaxed(U + static_cast<size_t>(j) * W + (i >> 6), static_cast<uint64_t>(1) << (i & 63));
+  };
+  if (d <= dx) {  // each member of N+(u), galloped to in N+(x)
+    uint32_t t = 0;
+    for (uint32_t j = 0; j < d && t < dx; ++j) {
+      t = kcs::gallop(nx, t, dx, nu[j]);
+      if (t < dx && nx[t] == nu[j]) {
+        hit(j);
+        ++t;
+      }
+    }
+  } else {  // each out-neighbour of x, galloped to in N+(u)
+    uint32_t j = 0;
+    for (uint32_t t = 0; t < dx && j < d; ++t) {
+      j = kcs::gallop(nu, j, d, nx[t]);
+      if (j < d && nu[j] == nx[t]) {
+        hit(j);
+        ++j;
+      }
+    }
+  }
+  while (cw < W) flush();
+}
+
+// Edge task (u, i): the i-th out-neighbour v of u.  k = 3: |N+(u) /\ N+(v)|.
+// Otherwise its candidates are row i of u's matrix: few -> renumbered into a
+// private one-word matrix and counted in place; more than the threshold ->
+// one child task takes the search over.
+GTAP_DEV void ks_edge(const Params &p, Outcome &o, uint32_t u, uint32_t i) {
+  const KsJob J = ks_job(p, o.job);
   if (J.kk == 1) {
-    o.value = c;
+    const int32_t s0 = J.rp[u];
+    const int32_t v = J.col[s0 + i];
+    o.value = kcs::isect(J.col + s0, static_cast<uint32_t>(J.rp[u + 1] - s0), J.col + J.rp[v],
+                         static_cast<uint32_t>(J.rp[v + 1] - J.rp[v]), nullptr, 0);
     return;
   }
+  const KsMat M = ks_mat(J, u);
+  const uint32_t W = M.W;
+  uint64_t S[kcs::kMaxW];
+  uint32_t c = 0;
+  for (uint32_t w = 0; w < W; ++w) {
+    S[w] = co_ld64(M.D + static_cast<size_t>(i) * W + w);
+    c += __popcll(S[w]);
+  }
   if (c < J.kk) return;
+  if (!J.pivot && J.kk == 2) {  // directed edges inside C
+    int64_t e = 0;
+    for (uint32_t w = 0; w < W; ++w)
+      for (uint64_t t = S[w]; t; t &= t - 1) {
+        const uint32_t y = w * 64 + __builtin_ctzll(t);
+        for (uint32_t v = 0; v < W; ++v) e += __popcll(S[v] & co_ld64(M.D + static_cast<size_t>(y) * W + v));
+      }
+    o.value = e;
+    return;
+  }
   if (c > J.thr) {
     o.type = OUT_FORK;
     o.nchild = 1;
     o.ckind = TK_KS_HEAVY;
     o.big = 1;
     o.d[0] = u;
-    o.d[1] = j;
+    o.d[1] = i;
     return;
   }
   uint64_t A[kcs::kMaxThr];
-  for (uint32_t i = 0; i < c; ++i) {
-    const int32_t x = C[i];
-    A[i] = kcs::row_word(J.col + J.rp[x], static_cast<uint32_t>(J.rp[x + 1] - J.rp[x]), C, c);
-  }
-  if (J.pivot) {  // undirected closure, in place
-    for (uint32_t i = 0; i < c; ++i)
-      for (uint64_t t = A[i]; t; t &= t - 1) A[__builtin_ctzll(t)] |= 1ull << i;
-  }
+  kcs::compact(M.rows, W, S, A);
   const uint64_t all = kcs::low_mask(c);
   o.value = J.pivot ? kcs::sct_count(A, all, 0, 0, J.kk) : kcs::dag_count(A, all, J.kk);
 }
 
-// Root node of a heavy edge's search, in a big frame: the candidate list and
-// the bit matrix go to the buffer, then one task per branch (the orientation
-// algorithm counts in place when only pairs remain: k = 4).
-GTAP_DEV void ks_heavy(const Params &p, uint32_t tid, uint32_t *f, Outcome &o, uint32_t u, uint32_t j) {
+// Root node of a heavy edge's search (its big frame holds the node state;
+// the matrix is u's): one task per branch.
+GTAP_DEV void ks_heavy(const Params &p, uint32_t *f, Outcome &o, uint32_t u, uint32_t i) {
   const KsJob J = ks_job(p, o.job);
-  const int32_t s0 = J.rp[u];
-  const uint32_t du = static_cast<uint32_t>(J.rp[u + 1] - s0);
-  const int32_t v = J.col[s0 + j];
-  const int32_t s1 = J.rp[v];
-  const uint32_t dv = static_cast<uint32_t>(J.rp[v + 1] - s1);
-  uint32_t *buf = f + FW_BUF;
-  int32_t *C = reinterpret_cast<int32_t *>(buf + kcs::EB_LIST);
-  const uint32_t c = kcs::isect(J.col + s0, du, J.col + s1, dv, C, 0xFFFFFFFFu);
-  if (!J.pivot && J.kk == 2) {  // directed edges inside C
-    int64_t e = 0;
-    for (uint32_t i = 0; i < c; ++i) {
-      const int32_t x = C[i];
-      e += kcs::isect(J.col + J.rp[x], static_cast<uint32_t>(J.rp[x + 1] - J.rp[x]), C, c, nullptr, 0);
-    }
-    o.value = e;
-    return;
-  }
-  // heavy: the whole matrix in the frame, then one task per branch
-  const uint32_t W = (c + 63) / 64;
-  const uint32_t rows_off = kcs::EB_LIST + ((c + 1) & ~1u);
-  const uint32_t ns = rows_off + 2 * c * W;
-  uint64_t *rows = reinterpret_cast<uint64_t *>(buf + rows_off);
-  for (uint32_t i = 0; i < c; ++i) {
-    const int32_t x = C[i];
-    kcs::build_row(J.col + J.rp[x], static_cast<uint32_t>(J.rp[x + 1] - J.rp[x]), C, c,
-                   rows + static_cast<size_t>(i) * W, W);
-  }
-  if (J.pivot) {  // undirected closure, in place
-    for (uint32_t i = 0; i < c; ++i)
-      for (uint32_t w = 0; w < W; ++w)
-        for (uint64_t t = rows[static_cast<size_t>(i) * W + w]; t; t &= t - 1) {
-          const uint32_t y = w * 64 + __builtin_ctzll(t);
-          rows[static_cast<size_t>(y) * W + (i >> 6)] |= 1ull << (i & 63);
-        }
-  }
-  for (uint32_t x = 0; x < c * W; ++x) co_st64(rows + x, rows[x]);
-  co_st32(buf + kcs::EB_C, c);
-  co_st32(buf + kcs::EB_W, W);
-  co_st32(buf + kcs::EB_ROWS, rows_off);
-  co_st32(buf + kcs::EB_NS, ns);
+  const KsMat M = ks_mat(J, u);
+  const uint32_t W = M.W;
   uint64_t P[kcs::kMaxW], R[kcs::kMaxW];
-  for (uint32_t w = 0; w < W; ++w) P[w] = kcs::low_mask(c > w * 64 ? c - w * 64 : 0);
+  uint32_t c = 0;
+  for (uint32_t w = 0; w < W; ++w) {
+    P[w] = co_ld64(M.D + static_cast<size_t>(i) * W + w);
+    c += __popcll(P[w]);
+  }
   uint64_t meta = J.kk;
   uint32_t nchild = c;
   if (J.pivot) {
-    const uint32_t piv = ks_pivot(rows, W, P, R);
+    const uint32_t piv = ks_pivot(M.rows, W, P, R);
     meta = static_cast<uint64_t>(piv) << 32;  // no held vertices, no pivots yet
     nchild = 1;
     for (uint32_t w = 0; w < W; ++w) nchild += __popcll(R[w]);
   }
-  ks_store_node(buf + ns, meta, P, R, W, J.pivot);
+  ks_store_node(f + FW_BUF, meta, P, R, W, J.pivot);
   o.type = OUT_FORK;
   o.nchild = nchild;
   o.ckind = TK_KS_NODE;
   o.big = (J.pivot || J.kk - 1 >= 3) ? 1u : 0u;  // children that may split keep state in a big frame
-  o.d[0] = tid;
-  o.d[1] = ns;
+  o.d[0] = u;
+  o.d[1] = 0;
 }
 
-// Branch j of a node that split: E is the edge task's frame, ns the node
-// state's offset in the parent's buffer.
-GTAP_DEV void ks_node(const Params &p, uint32_t tid, uint32_t *f, Outcome &o, uint32_t E, uint32_t j, uint32_t ns) {
+// Branch j of a node that split: u is the vertex whose matrix the search
+// uses, ns the node state's offset in the parent's buffer.
+GTAP_DEV void ks_node(const Params &p, uint32_t *f, Outcome &o, uint32_t u, uint32_t j, uint32_t ns) {
   const KsJob J = ks_job(p, o.job);
-  const uint32_t *eb = frame_ptr(p, E) + FW_BUF;
-  const uint32_t W = co_ld32(eb + kcs::EB_W);
-  const uint64_t *rows = reinterpret_cast<const uint64_t *>(eb + co_ld32(eb + kcs::EB_ROWS));
+  const KsMat M = ks_mat(J, u);
+  const uint32_t W = M.W;
+  const uint64_t *rows = M.rows;
   const uint64_t *pb = reinterpret_cast<const uint64_t *>(frame_ptr(p, o.parent) + FW_BUF + ns);
   const uint64_t meta = co_ld64(pb);
   uint64_t P[kcs::kMaxW], S[kcs::kMaxW], R[kcs::kMaxW];
@@ -423,7 +463,7 @@ GTAP_DEV void ks_node(const Params &p, uint32_t tid, uint32_t *f, Outcome &o, ui
     o.big = 1;
   }
   o.ckind = TK_KS_NODE;
-  o.d[0] = E;
+  o.d[0] = u;
   o.d[1] = 0;
 }
 
@@ -466,6 +506,16 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
         return;
       }
       o.value = n;
+      return;
+    }
+    if (pc == 1 && kind == TK_KS_VERTEX) {  // the matrix is complete: the edge tasks
+      const uint32_t u = co_ld32(frame_ptr(p, tid) + FW_P0);  // (written at spawn or when it forked)
+      const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 0));
+      o.type = OUT_FORK;
+      o.nchild = static_cast<uint32_t>(rp[u + 1] - rp[u]);
+      o.ckind = TK_KS_EDGE;
+      o.d[0] = u;
+      o.pc_next = 2;
       return;
     }
   }
@@ -562,7 +612,10 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
       o.ckind = hi - lo > leaf ? TK_KS_RANGE : TK_KS_VERTEX;
       return;
     }
-    if (kind == TK_KS_VERTEX) {  // one edge task per out-neighbour
+    if (kind == TK_KS_VERTEX) {
+      // k = 3: one edge task per out-neighbour.  k >= 4 (at least k-1
+      // out-neighbours): the row tasks of the vertex's matrix first (resume
+      // point 1 forks the edge tasks, resume point 2 sums them)
       const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 0));
       const uint32_t k = static_cast<uint32_t>(job_arg(p, o.job, 3));
       const uint32_t deg = static_cast<uint32_t>(rp[p0 + 1] - rp[p0]);
@@ -570,11 +623,25 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
         o.value = k == 1 ? 1 : deg;
         return;
       }
-      if (deg == 0) return;
+      if (deg == 0 || (k >= 4 && deg < k - 1)) return;
       o.type = OUT_FORK;
       o.nchild = deg;
-      o.ckind = TK_KS_EDGE;
       o.d[0] = p0;
+      if (k == 3) {  // no matrix: the edge tasks now, the sum at resume point 2
+        o.ckind = TK_KS_EDGE;
+        o.pc_next = 2;
+        return;
+      }
+      const KsJob J = ks_job(p, o.job);
+      if (J.pivot) {  // U is built by atomic ORs: cleared first
+        const KsMat M = ks_mat(J, p0);
+        for (uint32_t x = 0; x < deg * M.W; ++x) co_st64(M.rows + x, 0ull);
+      }
+      o.ckind = TK_KS_ROW;
+      return;
+    }
+    if (kind == TK_KS_ROW) {
+      ks_row(p, o, p0, p1);
       return;
     }
     if (kind == TK_KS_EDGE) {
@@ -582,11 +649,11 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
       return;
     }
     if (kind == TK_KS_HEAVY) {
-      ks_heavy(p, tid, f, o, p0, p1);
+      ks_heavy(p, f, o, p0, p1);
       return;
     }
     if (kind == TK_KS_NODE) {
-      ks_node(p, tid, f, o, p0, p1, p2);
+      ks_node(p, f, o, p0, p1, p2);
       return;
     }
     if (kind == TK_DTT) {
@@ -834,7 +901,7 @@ GTAP_DEV void make_child(uint32_t ckind, const uint32_t *d, uint32_t j, ChildIni
       c.p[0] = d[0] + j;
       return;
     }
-    if (ckind == TK_KS_EDGE) {  // (u, index of the out-neighbour)
+    if (ckind == TK_KS_EDGE || ckind == TK_KS_ROW) {  // (u, index of the out-neighbour)
       c.p[0] = d[0];
       c.p[1] = j;
       return;
@@ -844,7 +911,7 @@ GTAP_DEV void make_child(uint32_t ckind, const uint32_t *d, uint32_t j, ChildIni
       c.p[1] = d[1];
       return;
     }
-    if (ckind == TK_KS_NODE) {  // (edge frame, branch, parent's node-state offset)
+    if (ckind == TK_KS_NODE) {  // (vertex, branch, parent's node-state offset)
       c.p[0] = d[0];
       c.p[1] = j;
       c.p[2] = d[1];

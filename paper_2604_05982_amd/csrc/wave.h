@@ -127,6 +127,10 @@ template <typename T>
 GTAP_DEV T fetch_add_relaxed(T *p, T v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+template <typename T>
+GTAP_DEV T fetch_or_relaxed(T *p, T v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 // CAS; on failure *expected receives the current value.
 template <typename T>
 GTAP_DEV bool cas_relaxed(T *p, T *expected, T desired) {

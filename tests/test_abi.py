@@ -84,10 +84,11 @@ def test_enum_values_match_header(tmp_path):
 
 
 def test_kclique_split_buffer_size_without_device():
-    """Buffer ints of a split k-clique job: list, bit matrix and node state
-    for out-degree D (W = ceil(D/64) words per row); 0 outside [0, 1024]."""
+    """Big-frame buffer ints of a split k-clique job: a split node's state
+    (a 64-bit meta word and two sets of W = ceil(D/64) 64-bit words) for
+    out-degree D; 0 outside [0, 1024]."""
     from paper_2604_05982_amd import gtap
     for d in (0, 1, 40, 64, 65, 313, 1024):
         w = max((d + 63) // 64, 1)
-        assert gtap.kclique_split_buffer_ints(d) == max(4 + ((d + 1) & ~1) + 2 * d * w + 2 + 4 * w, 2 + 4 * w)
+        assert gtap.kclique_split_buffer_ints(d) == 2 + 4 * w
     assert gtap.kclique_split_buffer_ints(-1) == 0 and gtap.kclique_split_buffer_ints(1025) == 0

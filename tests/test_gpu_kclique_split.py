@@ -88,7 +88,7 @@ def test_split_multiword_candidate_sets(gtap, alg):
                             ("K_{12x8}", multipartite(12, 8), lambda k: math.comb(12, k) * 8 ** k)):
         assert g.max_outdeg > 64
         ks, thrs = cases[(alg, name)]
-        with make_rt(gtap, g.max_outdeg, big_frames=1 << 19) as rt:
+        with make_rt(gtap, g.max_outdeg, big_frames=1 << 21) as rt:
             for k in ks:
                 for thr in thrs:
                     say(f"split k-clique {alg} {name} k={k} thr={thr}")
@@ -167,7 +167,7 @@ def test_split_shares_launch_with_other_jobs(gtap):
     col = torch.as_tensor(g.col).cuda()
     keys = np.random.default_rng(4).integers(0, 2**32, size=20000, dtype=np.uint32)
     kt = torch.from_numpy(keys.view(np.int32)).cuda()
-    with make_rt(gtap, g.max_outdeg) as rt:
+    with make_rt(gtap, g.max_outdeg, big_frames=1 << 19) as rt:
         say("split k-clique jobs with other kinds in one launch")
         jobs = [(rt.submit_kclique_split(rp, col, k, threshold=t, algorithm=a, max_outdeg=g.max_outdeg),
                  oracle.kclique(g.row_ptr, g.col, k).value)
@@ -193,7 +193,7 @@ def test_split_full_size_chung_lu_1m(gtap, alg):
                 want = (f[1], int(f[3]))
     g = graphs.chung_lu(1000000, 40, 2.1, 0.6, 2)
     assert g.checksum() == want[0]
-    with make_rt(gtap, g.max_outdeg, big_frames=1 << 20, deque_capacity=1 << 17) as rt:
+    with make_rt(gtap, g.max_outdeg, big_frames=1 << 23, deque_capacity=1 << 17) as rt:
         say(f"split k-clique {alg}: 7-cliques of the 10^6-vertex graph")
         got, st = run_split(rt, g, 7, 16, alg, gtap)
         say(f"  count {got}, tasks {st['tasks']}, kernel {st['kernel_ms']:.1f} ms")
