@@ -130,7 +130,8 @@ def bench_kclique7(args, gtap) -> int:
                 timeout_ms=60000, steal_below=args.steal_below)
     split = args.kclique_split != "none"
     if args.queues > 1:
-        opts.update(num_queues=args.queues, daq_policy=2, daq_bounds=[8, 32, 128][: args.queues - 1],
+        opts.update(num_queues=args.queues, daq_policy=2,
+                    daq_bounds=[int(b) for b in args.daq_bounds.split(",")][: args.queues - 1],
                     deque_capacity=1 << 19, big_frames=1 << 24)
     if split:  # node-state frames for heavy edges and the nodes that split
         opts.update(waves_per_group=4, big_frames=1 << 23,
@@ -647,6 +648,7 @@ def main() -> int:
     ap.add_argument("--queues", type=int, default=1, help="kclique7: DAQ queues (1 = off)")
     ap.add_argument("--kclique-split", default="none", choices=("none", "orient", "pivot"),
                     help="kclique7: bitset candidate subgraphs with cost-threshold splitting")
+    ap.add_argument("--daq-bounds", default="8,32,128", help="kclique7 with --queues: class bounds")
     ap.add_argument("--split-threshold", type=int, default=16,
                     help="kclique7 with --kclique-split: split nodes with more candidates than this")
     args = ap.parse_args()

@@ -833,16 +833,23 @@ GTAP_DEV uint32_t child_class(const Params &p, uint32_t job, uint32_t ckind, con
       return 0;
     }
     if (p.daq_policy == 2 && ckind >= TK_KS_RANGE) {
-      // split k-clique: a vertex by its out-degree, an edge by min(outdeg u,
-      // outdeg v), the bound on its candidate count; ranges, a heavy edge's
-      // search and its branches in the highest class
+      // split k-clique: a vertex by its out-degree; an edge by its candidate
+      // count when its row of the vertex's matrix is built (k >= 4; its
+      // parent forks the edges only then), else by min(outdeg u, outdeg v);
+      // ranges, row tasks, a heavy edge's search and its branches in the
+      // highest class
       if (ckind != TK_KS_EDGE && ckind != TK_KS_VERTEX) return p.Q - 1;
-      const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, job, 0));
-      const int32_t *col = reinterpret_cast<const int32_t *>(job_arg(p, job, 1));
+      const KsJob J = ks_job(p, job);
       const uint32_t u = c.p[0];
-      if (ckind == TK_KS_VERTEX) return bucket_of(p, static_cast<uint32_t>(rp[u + 1] - rp[u]));
-      const int32_t v = col[rp[u] + c.p[1]];
-      const uint32_t du = static_cast<uint32_t>(rp[u + 1] - rp[u]), dv = static_cast<uint32_t>(rp[v + 1] - rp[v]);
+      if (ckind == TK_KS_VERTEX) return bucket_of(p, static_cast<uint32_t>(J.rp[u + 1] - J.rp[u]));
+      if (J.kk >= 2) {
+        const KsMat M = ks_mat(J, u);
+        uint32_t n = 0;
+        for (uint32_t w = 0; w < M.W; ++w) n += __popcll(co_ld64(M.D + static_cast<size_t>(c.p[1]) * M.W + w));
+        return bucket_of(p, n);
+      }
+      const int32_t v = J.col[J.rp[u] + c.p[1]];
+      const uint32_t du = static_cast<uint32_t>(J.rp[u + 1] - J.rp[u]), dv = static_cast<uint32_t>(J.rp[v + 1] - J.rp[v]);
       return bucket_of(p, du < dv ? du : dv);
     }
   }
