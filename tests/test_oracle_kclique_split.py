@@ -99,16 +99,17 @@ def test_split_complete_graph_counts_and_trees(n):
     for k in range(3, min(n, 9) + 1):
         kk = k - 2
         # vertex i has n-1-i out-neighbours; for k >= 4 only vertices with at
-        # least k-1 of them fork, first one row task, then one edge task each
-        if k == 3:
-            base = _range_tasks(0, n, 64) + n + len(edges)
-            cs = [n - 1 - j for i in range(n) for j in range(i + 1, n)]
-        else:
-            live = [i for i in range(n) if n - 1 - i >= k - 1]
-            base = _range_tasks(0, n, 64) + n + 2 * sum(n - 1 - i for i in live)
-            cs = [n - 1 - j for i in live for j in range(i + 1, n)]
+        # least k-1 and more than t of them fork, first one row task, then
+        # one edge task each (the others count in place)
         for alg in ALGS:
             for thr in (0, 3, 1000):
+                if k == 3:
+                    base = _range_tasks(0, n, 64) + n + len(edges)
+                    cs = [n - 1 - j for i in range(n) for j in range(i + 1, n)]
+                else:
+                    live = [i for i in range(n) if n - 1 - i >= k - 1 and n - 1 - i > thr]
+                    base = _range_tasks(0, n, 64) + n + 2 * sum(n - 1 - i for i in live)
+                    cs = [n - 1 - j for i in live for j in range(i + 1, n)]
                 r = oracle.kclique_split(g.row_ptr, g.col, k, threshold=thr, algorithm=alg)
                 assert r.value == math.comb(n, k)
                 # an edge with more than thr candidates hands its search to one
@@ -152,11 +153,16 @@ def test_split_no_split_tree_and_degenerate_cases():
         assert r.tasks == rt + 30 + m and r.aux == 0
         assert r.conts == rt + int((deg > 0).sum())
         for k in (4, 5):
-            # vertices with k-1 or more out-neighbours: row tasks, edge tasks, two resumptions
-            live = deg >= k - 1
+            # every vertex counts in place under a threshold above its out-degree
             r = oracle.kclique_split(g.row_ptr, g.col, k, range_leaf=8, threshold=1000, algorithm=alg)
-            assert r.tasks == rt + 30 + 2 * int(deg[live].sum()) and r.aux == 0
-            assert r.conts == rt + 2 * int(live.sum())
+            assert r.tasks == rt + 30 and r.aux == 0 and r.conts == rt
+            # threshold 2: vertices with k-1 or more (and more than 2) out-neighbours fork
+            # one row task and one edge task per out-neighbour and resume twice; the
+            # rest are heavy edges' hand-offs and split nodes, one resumption each
+            live = (deg >= k - 1) & (deg > 2)
+            r = oracle.kclique_split(g.row_ptr, g.col, k, range_leaf=8, threshold=2, algorithm=alg)
+            extra = r.tasks - (rt + 30 + 2 * int(deg[live].sum()))
+            assert extra >= 0 and r.conts >= rt + 2 * int(live.sum())
         e0 = graphs.oriented_from_edges(12, [], "id")
         assert oracle.kclique_split(e0.row_ptr, e0.col, 4, algorithm=alg).value == 0
         z = graphs.oriented_from_edges(0, [], "id")
