@@ -302,6 +302,50 @@ GTAP_DEV void ks_row(const Params &p, Outcome &o, uint32_t u, uint32_t i) {
   while (cw < W) flush();
 }
 
+// A vertex with d <= threshold out-neighbours (k >= 4): its matrix in private
+// one-word rows (galloping as the row tasks do), then every edge's search in
+// place: edge i's candidates are row i.
+GTAP_DEV int64_t ks_vertex_in_place(const KsJob &J, uint32_t u, uint32_t d) {
+  const int32_t *nu = J.col + J.rp[u];
+  uint64_t A[kcs::kMaxThr], B[kcs::kMaxThr];
+  for (uint32_t i = 0; i < d; ++i) {
+    const int32_t x = nu[i];
+    const int32_t *nx = J.col + J.rp[x];
+    const uint32_t dx = static_cast<uint32_t>(J.rp[x + 1] - J.rp[x]);
+    uint64_t r = 0;
+    if (d <= dx) {
+      uint32_t t = 0;
+      for (uint32_t j = 0; j < d && t < dx; ++j) {
+        t = kcs::gallop(nx, t, dx, nu[j]);
+        if (t < dx && nx[t] == nu[j]) {
+          r |= 1ull << j;
+          ++t;
+        }
+      }
+    } else {
+      uint32_t j = 0;
+      for (uint32_t t = 0; t < dx && j < d; ++t) {
+        j = kcs::gallop(nu, j, d, nx[t]);
+        if (j < d && nu[j] == nx[t]) {
+          r |= 1ull << j;
+          ++j;
+        }
+      }
+    }
+    A[i] = r;
+    B[i] = r;
+  }
+  if (J.pivot)  // both directions
+    for (uint32_t i = 0; i < d; ++i)
+      for (uint64_t t = A[i]; t; t &= t - 1) B[__builtin_ctzll(t)] |= 1ull << i;
+  int64_t total = 0;
+  for (uint32_t i = 0; i < d; ++i) {
+    if (static_cast<uint32_t>(__popcll(A[i])) < J.kk) continue;
+    total += J.pivot ? kcs::sct_count(B, A[i], 0, 0, J.kk) : kcs::dag_count(A, A[i], J.kk);
+  }
+  return total;
+}
+
 // Edge task (u, i): the i-th out-neighbour v of u.  k = 3: |N+(u) /\ N+(v)|.
 // Otherwise its candidates are row i of u's matrix: few -> renumbered into a
 // private one-word matrix and counted in place; more than the threshold ->
@@ -633,6 +677,11 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
         return;
       }
       const KsJob J = ks_job(p, o.job);
+      if (deg <= J.thr) {  // few out-neighbours: the whole vertex in place, one-word rows
+        o.type = OUT_DONE;
+        o.value = ks_vertex_in_place(J, p0, deg);
+        return;
+      }
       if (J.pivot) {  // U is built by atomic ORs: cleared first
         const KsMat M = ks_mat(J, p0);
         for (uint32_t x = 0; x < deg * M.W; ++x) co_st64(M.rows + x, 0ull);
