@@ -102,8 +102,10 @@ typedef struct {
  * bit matrix (one row task per out-neighbour), then forks one edge task per
  * out-neighbour v: the edge's candidates N+(u) /\ N+(v) are row v, and it
  * counts the (k-2)-cliques among them (k = 3: the size of the intersection).
- * gtap_run allocates the job's matrices for the run: sum over those vertices
- * of d * ceil(d/64) * 8 bytes (twice that for pivoting), d = out-degree.
+ * A vertex with at most `threshold` out-neighbours counts all its edges in
+ * place instead.  gtap_run allocates the job's matrices for the run: sum over
+ * the vertices that fork of d * ceil(d/64) * 8 bytes (twice that for
+ * pivoting), d = out-degree.
  * A search node whose candidate set has more than
  * `threshold` members splits into one child task per branch -- per candidate
  * for the orientation algorithm; the pivot and each of its non-neighbours for

@@ -431,14 +431,16 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
           return GTAP_E_HIP;
         for (int32_t v = 0; v < a.n; ++v)
           if (rp[v + 1] < rp[v] || rp[v + 1] - rp[v] > a.max_outdeg) return GTAP_E_INVAL;
-        // k >= 4: a vertex with at least k-1 out-neighbours gets its d x W bit
-        // matrix (two of them for pivoting) in the job's matrix buffer
+        // k >= 4: a vertex that forks row tasks (at least k-1 and more than
+        // threshold out-neighbours; smaller ones count in place) gets its
+        // d x W bit matrix (two of them for pivoting) in the job's buffer
         if (ks_off && a.k >= 4) {
           ks_off->assign(static_cast<size_t>(a.n) + 1, 0);
           const uint64_t mats = a.algorithm == GTAP_KCLIQUE_PIVOT ? 2 : 1;
           for (int32_t v = 0; v < a.n; ++v) {
             const uint64_t d = static_cast<uint64_t>(rp[v + 1] - rp[v]);
-            (*ks_off)[v + 1] = (*ks_off)[v] + (d >= static_cast<uint64_t>(a.k - 1) ? mats * d * ((d + 63) / 64) : 0);
+            const bool forks = d >= static_cast<uint64_t>(a.k - 1) && d > static_cast<uint64_t>(a.threshold);
+            (*ks_off)[v + 1] = (*ks_off)[v] + (forks ? mats * d * ((d + 63) / 64) : 0);
           }
         }
       }

@@ -93,30 +93,54 @@ GTAP_DEV uint32_t uts_children(uint64_t id, uint32_t depth, uint64_t thr, uint32
   return c;
 }
 
-// |C /\ B| for an ascending candidate list C (read coherently: it may be a
-// buffer another wavefront wrote) and an ascending CSR list B (read-only
-// input); writes the intersection coherently if out != 0.
-GTAP_DEV uint32_t intersect_sorted(const int32_t *C, uint32_t nc, const int32_t *B, uint32_t nb,
-                                   int32_t *out) {
-  uint32_t i = 0, j = 0, o = 0;
-  if (nc == 0 || nb == 0) return 0;
-  int32_t x = co_ld32i(C), y = B[0];
-  for (;;) {
-    if (x < y) {
-      if (++i == nc) break;
-      x = co_ld32i(C + i);
-    } else if (x > y) {
-      if (++j == nb) break;
-      y = B[j];
-    } else {
+// First index in the ascending list b[lo, nb) whose element is >= x, by a
+// galloping search (doubling steps from lo, then bisection); kCo: b is read
+// coherently (a buffer another wavefront wrote).
+template <bool kCo>
+GTAP_DEV int32_t ld_list(const int32_t *b, uint32_t i) {
+  if constexpr (kCo) return co_ld32i(b + i);
+  else return b[i];
+}
+template <bool kCo>
+GTAP_DEV uint32_t gallop_list(const int32_t *b, uint32_t lo, uint32_t nb, int32_t x) {
+  if (lo >= nb || ld_list<kCo>(b, lo) >= x) return lo;
+  uint32_t step = 1, prev = lo;
+  while (prev + step < nb && ld_list<kCo>(b, prev + step) < x) {
+    prev += step;
+    step <<= 1;
+  }
+  uint32_t l = prev + 1, h = prev + step < nb ? prev + step : nb;
+  while (l < h) {
+    const uint32_t mid = l + (h - l) / 2;
+    if (ld_list<kCo>(b, mid) < x) l = mid + 1;
+    else h = mid;
+  }
+  return l;
+}
+// Common elements of the ascending lists s (walked) and l (galloped into).
+template <bool kCoS, bool kCoL>
+GTAP_DEV uint32_t isect_gallop(const int32_t *s, uint32_t ns, const int32_t *l, uint32_t nl, int32_t *out) {
+  uint32_t j = 0, o = 0;
+  for (uint32_t i = 0; i < ns && j < nl; ++i) {
+    const int32_t x = ld_list<kCoS>(s, i);
+    j = gallop_list<kCoL>(l, j, nl, x);
+    if (j < nl && ld_list<kCoL>(l, j) == x) {
       if (out) co_st32i(out + o, x);
       ++o;
-      if (++i == nc || ++j == nb) break;
-      x = co_ld32i(C + i);
-      y = B[j];
+      ++j;
     }
   }
   return o;
+}
+
+// |C /\ B| for an ascending candidate list C (read coherently: it may be a
+// buffer another wavefront wrote) and an ascending CSR list B (read-only
+// input); writes the intersection coherently if out != 0.  The shorter list
+// is walked and each of its elements galloped to in the longer one.
+GTAP_DEV uint32_t intersect_sorted(const int32_t *C, uint32_t nc, const int32_t *B, uint32_t nb,
+                                   int32_t *out) {
+  if (nc == 0 || nb == 0) return 0;
+  return nc <= nb ? isect_gallop<true, false>(C, nc, B, nb, out) : isect_gallop<false, true>(B, nb, C, nc, out);
 }
 
 // Job arguments.  Read coherently: while serving, a job slot is rewritten by
