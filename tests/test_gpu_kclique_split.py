@@ -213,3 +213,26 @@ def test_split_with_daq_queues(gtap, alg):
             want = oracle.kclique_split(g.row_ptr, g.col, k, threshold=thr, algorithm=alg)
             assert got == want.value
             assert (st["tasks"], st["conts"]) == (want.tasks, want.conts), (k, thr)
+
+
+@pytest.mark.parametrize("alg", ALGS)
+def test_split_max_outdegree_1024(gtap, alg):
+    """A hub with the largest allowed out-degree (1024: 16-word rows and node
+    sets) over a 40-clique and a sparse remainder: counts and task trees
+    against the oracle, and the closed form C(40, k-1) + C(40, k) + (cliques
+    of the remainder, none here beyond edges and triangles)."""
+    rng = np.random.default_rng(17)
+    n = 1025
+    edges = [(0, v) for v in range(1, n)]
+    edges += [(a, b) for a in range(1, 41) for b in range(a + 1, 41)]
+    edges += [(int(a), int(b)) for a, b in rng.integers(41, n, size=(300, 2)) if a < b]
+    edges = sorted(set(edges))
+    g = graphs.oriented_from_edges(n, edges, "id")
+    assert g.max_outdeg == 1024
+    with make_rt(gtap, g.max_outdeg, big_frames=1 << 20) as rt:
+        for k, thr in ((4, 8), (5, 8), (6, 0), (5, 64)):
+            say(f"split k-clique {alg}: hub of out-degree 1024, k={k} thr={thr}")
+            got, st = run_split(rt, g, k, thr, alg, gtap)
+            want = oracle.kclique_split(g.row_ptr, g.col, k, threshold=thr, algorithm=alg)
+            assert got == want.value == math.comb(40, k - 1) + math.comb(40, k)
+            assert (st["tasks"], st["conts"]) == (want.tasks, want.conts), (k, thr)
