@@ -113,6 +113,20 @@ def cpu_baseline(min_seconds: float = 10.0, max_seconds: float = 30.0) -> dict:
                       f"{el:.1f} s on one host thread"}
 
 
+def kclique_cpu_baseline(g, args, stride: int = 4) -> dict:
+    """The oracle on one host thread over the 7-cliques whose lowest vertex is
+    0 mod `stride` (a vertex sample of the same graph, 10-30 s)."""
+    import oracle
+    alg = "pivot" if args.kclique_split == "pivot" else "orient"
+    thr = args.split_threshold if args.kclique_split != "none" else 64
+    t0 = time.perf_counter()
+    r = oracle.kclique_split_roots(g.row_ptr, g.col, 7, stride, 0, threshold=thr, algorithm=alg)
+    el = time.perf_counter() - t0
+    return {"value": r.value / el, "unit": "k-cliques/s", "cores": 1, "kind": "oracle",
+            "sample": f"the {r.value} 7-cliques whose lowest vertex is 0 mod {stride} ({alg}, threshold {thr}), "
+                      f"{el:.1f} s on one host thread"}
+
+
 def bench_kclique7(args, gtap) -> int:
     """7-cliques of the seeded n=10^6, mean degree 40, exponent 2.1 Chung-Lu graph
     (thread mode; DAQ with 4 candidate-size buckets when --queues 4)."""
@@ -173,6 +187,7 @@ def bench_kclique7(args, gtap) -> int:
            "steps": args.steps, "warmup": args.warmup, "dtype": "int64", "data": "synthetic",
            "config": {"workload": "7-cliques, Chung-Lu n=1e6, mean degree 40, exponent 2.1, cap 0.6, seed 2",
                       "graph_edges": g.m_undirected, "max_outdeg": g.max_outdeg},
+           "cpu_baseline": None if args.no_cpu_baseline else kclique_cpu_baseline(g, args),
            "runtime_counters_per_step": {k: v // args.steps for k, v in tot.items()}}
     rt.close()
     print(json.dumps(out), flush=True)

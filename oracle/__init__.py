@@ -68,6 +68,10 @@ def _load():
     lib.orc_kclique_split.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                       ctypes.c_int64, ctypes.c_int, ctypes.c_int, P(_Counts)]
     lib.orc_kclique_split.restype = ctypes.c_int64
+    lib.orc_kclique_split_roots.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                            ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                            P(_Counts)]
+    lib.orc_kclique_split_roots.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -254,6 +258,22 @@ def kclique_split(row_ptr, col, k: int, range_leaf: int = 64, threshold: int = 3
                                   int(range_leaf), int(threshold), KCLIQUE_ALGORITHMS[algorithm], ctypes.byref(c))
     if v < 0:
         raise ValueError("oracle kclique_split: invalid arguments" if v == -1 else "oracle kclique_split: no memory")
+    return _res(v, c)
+
+
+def kclique_split_roots(row_ptr, col, k: int, stride: int, offset: int = 0, threshold: int = 32,
+                        algorithm: str = "orient") -> OracleResult:
+    """kclique_split restricted to the cliques whose lowest vertex is
+    offset mod stride: a sample of the vertex tasks, for timing."""
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    cl = np.ascontiguousarray(np.asarray(col, dtype=np.int32))
+    n = rp.shape[0] - 1
+    c = _Counts()
+    v = _load().orc_kclique_split_roots(rp.ctypes.data, cl.ctypes.data if cl.size else None, n, int(k),
+                                        int(stride), int(offset), int(threshold), KCLIQUE_ALGORITHMS[algorithm],
+                                        ctypes.byref(c))
+    if v < 0:
+        raise ValueError("oracle kclique_split_roots: invalid arguments" if v == -1 else "no memory")
     return _res(v, c)
 
 

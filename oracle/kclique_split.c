@@ -371,3 +371,21 @@ int64_t orc_kclique_split(const int64_t *row_ptr, const int32_t *col, int64_t n,
     int64_t v = ks_R(&x, 0, n, range_leaf);
     return x.bad ? -2 : v;
 }
+
+/* The same count restricted to the cliques whose lowest vertex v satisfies
+ * v % stride == offset (a sample of vertex tasks for timing; summing over
+ * every offset gives the full count).  Task counts cover those vertex
+ * subtrees only. */
+int64_t orc_kclique_split_roots(const int64_t *row_ptr, const int32_t *col, int64_t n, int k,
+                                int64_t stride, int64_t offset, int threshold, int algorithm,
+                                ks_counts *c)
+{
+    memset(c, 0, sizeof(*c));
+    if (k < 1 || n < 0 || stride < 1 || offset < 0 || offset >= stride || threshold < 0 ||
+        (algorithm != 0 && algorithm != 1))
+        return -1;
+    ks_ctx x = {row_ptr, col, k, k - 2, threshold, algorithm, 0, c, NULL, 0};
+    int64_t sum = 0;
+    for (int64_t v = offset; v < n; v += stride) sum += ks_V(&x, (int32_t)v);
+    return x.bad ? -2 : sum;
+}

@@ -171,3 +171,17 @@ def test_split_no_split_tree_and_degenerate_cases():
             oracle.kclique_split(g.row_ptr, g.col, 0, algorithm=alg)
         with pytest.raises(ValueError):
             oracle.kclique_split(g.row_ptr, g.col, 4, threshold=-1, algorithm=alg)
+
+
+def test_split_root_sample_sums_to_full_count():
+    """The vertex-sample form (cliques whose lowest vertex is offset mod
+    stride) partitions the count."""
+    g = graphs.chung_lu(1500, 18, 2.3, 1.0, 4)
+    for alg in ALGS:
+        for k in (4, 6):
+            full = oracle.kclique_split(g.row_ptr, g.col, k, threshold=8, algorithm=alg).value
+            parts = [oracle.kclique_split_roots(g.row_ptr, g.col, k, 7, o, threshold=8, algorithm=alg).value
+                     for o in range(7)]
+            assert sum(parts) == full and all(p_ >= 0 for p_ in parts)
+    with pytest.raises(ValueError):
+        oracle.kclique_split_roots(g.row_ptr, g.col, 4, 3, 3)
