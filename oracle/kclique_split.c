@@ -18,13 +18,9 @@
  * Task tree (k' = k - 2; t = the split threshold):
  *   R(lo,hi)  vertex range: more than `leaf` vertices -> R(lo,mid), R(mid,hi),
  *             mid = lo + (hi-lo)/2; otherwise one V(v) per vertex.
- *   V(v)      k = 1 -> 1; k = 2 -> |N+(v)|; N+(v) empty -> 0; k = 3 -> one
- *             E(v, w) per w in N+(v).  k >= 4: fewer than k-1 out-neighbours
- *             -> 0; at most t of them -> every edge's search counted in place
- *             (the out-degree bounds every candidate count); otherwise first
- *             one row task per w in N+(v) (it encodes which members of N+(v)
- *             are out-neighbours of w: the vertex's bit matrix), then,
- *             resumed, one E(v, w) per w, then, resumed again, the sum.
+ *   V(v)      k = 1 -> 1; k = 2 -> |N+(v)|; N+(v) empty -> 0; otherwise
+ *             one E(v, w) per w in N+(v) (each task explores one edge), then,
+ *             resumed, the sum.
  *   E(u,v)    C = C(u,v), c = |C|.  k' = 1 -> c; c < k' -> 0; the orientation
  *             algorithm with k' = 2, or c <= t -> the root node of the chosen
  *             algorithm on C, counted in place; otherwise one child H(u,v).
@@ -312,28 +308,9 @@ static int64_t ks_V(ks_ctx *x, int32_t v)
         x->c->leaves++;
         return 1;
     }
-    if (x->k == 2 || nv == 0 || (x->k >= 4 && nv < x->k - 1)) {
+    if (x->k == 2 || nv == 0) {
         x->c->leaves++;
         return x->k == 2 ? nv : 0;
-    }
-    if (x->k >= 4 && nv <= x->thr) {  /* in place: each edge's root node */
-        int64_t sum = 0;
-        for (int64_t i = 0; i < nv; i++) {
-            int64_t nw;
-            const int32_t *ow = ks_out(x, ov[i], &nw);
-            int32_t *C = ks_alloc(x, sizeof(int32_t) * (size_t)(nv < nw ? nv : nw));
-            if (!C) return 0;
-            int64_t c = ks_isect(ov, nv, ow, nw, C);
-            if (c >= x->kk) sum += ks_root(x, C, c, 0);
-            free(C);
-        }
-        x->c->leaves++;
-        return sum;
-    }
-    if (x->k >= 4) {  /* the row tasks, then a resumption */
-        x->c->tasks += nv;
-        x->c->leaves += nv;
-        x->c->conts++;
     }
     int64_t sum = 0;
     for (int64_t i = 0; i < nv; i++) sum += ks_E(x, v, ov[i]);

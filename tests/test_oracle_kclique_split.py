@@ -90,26 +90,19 @@ def _orient_tree(s, l, thr):
 @pytest.mark.parametrize("n", [9, 16, 24])
 def test_split_complete_graph_counts_and_trees(n):
     """K_n oriented by id: C(n, k) cliques; edge (i, j) has the n-1-j later
-    vertices as candidates.  An edge with c > t candidates hands its search to
-    one child task; pivoting on a clique always picks the first candidate and
-    has no non-neighbours, so that child splits into a chain of c - t pivot
-    tasks.  Vertices with fewer than k-1 out-neighbours fork nothing."""
+    vertices as candidates.  Every vertex with out-neighbours forks one edge
+    task per out-neighbour and resumes once.  An edge with c > t candidates
+    hands its search to one child task; pivoting on a clique always picks the
+    first candidate and has no non-neighbours, so that child splits into a
+    chain of c - t pivot tasks."""
     edges = [(i, j) for i in range(n) for j in range(i + 1, n)]
     g = graphs.oriented_from_edges(n, edges, "id")
     for k in range(3, min(n, 9) + 1):
         kk = k - 2
-        # vertex i has n-1-i out-neighbours; for k >= 4 only vertices with at
-        # least k-1 and more than t of them fork, first one row task, then
-        # one edge task each (the others count in place)
         for alg in ALGS:
             for thr in (0, 3, 1000):
-                if k == 3:
-                    base = _range_tasks(0, n, 64) + n + len(edges)
-                    cs = [n - 1 - j for i in range(n) for j in range(i + 1, n)]
-                else:
-                    live = [i for i in range(n) if n - 1 - i >= k - 1 and n - 1 - i > thr]
-                    base = _range_tasks(0, n, 64) + n + 2 * sum(n - 1 - i for i in live)
-                    cs = [n - 1 - j for i in live for j in range(i + 1, n)]
+                base = _range_tasks(0, n, 64) + n + len(edges)
+                cs = [n - 1 - j for i in range(n) for j in range(i + 1, n)]
                 r = oracle.kclique_split(g.row_ptr, g.col, k, threshold=thr, algorithm=alg)
                 assert r.value == math.comb(n, k)
                 # an edge with more than thr candidates hands its search to one
@@ -126,6 +119,9 @@ def test_split_complete_graph_counts_and_trees(n):
                         splits += sp
                 assert r.tasks == base + extra, (k, alg, thr)
                 assert r.aux == splits, (k, alg, thr)
+                # every task with children resumes once: ranges, vertices with
+                # out-neighbours, hand-off edges and split nodes
+                assert r.conts == _range_tasks(0, n, 64) + (n - 1) + len(heavy) + splits, (k, alg, thr)
 
 
 def test_split_matches_plain_recursion_on_chung_lu():
@@ -153,16 +149,17 @@ def test_split_no_split_tree_and_degenerate_cases():
         assert r.tasks == rt + 30 + m and r.aux == 0
         assert r.conts == rt + int((deg > 0).sum())
         for k in (4, 5):
-            # every vertex counts in place under a threshold above its out-degree
+            # no split under a threshold above every out-degree: ranges,
+            # vertices and one task per edge, nothing more
             r = oracle.kclique_split(g.row_ptr, g.col, k, range_leaf=8, threshold=1000, algorithm=alg)
-            assert r.tasks == rt + 30 and r.aux == 0 and r.conts == rt
-            # threshold 2: vertices with k-1 or more (and more than 2) out-neighbours fork
-            # one row task and one edge task per out-neighbour and resume twice; the
-            # rest are heavy edges' hand-offs and split nodes, one resumption each
-            live = (deg >= k - 1) & (deg > 2)
+            assert r.tasks == rt + 30 + m and r.aux == 0
+            assert r.conts == rt + int((deg > 0).sum())
+            # threshold 2: the same tree plus heavy edges' hand-offs and split
+            # nodes, one resumption each
             r = oracle.kclique_split(g.row_ptr, g.col, k, range_leaf=8, threshold=2, algorithm=alg)
-            extra = r.tasks - (rt + 30 + 2 * int(deg[live].sum()))
-            assert extra >= 0 and r.conts >= rt + 2 * int(live.sum())
+            extra = r.tasks - (rt + 30 + m)
+            hand = r.conts - (rt + int((deg > 0).sum())) - r.aux
+            assert 0 <= hand <= extra and (extra == 0) == (hand == 0), (k, alg, extra, hand, r.aux)
         e0 = graphs.oriented_from_edges(12, [], "id")
         assert oracle.kclique_split(e0.row_ptr, e0.col, 4, algorithm=alg).value == 0
         z = graphs.oriented_from_edges(0, [], "id")
