@@ -360,6 +360,9 @@ typedef struct gtap_stats {
     uint64_t idle_cycles;    /* shader-clock cycles in iterations that found none */
     uint64_t admitted;       /* serving: jobs admitted from the ring           */
     uint64_t local_pushed;   /* children kept in a wavefront's LDS stack       */
+    uint64_t atomics;        /* thread mode: device-scope read-modify-writes the
+                                scheduler issued (join updates, deque counts,
+                                claims and thieves' locks; one per lane)      */
     double kernel_ms;        /* device time of the last run's persistent kernel */
     int32_t num_waves;
     int32_t waves_per_group;
@@ -483,6 +486,62 @@ typedef struct {
  * own failure. */
 int gtap_autotune(const gtap_config *base, const gtap_trace_job *calib, size_t n,
                   const gtap_tune_space *space, gtap_config *best, gtap_tune_report *report);
+
+/* ---- platform probes ------------------------------------------------------------ */
+/* Not in the paper: measurements of the two platform properties the runtime's
+ * design rests on (its hand-offs use relaxed device-scope accesses ordered by
+ * waiting for completion instead of release/acquire fences, Sec. 5.1.3's
+ * publication fence and count update).  Both launch on `stream` (NULL = the
+ * default stream), wait for it, and use only the caller's device buffer. */
+
+/* Device-scope 64-bit fetch-add throughput.  `blocks` workgroups of 256
+ * threads; every issuing lane performs `iters` RMWs with return:
+ *   GTAP_PROBE_DISTINCT  every lane on its own 64-byte line (like the join
+ *                        words of different frames); words >= blocks*256*8
+ *   GTAP_PROBE_PER_WAVE  lane 0 of each wavefront on that wavefront's word
+ *                        (like a deque count); words >= blocks*4*16
+ *   GTAP_PROBE_ONE_WORD  lane 0 of every wavefront on one word; words >= 1
+ * words_dev: caller-owned uint64 device array of `words` entries (contents
+ * overwritten).  *rmw_per_s receives RMWs / kernel time, *ms the kernel time.
+ * Errors: GTAP_E_INVAL (mode, sizes, iters outside 1..65536, blocks outside
+ * 1..65536), GTAP_E_HIP. */
+enum gtap_probe_mode { GTAP_PROBE_DISTINCT = 0, GTAP_PROBE_PER_WAVE = 1, GTAP_PROBE_ONE_WORD = 2 };
+int gtap_probe_atomics(int32_t mode, uint32_t blocks, uint32_t iters, uint64_t *words_dev, uint64_t words,
+                       void *stream, double *rmw_per_s, double *ms);
+
+/* Litmus tests between the two one-wavefront workgroups of each of `pairs`
+ * pairs (workgroups 2p and 2p+1, which the dispatcher places on different
+ * XCDs; the XCC ids read by each workgroup are checked), 64 lane instances
+ * per pair, each on its own 128-byte lines, with relaxed device-scope stores
+ * and loads and, when `ordered`, a wait for completion between the two
+ * accesses of each thread:
+ *   test 0, message passing: the writer stores data = k then flag = k for
+ *     k = 1..rounds; the reader, 4*rounds times, loads flag then data and
+ *     counts data < flag (stale: forbidden when ordered);
+ *   test 1, store buffering: in round r = 1..rounds, A stores x = r then
+ *     loads y, B stores y = r then loads x; both loads seeing a value below r
+ *     is forbidden when ordered.
+ * buf_dev: caller-owned device memory of at least
+ * pairs * (16384 + 512 * rounds) + 16384 bytes.  No wait in the
+ * kernels depends on the other workgroup: every run ends.
+ * Errors: GTAP_E_INVAL (test, pairs outside 1..1024, rounds outside
+ * 1..65536, null pointers), GTAP_E_NOMEM (buffer too small), GTAP_E_HIP. */
+typedef struct {
+    uint64_t instances;       /* lane pairs tested (64 per workgroup pair)     */
+    uint64_t mp_reads;        /* message passing: flag-then-data reads         */
+    uint64_t mp_stale;        /*   of those, data older than the flag          */
+    uint64_t mp_overlap;      /*   of those, a flag strictly inside (0, rounds):
+                                   reader and writer ran at the same time     */
+    uint64_t sb_rounds;       /* store buffering: rounds over all instances     */
+    uint64_t sb_both_new;     /*   both loads saw the other's round-r store     */
+    uint64_t sb_a_new_only;
+    uint64_t sb_b_new_only;
+    uint64_t sb_both_old;     /*   neither did (forbidden when ordered)         */
+    int32_t pairs;
+    int32_t pairs_on_distinct_xcds;
+} gtap_litmus_result;
+int gtap_litmus(int32_t test, int32_t ordered, uint32_t pairs, uint32_t rounds, void *buf_dev, uint64_t buf_bytes,
+                void *stream, gtap_litmus_result *out);
 
 #ifdef __cplusplus
 }

@@ -105,6 +105,7 @@ enum StatIdx : uint32_t {
   ST_TASKS = 0, ST_CONTS, ST_SPAWNS, ST_PUSHED, ST_PUSH_BATCHES, ST_POPPED,
   ST_POP_BATCHES, ST_STOLEN, ST_STEAL_BATCHES, ST_STEAL_ATTEMPTS, ST_ITERS,
   ST_IDLE, ST_SPILLS, ST_REFILLS, ST_BUSY_CYCLES, ST_IDLE_CYCLES, ST_ADMITTED, ST_LOCAL,
+  ST_RMW,  // device-scope read-modify-writes issued by the scheduler (one per lane)
   ST_COUNT
 };
 

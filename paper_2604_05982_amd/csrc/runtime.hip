@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -22,6 +23,7 @@
 #include "fmm_lists.h"
 #include "kclique_bits.h"
 #include "layout.h"
+#include "probes.h"
 #include "sched_block.h"
 #include "sched_thread.h"
 
@@ -192,6 +194,52 @@ __global__ void reset_kernel(Params p, uint32_t ndeques) {
   }
 }
 
+// Kernel parameters of a batch run whose workspace starts at `ws` and is
+// laid out by L; returns the device wall-clock rate (kHz) the watchdog uses.
+int fill_params(const gtap_config &cfg, uint32_t nw, const Layout &L, char *ws, Params &p) {
+  p = Params{};
+  p.ctl = reinterpret_cast<Control *>(ws + L.ctl);
+  p.jobs = reinterpret_cast<JobSlot *>(ws + L.jobs);
+  p.njobs = 0;
+  p.nwaves = nw;
+  p.dq = reinterpret_cast<DequeMeta *>(ws + L.dq);
+  p.rings = reinterpret_cast<uint32_t *>(ws + L.rings);
+  p.cap = cfg.deque_capacity;
+  p.Q = static_cast<uint32_t>(cfg.num_queues);
+  p.frames_s = reinterpret_cast<uint32_t *>(ws + L.frames_s);
+  p.nframes_s = static_cast<uint32_t>(cfg.small_frames);
+  p.frames_b = reinterpret_cast<uint32_t *>(ws + L.frames_b);
+  p.nframes_b = static_cast<uint32_t>(cfg.big_frames);
+  p.stride_b = L.stride_b;
+  p.big_ints = cfg.big_frame_ints;
+  p.bins_s = reinterpret_cast<DepotBin *>(ws + L.bins_s);
+  p.store_s = reinterpret_cast<uint32_t *>(ws + L.store_s);
+  p.bincap_s = L.bincap_s;
+  p.bins_b = reinterpret_cast<DepotBin *>(ws + L.bins_b);
+  p.store_b = reinterpret_cast<uint32_t *>(ws + L.store_b);
+  p.bincap_b = L.bincap_b;
+  p.steal_below = cfg.steal_below;
+  p.steal_probes = cfg.steal_probes;
+  p.steal_div = cfg.steal_div;
+  p.daq_policy = static_cast<uint32_t>(cfg.daq_policy);
+  for (uint32_t i = 0; i < kMaxQueues - 1; ++i) p.daq_bounds[i] = cfg.daq_bounds[i];
+  const uint32_t fl = cfg.flags;
+  p.sched = (fl & GTAP_FLAG_SCHED_CENTRAL)       ? kSchedCentral
+            : (fl & GTAP_FLAG_SCHED_SINGLE)      ? kSchedSingle
+            : (fl & GTAP_FLAG_NO_PRIVATE_STACK) ? kSchedBatchedNoLocal
+                                                 : kSchedBatched;
+  p.ccap = L.ccap;
+  p.cq = p.ccap ? reinterpret_cast<CentralQueue *>(ws + L.cq) : nullptr;
+  p.cring = p.ccap ? reinterpret_cast<uint64_t *>(ws + L.cring) : nullptr;
+  int dev = 0, rate_khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
+    rate_khz = 100000;  // gfx9 constant clock: 100 MHz
+  const uint32_t tmo = cfg.timeout_ms ? cfg.timeout_ms : 120000;
+  p.timeout_ticks = static_cast<uint64_t>(tmo) * static_cast<uint64_t>(rate_khz);
+  return rate_khz;
+}
+
 }  // namespace
 
 struct gtap_ctx {
@@ -297,46 +345,8 @@ int gtap_init(const gtap_config *cfg, gtap_ctx **out) {
     gtap_finalize(c);
     return GTAP_E_HIP;
   }
-  Params &p = c->params;
-  p.ctl = reinterpret_cast<Control *>(c->ws + c->lay.ctl);
-  p.jobs = reinterpret_cast<JobSlot *>(c->ws + c->lay.jobs);
-  p.njobs = 0;
-  p.nwaves = nw;
-  p.dq = reinterpret_cast<DequeMeta *>(c->ws + c->lay.dq);
-  p.rings = reinterpret_cast<uint32_t *>(c->ws + c->lay.rings);
-  p.cap = c->cfg.deque_capacity;
-  p.Q = static_cast<uint32_t>(c->cfg.num_queues);
-  p.frames_s = reinterpret_cast<uint32_t *>(c->ws + c->lay.frames_s);
-  p.nframes_s = static_cast<uint32_t>(c->cfg.small_frames);
-  p.frames_b = reinterpret_cast<uint32_t *>(c->ws + c->lay.frames_b);
-  p.nframes_b = static_cast<uint32_t>(c->cfg.big_frames);
-  p.stride_b = c->lay.stride_b;
-  p.big_ints = c->cfg.big_frame_ints;
-  p.bins_s = reinterpret_cast<DepotBin *>(c->ws + c->lay.bins_s);
-  p.store_s = reinterpret_cast<uint32_t *>(c->ws + c->lay.store_s);
-  p.bincap_s = c->lay.bincap_s;
-  p.bins_b = reinterpret_cast<DepotBin *>(c->ws + c->lay.bins_b);
-  p.store_b = reinterpret_cast<uint32_t *>(c->ws + c->lay.store_b);
-  p.bincap_b = c->lay.bincap_b;
-  p.steal_below = c->cfg.steal_below;
-  p.steal_probes = c->cfg.steal_probes;
-  p.steal_div = c->cfg.steal_div;
-  p.daq_policy = static_cast<uint32_t>(c->cfg.daq_policy);
-  for (uint32_t i = 0; i < kMaxQueues - 1; ++i) p.daq_bounds[i] = c->cfg.daq_bounds[i];
-  const uint32_t fl = c->cfg.flags;
-  p.sched = (fl & GTAP_FLAG_SCHED_CENTRAL)       ? kSchedCentral
-            : (fl & GTAP_FLAG_SCHED_SINGLE)      ? kSchedSingle
-            : (fl & GTAP_FLAG_NO_PRIVATE_STACK) ? kSchedBatchedNoLocal
-                                                 : kSchedBatched;
-  p.ccap = c->lay.ccap;
-  p.cq = p.ccap ? reinterpret_cast<CentralQueue *>(c->ws + c->lay.cq) : nullptr;
-  p.cring = p.ccap ? reinterpret_cast<uint64_t *>(c->ws + c->lay.cring) : nullptr;
-  int dev = 0, rate_khz = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
-    rate_khz = 100000;  // gfx9 constant clock: 100 MHz
+  const int rate_khz = fill_params(c->cfg, nw, c->lay, c->ws, c->params);
   c->clock_khz = static_cast<uint32_t>(rate_khz);
-  p.timeout_ticks = static_cast<uint64_t>(c->cfg.timeout_ms) * static_cast<uint64_t>(rate_khz);
   c->stats.num_waves = static_cast<int32_t>(nw);
   c->stats.waves_per_group = c->cfg.waves_per_group;
   c->stats.num_queues = c->cfg.num_queues;
@@ -352,12 +362,12 @@ extern "C" int32_t gtap_kclique_split_buffer_ints(int32_t max_outdeg) {
 }
 
 // Validate a root task's arguments and pack them into a job slot.
-static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t args_bytes, JobSlot &J,
-                    std::vector<uint64_t> *ks_off = nullptr) {
+static int pack_job(const gtap_config &cfg, hipStream_t stream, int32_t kind, const void *args,
+                    size_t args_bytes, JobSlot &J, std::vector<uint64_t> *ks_off = nullptr) {
   if (!args) return GTAP_E_INVAL;
   std::memset(&J, 0, sizeof(J));
   J.kind = static_cast<uint32_t>(kind);
-  const bool block = c->cfg.mode == GTAP_MODE_BLOCK;
+  const bool block = cfg.mode == GTAP_MODE_BLOCK;
   if (block && kind != GTAP_KIND_FIB && kind != GTAP_KIND_UTS && kind != GTAP_KIND_FMM) return GTAP_E_INVAL;
   switch (kind) {
     case GTAP_KIND_FIB: {
@@ -397,8 +407,8 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
         return GTAP_E_INVAL;
       if (a.n > 0 && (!a.row_ptr_dev || !a.col_dev)) return GTAP_E_INVAL;
       // candidate tasks at level >= 2 keep C' in a big frame (k >= 4)
-      if (a.k >= 4 && static_cast<uint32_t>(a.max_outdeg) > c->cfg.big_frame_ints) return GTAP_E_INVAL;
-      if (a.k >= 4 && c->cfg.big_frames == 0) return GTAP_E_INVAL;
+      if (a.k >= 4 && static_cast<uint32_t>(a.max_outdeg) > cfg.big_frame_ints) return GTAP_E_INVAL;
+      if (a.k >= 4 && cfg.big_frames == 0) return GTAP_E_INVAL;
       J.a[0] = reinterpret_cast<uint64_t>(a.row_ptr_dev);
       J.a[1] = reinterpret_cast<uint64_t>(a.col_dev);
       J.a[2] = static_cast<uint64_t>(a.n);
@@ -411,7 +421,7 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
       if (args_bytes != sizeof(gtap_kclique_split_args)) return GTAP_E_INVAL;
       gtap_kclique_split_args a;
       std::memcpy(&a, args, sizeof(a));
-      if (block || c->cfg.waves_per_group != 4 || c->cfg.flags != 0) return GTAP_E_INVAL;
+      if (block || cfg.waves_per_group != 4 || cfg.flags != 0) return GTAP_E_INVAL;
       if (a.n < 0 || a.k < 1 || a.k > static_cast<int32_t>(kcs::kMaxK) || a.range_leaf < 1 ||
           static_cast<uint32_t>(a.range_leaf) > kMaxChildren || a.max_outdeg < 0 ||
           a.max_outdeg > static_cast<int32_t>(kcs::kMaxW * 64) || a.threshold < 0 ||
@@ -419,15 +429,15 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
           (a.algorithm != GTAP_KCLIQUE_ORIENT && a.algorithm != GTAP_KCLIQUE_PIVOT))
         return GTAP_E_INVAL;
       if (a.n > 0 && (!a.row_ptr_dev || !a.col_dev)) return GTAP_E_INVAL;
-      if (a.k >= 4 && (c->cfg.big_frames == 0 ||
-                       kcs::buffer_ints(static_cast<uint32_t>(a.max_outdeg)) > c->cfg.big_frame_ints))
+      if (a.k >= 4 && (cfg.big_frames == 0 ||
+                       kcs::buffer_ints(static_cast<uint32_t>(a.max_outdeg)) > cfg.big_frame_ints))
         return GTAP_E_INVAL;
       // the frame buffers are sized from max_outdeg: check it against the graph
       if (a.n > 0) {
         std::vector<int32_t> rp(static_cast<size_t>(a.n) + 1);
         if (hipMemcpyAsync(rp.data(), a.row_ptr_dev, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
-                           c->stream) != hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess)
+                           stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
           return GTAP_E_HIP;
         for (int32_t v = 0; v < a.n; ++v)
           if (rp[v + 1] < rp[v] || rp[v + 1] - rp[v] > a.max_outdeg) return GTAP_E_INVAL;
@@ -457,7 +467,7 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
       if (args_bytes != sizeof(gtap_cilksort_args)) return GTAP_E_INVAL;
       gtap_cilksort_args a;
       std::memcpy(&a, args, sizeof(a));
-      if (block || c->cfg.waves_per_group != 4 || c->cfg.flags != 0) return GTAP_E_INVAL;
+      if (block || cfg.waves_per_group != 4 || cfg.flags != 0) return GTAP_E_INVAL;
       if (a.n < 0 || a.n >= (1ll << 29) || a.sort_cutoff < 1 || a.sort_cutoff > 64 || a.merge_cutoff < 2 ||
           a.merge_cutoff > (1 << 20) || (a.n > 0 && (!a.keys_dev || !a.tmp_dev)))
         return GTAP_E_INVAL;
@@ -479,7 +489,7 @@ static int pack_job(const gtap_ctx *c, int32_t kind, const void *args, size_t ar
       // per group, without the comparison variants)
       if (block ? a.traversal != GTAP_FMM_TASKS
                 : (a.traversal != GTAP_FMM_LISTS && a.traversal != GTAP_FMM_WORKLIST) ||
-                      c->cfg.waves_per_group != 4 || c->cfg.flags != 0)
+                      cfg.waves_per_group != 4 || cfg.flags != 0)
         return GTAP_E_INVAL;
       return GTAP_OK;  // the device descriptor is built by gtap_run
     }
@@ -494,7 +504,7 @@ extern "C" int gtap_submit(gtap_ctx *c, int32_t kind, const void *args, size_t a
   if (c->pending.size() >= c->cfg.max_jobs) return GTAP_E_FULL;
   JobSlot J;
   std::vector<uint64_t> ks_off;
-  const int rc = pack_job(c, kind, args, args_bytes, J, &ks_off);
+  const int rc = pack_job(c->cfg, c->stream, kind, args, args_bytes, J, &ks_off);
   if (rc) return rc;
   if (c->pending.empty()) {
     c->pending_first = c->next_job_id;
@@ -536,6 +546,7 @@ static int record_run(gtap_ctx *c, const Control &ctl, float ms) {
   s.idle_cycles = ctl.stats[ST_IDLE_CYCLES];
   s.admitted = ctl.stats[ST_ADMITTED];
   s.local_pushed = ctl.stats[ST_LOCAL];
+  s.atomics = ctl.stats[ST_RMW];
   s.kernel_ms = ms;
   if (ctl.error != 0) {
     c->err.code = ctl.error;
@@ -1184,7 +1195,7 @@ int gtap_serve_submit(gtap_ctx *c, int32_t kind, const void *args, size_t args_b
   // no split k-clique search
   if (kind == GTAP_KIND_FMM || kind == GTAP_KIND_CILKSORT || kind == GTAP_KIND_KCLIQUE_SPLIT) return GTAP_E_INVAL;
   JobSlot J;
-  const int rc = pack_job(c, kind, args, args_bytes, J);
+  const int rc = pack_job(c->cfg, c->stream, kind, args, args_bytes, J);
   if (rc) return rc;
   const uint64_t t = c->next_ticket;
   const uint64_t R = c->params.ring_cap;
@@ -1504,3 +1515,110 @@ const char *gtap_status_string(int32_t s) {
 }
 
 }  // extern "C"
+
+// ---- platform probes ----------------------------------------------------------
+namespace {
+
+struct ProbeEvents {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~ProbeEvents() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  bool make() { return hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess; }
+};
+
+}  // namespace
+
+extern "C" int gtap_probe_atomics(int32_t mode, uint32_t blocks, uint32_t iters, uint64_t *words_dev,
+                                  uint64_t words, void *stream_v, double *rmw_per_s, double *ms_out) {
+  if (!words_dev || !rmw_per_s || blocks < 1 || blocks > 65536 || iters < 1 || iters > 65536) return GTAP_E_INVAL;
+  const uint64_t need = mode == GTAP_PROBE_DISTINCT   ? static_cast<uint64_t>(blocks) * 256 * 8
+                        : mode == GTAP_PROBE_PER_WAVE ? static_cast<uint64_t>(blocks) * 4 * 16
+                        : mode == GTAP_PROBE_ONE_WORD ? 1
+                                                      : 0;
+  if (need == 0 || words < need + 1) return GTAP_E_INVAL;  // one more word: the sink
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  ProbeEvents ev;
+  if (!ev.make()) return GTAP_E_HIP;
+  if (hipMemsetAsync(words_dev, 0, (need + 1) * sizeof(uint64_t), stream) != hipSuccess) return GTAP_E_HIP;
+  if (hipEventRecord(ev.a, stream) != hipSuccess) return GTAP_E_HIP;
+  hipLaunchKernelGGL(probe::atomic_probe_kernel, dim3(blocks), dim3(256), 0, stream, words_dev,
+                     static_cast<uint32_t>(mode), iters, words_dev + need);
+  if (hipGetLastError() != hipSuccess || hipEventRecord(ev.b, stream) != hipSuccess ||
+      hipEventSynchronize(ev.b) != hipSuccess)
+    return GTAP_E_HIP;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, ev.a, ev.b) != hipSuccess || ms <= 0.f) return GTAP_E_HIP;
+  const double lanes = mode == GTAP_PROBE_DISTINCT ? 256.0 * blocks : 4.0 * blocks;
+  *rmw_per_s = lanes * iters / (ms * 1e-3);
+  if (ms_out) *ms_out = ms;
+  return GTAP_OK;
+}
+
+extern "C" int gtap_litmus(int32_t test, int32_t ordered, uint32_t pairs, uint32_t rounds, void *buf_dev,
+                           uint64_t buf_bytes, void *stream_v, gtap_litmus_result *out) {
+  if ((test != 0 && test != 1) || pairs < 1 || pairs > 1024 || rounds < 1 || rounds > 65536 || !buf_dev || !out)
+    return GTAP_E_INVAL;
+  const uint64_t inst = static_cast<uint64_t>(pairs) * kWave;
+  const uint64_t need = static_cast<uint64_t>(pairs) * (16384 + 512ull * rounds) + 16384;
+  if (buf_bytes < need) return GTAP_E_NOMEM;
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  char *b = static_cast<char *>(buf_dev);
+  uint32_t *cells = reinterpret_cast<uint32_t *>(b);                       // inst * 256 B
+  uint32_t *xcc = reinterpret_cast<uint32_t *>(b + inst * 256);            // 2 * pairs words
+  unsigned long long *counts = reinterpret_cast<unsigned long long *>(b + inst * 256 + 8192);
+  uint32_t *res = reinterpret_cast<uint32_t *>(b + inst * 256 + 8192 + 64);  // MP: 2 * inst; SB: 2 * inst * rounds
+  const size_t clear = static_cast<size_t>(inst * 256 + 8192 + 64);
+  if (hipMemsetAsync(b, 0, clear, stream) != hipSuccess) return GTAP_E_HIP;
+  std::memset(out, 0, sizeof(*out));
+  out->instances = inst;
+  out->pairs = static_cast<int32_t>(pairs);
+  const uint32_t reads = rounds * 4;
+  if (test == 0) {
+    uint32_t *stale = res, *mid = res + inst;
+    if (ordered)
+      hipLaunchKernelGGL(probe::litmus_mp_kernel<true>, dim3(2 * pairs), dim3(64), 0, stream, cells, rounds, reads,
+                         stale, mid, xcc);
+    else
+      hipLaunchKernelGGL(probe::litmus_mp_kernel<false>, dim3(2 * pairs), dim3(64), 0, stream, cells, rounds, reads,
+                         stale, mid, xcc);
+    if (hipGetLastError() != hipSuccess) return GTAP_E_HIP;
+    std::vector<uint32_t> h(2 * inst);
+    if (hipMemcpyAsync(h.data(), res, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, stream) != hipSuccess)
+      return GTAP_E_HIP;
+    std::vector<uint32_t> hx(2 * pairs);
+    if (hipMemcpyAsync(hx.data(), xcc, hx.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return GTAP_E_HIP;
+    for (uint64_t i = 0; i < inst; ++i) {
+      out->mp_stale += h[i];
+      out->mp_overlap += h[inst + i];
+    }
+    out->mp_reads = inst * reads;
+    for (uint32_t q = 0; q < pairs; ++q) out->pairs_on_distinct_xcds += (hx[2 * q] & 15u) != (hx[2 * q + 1] & 15u);
+    return GTAP_OK;
+  }
+  if (ordered)
+    hipLaunchKernelGGL(probe::litmus_sb_kernel<true>, dim3(2 * pairs), dim3(64), 0, stream, cells, rounds, res, xcc);
+  else
+    hipLaunchKernelGGL(probe::litmus_sb_kernel<false>, dim3(2 * pairs), dim3(64), 0, stream, cells, rounds, res, xcc);
+  if (hipGetLastError() != hipSuccess) return GTAP_E_HIP;
+  const uint64_t total = inst * rounds;
+  hipLaunchKernelGGL(probe::litmus_sb_count_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0,
+                     stream, res, rounds, static_cast<uint32_t>(inst), counts);
+  if (hipGetLastError() != hipSuccess) return GTAP_E_HIP;
+  unsigned long long hc[4] = {0, 0, 0, 0};
+  std::vector<uint32_t> hx(2 * pairs);
+  if (hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(hx.data(), xcc, hx.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return GTAP_E_HIP;
+  out->sb_rounds = total;
+  out->sb_both_new = hc[0];
+  out->sb_a_new_only = hc[1];
+  out->sb_b_new_only = hc[2];
+  out->sb_both_old = hc[3];
+  for (uint32_t q = 0; q < pairs; ++q) out->pairs_on_distinct_xcds += (hx[2 * q] & 15u) != (hx[2 * q + 1] & 15u);
+  return GTAP_OK;
+}

@@ -311,6 +311,7 @@ GTAP_DEV uint32_t pop_batch(const Params &p, WaveLds &L, uint32_t me, uint32_t q
         break;
       }
       const int32_t take = c < want ? c : want;
+      wc.add(ST_RMW, 1);
       if (cas_relaxed(&m->count, &c, c - take)) {
         claim = take;
         drained = (take == c) ? 1u : 0u;
@@ -373,12 +374,14 @@ GTAP_DEV uint32_t steal_batch(const Params &p, uint32_t me, uint32_t &rng, uint3
   uint32_t h = 0;
   if (ln == 0) {
     int32_t z = 0;
+    wc.add(ST_RMW, 1);
     if (cas_relaxed(&m->lock, &z, 1)) {
       int32_t cc = static_cast<int32_t>(key >> 6);
       h = ld_relaxed(&m->head);  // stable while we hold the lock
       while (cc > 0) {
         int32_t take = (cc + static_cast<int32_t>(p.steal_div) - 1) / static_cast<int32_t>(p.steal_div);
         take = take < want ? take : want;
+        wc.add(ST_RMW, 1);
         if (cas_relaxed(&m->count, &cc, cc - take)) {
           claim = take;
           break;
@@ -480,6 +483,7 @@ GTAP_DEV bool push_batch(const Params &p, WaveLds &L, uint32_t me, uint32_t q, u
   drain();  // slots (and the frames they name) complete before count rises
   if (ln == 0) fetch_add_relaxed(&deque_meta(p, me, q)->count, static_cast<int32_t>(n));
   wave_sync();
+  wc.add(ST_RMW, 1);
   wc.add(ST_PUSHED, n);
   wc.add(ST_PUSH_BATCHES, 1);
   return true;
@@ -1063,10 +1067,12 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     }
     const int64_t lim = static_cast<int64_t>(1) << kSmallValueBits;
     const bool big_val = tail && (run_val >= lim || run_val <= -lim);
-    if (ballot(big_val)) {
+    const uint64_t big_lanes = ballot(big_val);
+    if (big_lanes) {
       if (big_val) fetch_add_relaxed(bigacc_ptr(frame_ptr(p, o.parent)), run_val);
       drain();  // the large result is in place before the count can reach zero
     }
+    wc.add(ST_RMW, static_cast<uint32_t>(__popcll(ballot(tail))) + static_cast<uint32_t>(__popcll(big_lanes)));
     int64_t join_old = 0;
     if (tail) {
       const int64_t delta = (big_val ? 0 : run_val * (static_cast<int64_t>(1) << kJoinBits)) -
@@ -1336,9 +1342,11 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       const uint32_t n = (qq < p.Q) ? (use_local ? nglob : L.qn[qq] - (qq == R ? keep : 0u)) : 0u;
       // frames and ring slots written this iteration are complete before any
       // of them is published
-      if (ballot(n > 0) != 0ull) drain();
+      const uint64_t pushing = ballot(n > 0);
+      if (pushing != 0ull) drain();
       if (n > 0)
         fetch_add_relaxed(kCentral ? &p.cq->count : &deque_meta(p, me, qq)->count, static_cast<int32_t>(n));
+      wc.add(ST_RMW, static_cast<uint32_t>(__popcll(pushing)));
       wave_sync();
       if (n > 0) {
         L.tail[qq] += n;

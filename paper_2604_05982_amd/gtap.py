@@ -140,7 +140,7 @@ class gtap_stats(ctypes.Structure):
         "tasks", "conts", "spawns", "pushed", "push_batches", "popped", "pop_batches",
         "stolen", "steal_batches", "steal_attempts", "iterations", "idle_iterations",
         "small_frames_touched", "big_frames_touched", "depot_spills", "depot_refills",
-        "busy_cycles", "idle_cycles", "admitted", "local_pushed")] + [
+        "busy_cycles", "idle_cycles", "admitted", "local_pushed", "atomics")] + [
         ("kernel_ms", ctypes.c_double),
         ("num_waves", ctypes.c_int32),
         ("waves_per_group", ctypes.c_int32),
@@ -173,6 +173,15 @@ class gtap_tune_report(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int32), ("failed", ctypes.c_int32), ("best_ms", ctypes.c_double),
                 ("base_ms", ctypes.c_double), ("small_frames_touched", ctypes.c_uint64),
                 ("big_frames_touched", ctypes.c_uint64)]
+
+
+class gtap_litmus_result(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("instances", "mp_reads", "mp_stale", "mp_overlap", "sb_rounds",
+                                                "sb_both_new", "sb_a_new_only", "sb_b_new_only", "sb_both_old")] + \
+               [("pairs", ctypes.c_int32), ("pairs_on_distinct_xcds", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class gtap_error_report(ctypes.Structure):
@@ -216,10 +225,14 @@ def _load() -> ctypes.CDLL:
     lib.gtap_trace_run_plain.argtypes = [vp, P(gtap_trace_job), ctypes.c_size_t, P(gtap_trace_result)]
     lib.gtap_autotune.argtypes = [P(gtap_config), P(gtap_trace_job), ctypes.c_size_t, P(gtap_tune_space),
                                   P(gtap_config), P(gtap_tune_report)]
+    lib.gtap_probe_atomics.argtypes = [ctypes.c_int32, u32, u32, vp, u64, vp, P(ctypes.c_double),
+                                       P(ctypes.c_double)]
+    lib.gtap_litmus.argtypes = [ctypes.c_int32, ctypes.c_int32, u32, u32, vp, u64, vp, P(gtap_litmus_result)]
     for fn in ("gtap_workspace_size", "gtap_init", "gtap_submit", "gtap_run", "gtap_result",
                "gtap_finalize", "gtap_stats_get", "gtap_last_error", "gtap_serve_start",
                "gtap_serve_submit", "gtap_serve_poll", "gtap_serve_stop", "gtap_trace_run",
-               "gtap_trace_run_plain", "gtap_autotune"):
+               "gtap_trace_run_plain", "gtap_autotune", "gtap_probe_atomics",
+               "gtap_litmus"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -231,7 +244,7 @@ EXPORTED = ("gtap_config_default", "gtap_workspace_size", "gtap_init", "gtap_sub
             "gtap_result", "gtap_finalize", "gtap_stats_get", "gtap_last_error",
             "gtap_status_string", "gtap_serve_start", "gtap_serve_submit", "gtap_serve_poll",
             "gtap_serve_stop", "gtap_trace_run", "gtap_trace_run_plain", "gtap_autotune",
-            "gtap_kclique_split_buffer_ints")
+            "gtap_kclique_split_buffer_ints", "gtap_probe_atomics", "gtap_litmus")
 
 
 class GtapError(RuntimeError):
@@ -369,6 +382,32 @@ def gtap_autotune(base: "gtap_config", jobs, space: "gtap_tune_space"):
     if rc != GTAP_OK:
         raise GtapError(rc, "gtap_autotune")
     return best, {f: getattr(rep, f) for f, _ in rep._fields_}
+
+
+GTAP_PROBE_DISTINCT = 0
+GTAP_PROBE_PER_WAVE = 1
+GTAP_PROBE_ONE_WORD = 2
+
+
+def gtap_probe_atomics(mode: int, blocks: int, iters: int, words_dev_ptr: int, words: int, stream=None):
+    """(device-scope RMWs per second, kernel ms) of the atomic-throughput probe."""
+    rate, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = _lib.gtap_probe_atomics(int(mode), int(blocks), int(iters), ctypes.c_void_p(int(words_dev_ptr)),
+                                 int(words), stream, ctypes.byref(rate), ctypes.byref(ms))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_probe_atomics")
+    return rate.value, ms.value
+
+
+def gtap_litmus(test: int, ordered: bool, pairs: int, rounds: int, buf_dev_ptr: int, buf_bytes: int,
+                stream=None) -> dict:
+    """Message-passing (test 0) or store-buffering (test 1) litmus counts."""
+    out = gtap_litmus_result()
+    rc = _lib.gtap_litmus(int(test), int(bool(ordered)), int(pairs), int(rounds), ctypes.c_void_p(int(buf_dev_ptr)),
+                          int(buf_bytes), stream, ctypes.byref(out))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_litmus")
+    return out.as_dict()
 
 
 def tune_space(num_queues=(1,), waves_per_group=(4,), num_waves=(0,), bounds=(), daq_policy=0,

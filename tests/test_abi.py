@@ -41,7 +41,7 @@ def test_struct_layout_matches_header(tmp_path):
                gtap.gtap_kclique_args, gtap.gtap_kclique_split_args, gtap.gtap_fmm_args, gtap.gtap_fmm_result,
                gtap.gtap_cilksort_args, gtap.gtap_stats,
                gtap.gtap_error_report, gtap.gtap_trace_job, gtap.gtap_trace_result, gtap.gtap_tune_space,
-               gtap.gtap_tune_report]
+               gtap.gtap_tune_report, gtap.gtap_litmus_result]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gtap.h"', "int main(void){"]
     for st in structs:
         lines.append(f'printf("{st.__name__} %zu\\n", sizeof({st.__name__}));')
@@ -92,3 +92,4 @@ def test_kclique_split_buffer_size_without_device():
         w = max((d + 63) // 64, 1)
         assert gtap.kclique_split_buffer_ints(d) == 2 + 4 * w
     assert gtap.kclique_split_buffer_ints(-1) == 0 and gtap.kclique_split_buffer_ints(1025) == 0
+
