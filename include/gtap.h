@@ -363,6 +363,10 @@ typedef struct gtap_stats {
     uint64_t atomics;        /* thread mode: device-scope read-modify-writes the
                                 scheduler issued (join updates, deque counts,
                                 claims and thieves' locks; one per lane)      */
+    uint64_t data_bytes;     /* thread mode: bytes of task data the k-clique task
+                                bodies read or wrote (row bounds, candidate
+                                lists, neighbour lists, new candidate lists),
+                                each list counted once at its full length   */
     double kernel_ms;        /* device time of the last run's persistent kernel */
     int32_t num_waves;
     int32_t waves_per_group;
@@ -452,11 +456,14 @@ const char *gtap_status_string(int32_t status);
 /* ---- batching: configuration autotuner ---------------------------------------- */
 /* Not in the paper (its configuration is chosen by hand).  Candidate values,
  * each list terminated by 0 (or by its length).  Every combination of
- * num_queues x (daq_bounds sets, for num_queues > 1) x waves_per_group x
- * num_waves is tried on the calibration jobs. */
+ * num_queues x (for num_queues > 1: DAQ class function x, for
+ * GTAP_DAQ_KCLIQUE, daq_bounds sets) x waves_per_group x num_waves is tried
+ * on the calibration jobs. */
 typedef struct {
     int32_t num_queues[4];       /* 1 = DAQ off                                 */
-    int32_t daq_policy;          /* policy used when num_queues > 1             */
+    int32_t daq_policies[4];     /* class functions tried when num_queues > 1
+                                    (gtap_daq_policy; an empty list means
+                                    GTAP_DAQ_BY_KIND)                          */
     int32_t waves_per_group[4];
     int32_t num_waves[4];        /* a negative entry means 0 (occupancy maximum) */
     int32_t bounds_sets;         /* daq_bounds candidates in bounds[] (0..4)    */

@@ -106,6 +106,7 @@ enum StatIdx : uint32_t {
   ST_POP_BATCHES, ST_STOLEN, ST_STEAL_BATCHES, ST_STEAL_ATTEMPTS, ST_ITERS,
   ST_IDLE, ST_SPILLS, ST_REFILLS, ST_BUSY_CYCLES, ST_IDLE_CYCLES, ST_ADMITTED, ST_LOCAL,
   ST_RMW,  // device-scope read-modify-writes issued by the scheduler (one per lane)
+  ST_DATA_WORDS,  // 4-byte words of task data (input lists, candidate buffers) task bodies moved
   ST_COUNT
 };
 

@@ -547,6 +547,7 @@ static int record_run(gtap_ctx *c, const Control &ctl, float ms) {
   s.admitted = ctl.stats[ST_ADMITTED];
   s.local_pushed = ctl.stats[ST_LOCAL];
   s.atomics = ctl.stats[ST_RMW];
+  s.data_bytes = 4 * ctl.stats[ST_DATA_WORDS];
   s.kernel_ms = ms;
   if (ctl.error != 0) {
     c->err.code = ctl.error;
@@ -1405,29 +1406,34 @@ int gtap_autotune(const gtap_config *base, const gtap_trace_job *calib, size_t n
     return out;
   };
   for (int32_t q : list(space->num_queues, b.num_queues)) {
-    const int nb = (q > 1 && space->bounds_sets > 0) ? std::min(space->bounds_sets, 4) : 1;
-    for (int bi = 0; bi < nb; ++bi)
-      for (int32_t wpg : list(space->waves_per_group, b.waves_per_group))
-        for (int32_t nw : list(space->num_waves, b.num_waves)) {
-          gtap_config cand = b;
-          cand.num_queues = q;
-          cand.daq_policy = q > 1 ? space->daq_policy : GTAP_DAQ_NONE;
-          if (q > 1 && space->bounds_sets > 0) std::memcpy(cand.daq_bounds, space->bounds[bi], sizeof(cand.daq_bounds));
-          cand.waves_per_group = wpg;
-          cand.num_waves = nw < 0 ? 0 : nw;
-          double ms = 0.0;
-          ++rep.candidates;
-          if (validate(cand) != GTAP_OK ||
-              tune_candidate(cand, calib, n, repeats, &ms, &st) != GTAP_OK) {
-            ++rep.failed;
-            continue;
+    const std::vector<int32_t> pols =
+        q > 1 ? list(space->daq_policies, GTAP_DAQ_BY_KIND) : std::vector<int32_t>{GTAP_DAQ_NONE};
+    for (int32_t pol : pols) {
+      const bool by_bounds = q > 1 && pol == GTAP_DAQ_KCLIQUE && space->bounds_sets > 0;
+      const int nb = by_bounds ? std::min(space->bounds_sets, 4) : 1;
+      for (int bi = 0; bi < nb; ++bi)
+        for (int32_t wpg : list(space->waves_per_group, b.waves_per_group))
+          for (int32_t nw : list(space->num_waves, b.num_waves)) {
+            gtap_config cand = b;
+            cand.num_queues = q;
+            cand.daq_policy = pol;
+            if (by_bounds) std::memcpy(cand.daq_bounds, space->bounds[bi], sizeof(cand.daq_bounds));
+            cand.waves_per_group = wpg;
+            cand.num_waves = nw < 0 ? 0 : nw;
+            double ms = 0.0;
+            ++rep.candidates;
+            if (validate(cand) != GTAP_OK ||
+                tune_candidate(cand, calib, n, repeats, &ms, &st) != GTAP_OK) {
+              ++rep.failed;
+              continue;
+            }
+            if (ms < win_ms) {
+              win_ms = ms;
+              win = cand;
+              win_st = st;
+            }
           }
-          if (ms < win_ms) {
-            win_ms = ms;
-            win = cand;
-            win_st = st;
-          }
-        }
+    }
   }
   // frame pools: four times what the best run touched, at least 2^20, at most the base sizes
   auto size_pool = [](uint64_t touched, uint64_t cap) {

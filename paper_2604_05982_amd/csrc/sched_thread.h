@@ -770,6 +770,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   WaveCounters wc;
   for (int i = 0; i < static_cast<int>(ST_COUNT); ++i) wc.v[i] = 0;
   uint64_t busy_cycles = 0, idle_cycles = 0;
+  uint64_t data_words = 0;  // this lane's task-data words (summed over the wave on exit)
   if (ln == 0) {
     for (uint32_t q = 0; q < kMaxQueues; ++q) {
       L.tail[q] = 0;
@@ -982,6 +983,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     o.nchild = 0;
     o.big = 0;
     o.first = 0;
+    o.words = 0;
     for (int i = 0; i < 6; ++i) o.d[i] = 0;
     if constexpr (kExt) o.emit = 0;
     if (ln < cnt) {
@@ -1007,6 +1009,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         fmm::chunks_append(lchunks, D, 1, em && o.emit == 2, pair);
       }
     }
+    data_words += o.words;
     const uint32_t nfirst = __popcll(ballot(o.first != 0));
     wc.add(ST_TASKS, nfirst);
     wc.add(ST_CONTS, cnt - nfirst);
@@ -1391,7 +1394,12 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
 
   if constexpr (kExt) fmm::chunks_close(lchunks);
   // ---- flush counters ----
+  const uint64_t wave_words = wave_inclusive_sum64(data_words);
+  const uint64_t words_total =
+      (static_cast<uint64_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(wave_words >> 32), 63)) << 32) |
+      __builtin_amdgcn_readlane(static_cast<uint32_t>(wave_words), 63);
   if (ln == 0) {
+    if (words_total) fetch_add_relaxed(&p.ctl->stats[ST_DATA_WORDS], words_total);
     for (int i = 0; i < static_cast<int>(ST_COUNT); ++i)
       if (wc.v[i]) fetch_add_relaxed(&p.ctl->stats[i], static_cast<uint64_t>(wc.v[i]));
     if (busy_cycles) fetch_add_relaxed(&p.ctl->stats[ST_BUSY_CYCLES], busy_cycles);

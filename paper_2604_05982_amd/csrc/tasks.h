@@ -38,6 +38,7 @@ struct Outcome {
   uint32_t first;    // 1: first execution (resume point 0), 0: continuation
   uint32_t emit;     // FMM list traversal: 1 = M2L pair, 2 = P2P pair (d[0], d[1]), descriptor d[3..4]
   uint32_t pc_next;  // OUT_FORK of the extended kinds: resume point after the join (Cilksort sorts fork twice)
+  uint32_t words;    // 4-byte words of task data the body read or wrote (k-clique lists), for the byte count
 };
 
 // Payload of a new frame (words 3..7).
@@ -830,6 +831,7 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
       }
       const int32_t s = rp[v], e = rp[v + 1];
       const uint32_t deg = static_cast<uint32_t>(e - s);
+      o.words = 2;
       if (k == 2) {
         o.value = deg;
         return;
@@ -854,12 +856,14 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
       const uint32_t nC = p4;
       const int32_t s = rp[u], e = rp[u + 1];
       const uint32_t nu = static_cast<uint32_t>(e - s);
+      o.words = 2 + nC + nu;  // row bounds, the parent's candidates, N+(u)
       if (l == 1) {
         o.value = intersect_sorted(C, nC, col + s, nu, nullptr);
         return;
       }
       int32_t *buf = reinterpret_cast<int32_t *>(f + FW_BUF);
       const uint32_t m = intersect_sorted(C, nC, col + s, nu, buf);
+      o.words += m;  // the candidates written for the children
       if (m == 0) return;
       const uint64_t cptr = reinterpret_cast<uint64_t>(buf);
       o.type = OUT_FORK;

@@ -140,7 +140,7 @@ class gtap_stats(ctypes.Structure):
         "tasks", "conts", "spawns", "pushed", "push_batches", "popped", "pop_batches",
         "stolen", "steal_batches", "steal_attempts", "iterations", "idle_iterations",
         "small_frames_touched", "big_frames_touched", "depot_spills", "depot_refills",
-        "busy_cycles", "idle_cycles", "admitted", "local_pushed", "atomics")] + [
+        "busy_cycles", "idle_cycles", "admitted", "local_pushed", "atomics", "data_bytes")] + [
         ("kernel_ms", ctypes.c_double),
         ("num_waves", ctypes.c_int32),
         ("waves_per_group", ctypes.c_int32),
@@ -163,7 +163,7 @@ class gtap_trace_result(ctypes.Structure):
 
 
 class gtap_tune_space(ctypes.Structure):
-    _fields_ = [("num_queues", ctypes.c_int32 * 4), ("daq_policy", ctypes.c_int32),
+    _fields_ = [("num_queues", ctypes.c_int32 * 4), ("daq_policies", ctypes.c_int32 * 4),
                 ("waves_per_group", ctypes.c_int32 * 4), ("num_waves", ctypes.c_int32 * 4),
                 ("bounds_sets", ctypes.c_int32), ("bounds", (ctypes.c_int32 * 7) * 4),
                 ("repeats", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
@@ -411,16 +411,19 @@ def gtap_litmus(test: int, ordered: bool, pairs: int, rounds: int, buf_dev_ptr: 
 
 
 def tune_space(num_queues=(1,), waves_per_group=(4,), num_waves=(0,), bounds=(), daq_policy=0,
-               repeats=2) -> "gtap_tune_space":
-    """Build a gtap_tune_space from Python lists (num_waves 0 = occupancy maximum)."""
+               repeats=2, daq_policies=()) -> "gtap_tune_space":
+    """Build a gtap_tune_space from Python lists (num_waves 0 = occupancy
+    maximum; daq_policy is shorthand for a one-entry daq_policies)."""
     sp = gtap_tune_space()
+    pols = list(daq_policies) or ([daq_policy] if daq_policy else [])
+    for i, v in enumerate(pols[:4]):
+        sp.daq_policies[i] = int(v)
     for i, v in enumerate(list(num_queues)[:4]):
         sp.num_queues[i] = int(v)
     for i, v in enumerate(list(waves_per_group)[:4]):
         sp.waves_per_group[i] = int(v)
     for i, v in enumerate(list(num_waves)[:4]):
         sp.num_waves[i] = -1 if int(v) == 0 else int(v)
-    sp.daq_policy = int(daq_policy)
     sp.bounds_sets = min(len(bounds), 4)
     for i, bset in enumerate(list(bounds)[:4]):
         full = list(bset) + [1 << 30] * (7 - len(bset))
