@@ -50,21 +50,29 @@ struct BlockLds {
   uint32_t task, next, next_cont, stop;
   uint32_t out_type, nchild, ckind, pad0;
   int64_t value;
-  uint32_t child[8][2];         // FMM children (A, B)
-  int32_t ca[fmm::kCellInts], cb[fmm::kCellInts];
-  uint32_t branch;              // FMM: 0 split, 1 M2L, 2 P2P
+  uint32_t child[8][2];         // FMM: children to fork (A, B)
+  // FMM batch: the cell records of the task's pair (rec 0 = A, rec 1 = B) and
+  // of the cells a split created (rec 2 + c); pair i of the batch is
+  // (pid[i][0], pid[i][1]) with records (prec[i][0], prec[i][1])
+  int32_t rec[10][fmm::kCellInts];
+  uint32_t pid[8][2];
+  uint8_t prec[8][2];
+  uint32_t cbr[8];              // branch of child c: 0 split again, 1 M2L, 2 P2P
+  uint32_t n_m2l, n_p2p, m2l_idx[8], p2p_idx[8];
+  uint32_t split_a;
   uint32_t first_fail;          // UTS: first failed draw in a batch
   int64_t bottom, top_seen;     // owner's view of its deque
-  double T[fmm::kNc];
-  double QB[fmm::kNc];
+  double Tc[8][fmm::kNc];       // Taylor coefficients of the batch's M2L pairs
+  double QBc[8][fmm::kNc];      // and their source moments
   double red[kMaxBlockThreads];
   uint4 lstk[2 * kBlkLocal];    // private stack (frame words 0..7 of each task)
   uint32_t lbot, ltop, local, dry;
-  // M2L term table, copied once per workgroup: coefficient and
-  // a | b << 8 | (a+b) << 16.  Thread t owns the consecutive terms
-  // [t*C, (t+1)*C) (C = ceil(924 / threads)); its r-th term is stored at
-  // r * threads + t so that a round of loads touches consecutive words.
-  double mc[kM2LSlots];
+  // M2L term table, copied once per workgroup:
+  // a | b << 8 | (a+b) << 16 | coefficient << 24 (the coefficient
+  // C(a+b, a) (-1)^|b| is an integer of magnitude <= 20, kept as int8).
+  // Thread t owns the consecutive terms [t*C, (t+1)*C) (C = ceil(924 /
+  // threads)); its r-th term is stored at r * threads + t so that a round of
+  // loads touches consecutive words.
   uint32_t mab[kM2LSlots];
   // Running sums for the target cell of consecutive pairs (siblings of one
   // split share it): M2L local coefficients of cell lcell, P2P potentials of
@@ -178,84 +186,97 @@ GTAP_DEV void fmm_flush(const Params &p, FmmCounters &fc) {
   fc = FmmCounters{kNone, 0, 0, 0, 0, 0, nullptr};
 }
 
+constexpr bool m2l_coefficients_fit_int8() {
+  const fmm::Tables T = fmm::make_tables();
+  for (int m = 0; m < fmm::kM2LTerms; ++m) {
+    const double c = T.m2l_c[m];
+    if (c != static_cast<double>(static_cast<int32_t>(c)) || c > 127.0 || c < -127.0) return false;
+  }
+  return true;
+}
+static_assert(m2l_coefficients_fit_int8(), "the M2L term table packs its coefficients as int8");
+
+// Branch of the pair of cell records (A, B): 1 accept (M2L), 2 both leaves
+// (P2P), 0 split.
+GTAP_DEV uint32_t fmm_branch(const int32_t *A, const int32_t *B, const fmm::FmmDesc *D) {
+  if (fmm::mac_accept(A, B, D->ta, D->tb)) return 1;
+  return (A[7] == 0 && B[7] == 0) ? 2u : 0u;
+}
+
+// Make cell `a` the target of the workgroup's running sums (M2L: local
+// coefficients, P2P: potentials of its points), adding the previous target's
+// sums to memory first.  All threads; every thread reads the same state
+// because the last change was followed by a barrier.
 template <int NT>
-GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &fc) {
+GTAP_DEV void fmm_target(BlockLds &S, const fmm::FmmDesc *D, uint32_t a, bool m2l, int32_t pbegin = 0,
+                         int32_t pn = 0) {
+  const bool same = m2l ? (S.lcell == a && S.ldesc == D) : (S.pcell == a && S.pdesc == D);
+  if (same) return;
+  fmm_flush_acc<NT>(S, m2l, !m2l);
+  if (threadIdx.x == 0) {
+    if (m2l) {
+      S.lcell = a;
+      S.ldesc = D;
+    } else {
+      S.pcell = a;
+      S.pdesc = D;
+      S.pbegin = pbegin;
+      S.pn = pn;
+    }
+  }
+  __syncthreads();
+}
+
+// M2L(A <- B) for the batch's pairs m2l_idx[0 .. n): Taylor coefficients of
+// 1/|d + h| degree by degree for all of them at once, then each pair's 924
+// terms spread evenly over the workgroup into the running sums of its target.
+template <int NT>
+GTAP_DEV void fmm_m2l_batch(const Params &p, BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc) {
   const uint32_t tx = threadIdx.x;
-  const uint32_t a = S.fw[FW_P0], b = S.fw[FW_P0 + 1];
-  if (fc.job != job) {
-    fmm_flush(p, fc);
-    fc.job = job;
-    fc.desc = reinterpret_cast<const fmm::FmmDesc *>(co_ld64(&p.jobs[job].a[0]));
+  const uint32_t n = S.n_m2l;
+  if (n == 0) return;
+  auto delta = [&](uint32_t i, double &d0, double &d1, double &d2) {
+    const uint32_t k = S.m2l_idx[i];
+    const int32_t *A = S.rec[S.prec[k][0]], *B = S.rec[S.prec[k][1]];
+    d0 = fmm::cell_centre(A[1], A[0]) - fmm::cell_centre(B[1], B[0]);
+    d1 = fmm::cell_centre(A[2], A[0]) - fmm::cell_centre(B[2], B[0]);
+    d2 = fmm::cell_centre(A[3], A[0]) - fmm::cell_centre(B[3], B[0]);
+  };
+  // source moments of every pair (one round of loads), and T_0
+  for (uint32_t x = tx; x < n * static_cast<uint32_t>(fmm::kNc); x += NT) {
+    const uint32_t i = x / fmm::kNc, t = x - i * fmm::kNc;
+    S.QBc[i][t] = D->Q[static_cast<size_t>(S.pid[S.m2l_idx[i]][1]) * fmm::kNc + t];
   }
-  const fmm::FmmDesc *D = fc.desc;
-  if (tx < fmm::kCellInts) {
-    S.ca[tx] = D->cell[static_cast<size_t>(a) * fmm::kCellInts + tx];
-    S.cb[tx] = D->cell[static_cast<size_t>(b) * fmm::kCellInts + tx];
-  }
-  __syncthreads();
-  if (tx == 0) {
-    uint32_t br = 0;
-    if (fmm::mac_accept(S.ca, S.cb, D->ta, D->tb)) br = 1;
-    else if (S.ca[7] == 0 && S.cb[7] == 0) br = 2;
-    S.branch = br;
-    if (br == 0) {
-      // split the wider cell; on a tie the target unless it is a leaf; never a leaf
-      bool split_a = S.ca[0] < S.cb[0] ? true : (S.ca[0] > S.cb[0] ? false : S.ca[7] != 0);
-      if (split_a && S.ca[7] == 0) split_a = false;
-      if (!split_a && S.cb[7] == 0) split_a = true;
-      const int32_t *Sp = split_a ? S.ca : S.cb;
-      const uint32_t k = static_cast<uint32_t>(Sp[7]);
-      for (uint32_t i = 0; i < k; ++i) {
-        const uint32_t ch = static_cast<uint32_t>(Sp[6]) + i;
-        S.child[i][0] = split_a ? ch : a;
-        S.child[i][1] = split_a ? b : ch;
-      }
-      S.nchild = k;
-    }
+  if (tx < n) {
+    double d0, d1, d2;
+    delta(tx, d0, d1, d2);
+    S.Tc[tx][0] = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
   }
   __syncthreads();
-  const uint32_t br = S.branch;
-  if (br == 0) return;
-  if (br == 1) {
-    // ---- M2L(A <- B): Taylor coefficients of 1/|d + h|, degree by degree ----
-    double d0 = 0.0, d1 = 0.0, d2 = 0.0, r2 = 0.0;
-    {
-      const int32_t *A = S.ca, *B = S.cb;
-      d0 = fmm::cell_centre(A[1], A[0]) - fmm::cell_centre(B[1], B[0]);
-      d1 = fmm::cell_centre(A[2], A[0]) - fmm::cell_centre(B[2], B[0]);
-      d2 = fmm::cell_centre(A[3], A[0]) - fmm::cell_centre(B[3], B[0]);
-      r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    }
-    for (uint32_t t = tx; t < static_cast<uint32_t>(fmm::kNc); t += NT) S.QB[t] = D->Q[static_cast<size_t>(b) * fmm::kNc + t];
-    if (tx == 0) S.T[0] = 1.0 / sqrt(r2);
-    __syncthreads();
-    for (int deg = 1; deg <= fmm::kP; ++deg) {
-      const int lo = fmm::ncoef(deg - 1), hi = fmm::ncoef(deg);
-      const int t = lo + static_cast<int>(tx);
-      if (t < hi) {
-        const double dd[3] = {d0, d1, d2};
-        double s1 = 0.0, s2 = 0.0;
+  for (int deg = 1; deg <= fmm::kP; ++deg) {
+    const uint32_t lo = static_cast<uint32_t>(fmm::ncoef(deg - 1)), nd = static_cast<uint32_t>(fmm::ncoef(deg)) - lo;
+    for (uint32_t x = tx; x < n * nd; x += NT) {
+      const uint32_t i = x / nd, t = lo + (x - i * nd);
+      double dd[3];
+      delta(i, dd[0], dd[1], dd[2]);
+      const double r2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+      double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const uint8_t m1 = fmm::kTab.dm1[t][i], m2 = fmm::kTab.dm2[t][i];
-          if (m1 != 0xFF) s1 += dd[i] * S.T[m1];
-          if (m2 != 0xFF) s2 += S.T[m2];
-        }
-        S.T[t] = -((2.0 * deg - 1.0) * s1 + (deg - 1.0) * s2) / (deg * r2);
+      for (int c = 0; c < 3; ++c) {
+        const uint8_t m1 = fmm::kTab.dm1[t][c], m2 = fmm::kTab.dm2[t][c];
+        if (m1 != 0xFF) s1 += dd[c] * S.Tc[i][m1];
+        if (m2 != 0xFF) s2 += S.Tc[i][m2];
       }
-      __syncthreads();
+      S.Tc[i][t] = -((2.0 * deg - 1.0) * s1 + (deg - 1.0) * s2) / (deg * r2);
     }
-    // the running sums belong to target cell a
-    if (S.lcell != a || S.ldesc != D) {
-      fmm_flush_acc<NT>(S, true, false);
-      if (tx == 0) {
-        S.lcell = a;
-        S.ldesc = D;
-      }
-    }
-    // the 924 terms spread evenly over the workgroup: each thread sums its
-    // run of terms per target coefficient and adds to LDS when it changes
-    constexpr uint32_t C = (fmm::kM2LTerms + NT - 1) / NT;
+    __syncthreads();
+  }
+  constexpr uint32_t C = (fmm::kM2LTerms + NT - 1) / NT;
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t k = S.m2l_idx[i];
+    const uint32_t a = S.pid[k][0], b = S.pid[k][1];
+    fmm_target<NT>(S, D, a, true);
+    const double *T = S.Tc[i], *QB = S.QBc[i];
     uint32_t cur = 0xFFu;
     double acc = 0.0;
 #pragma unroll
@@ -267,31 +288,29 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
         acc = 0.0;
         cur = at;
       }
-      if (at != 0xFFu) acc += S.mc[r * NT + tx] * S.T[w >> 16] * S.QB[(w >> 8) & 0xFFu];
+      if (at != 0xFFu)
+        acc += static_cast<double>(static_cast<int8_t>(w >> 24)) * T[(w >> 16) & 0xFFu] * QB[(w >> 8) & 0xFFu];
     }
     if (cur != 0xFFu) atomicAdd(&S.lacc[cur], acc);
     fc.m2l += 1;
     fc.m2l_hash += fmm::pair_hash(a, b);
-    return;
+    __syncthreads();  // the sums are complete before a change of target adds them to memory
   }
-  // ---- P2P(A <- B), cooperative: target = tx mod 64, wavefront w takes the
-  // sources w, w + G, ...: every lane of a wavefront reads the same source
-  // point at once (wave-uniform loads, no staging, no barriers in the loop) ----
+}
+
+// P2P(A <- B), cooperative: target = tx mod 64, wavefront w takes the sources
+// w, w + G, ...: every lane of a wavefront reads the same source point at
+// once (wave-uniform loads, no staging, no barriers in the source loop).
+template <int NT>
+GTAP_DEV void fmm_p2p(BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc, uint32_t a, uint32_t b,
+                      const int32_t *A, const int32_t *B) {
+  const uint32_t tx = threadIdx.x;
   constexpr uint32_t G = NT / kP2PTile;
   const int32_t wsrc = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(tx / kP2PTile));
-  const int32_t ab = S.ca[4], ae = S.ca[5], bb = S.cb[4], be = S.cb[5];
+  const int32_t ab = A[4], ae = A[5], bb = B[4], be = B[5];
   uint32_t coinc = 0;
   const bool keep_sum = (ae - ab) <= static_cast<int32_t>(kP2PTile);  // sums stay in LDS
-  if (keep_sum && (S.pcell != a || S.pdesc != D)) {
-    fmm_flush_acc<NT>(S, false, true);
-    if (tx == 0) {
-      S.pcell = a;
-      S.pdesc = D;
-      S.pbegin = ab;
-      S.pn = ae - ab;
-    }
-    __syncthreads();
-  }
+  if (keep_sum) fmm_target<NT>(S, D, a, false, ab, ae - ab);
   for (int32_t t0 = ab; t0 < ae; t0 += kP2PTile) {
     const int32_t i = t0 + static_cast<int32_t>(tx % kP2PTile);
     const bool live = i < ae;
@@ -332,6 +351,99 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
     fc.p2p += 1;
     fc.p2p_hash += fmm::pair_hash(a, b);
     fc.inter += static_cast<uint64_t>(na * nb - (a == b ? na : 0));
+  }
+}
+
+// One cell-pair task (A, B) of the dual-tree traversal.  An accepted pair
+// runs M2L, a pair of leaves P2P.  Otherwise the wider cell splits, and the
+// workgroup classifies all the child pairs at once: accepted children run
+// their M2L together and leaf pairs their P2P inside this task; only
+// children that must split again become tasks (S.child, S.nchild).  The
+// traversal visits the same pairs as one task per pair would.
+template <int NT>
+GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &fc) {
+  const uint32_t tx = threadIdx.x;
+  const uint32_t a = S.fw[FW_P0], b = S.fw[FW_P0 + 1];
+  if (fc.job != job) {
+    fmm_flush(p, fc);
+    fc.job = job;
+    fc.desc = reinterpret_cast<const fmm::FmmDesc *>(co_ld64(&p.jobs[job].a[0]));
+  }
+  const fmm::FmmDesc *D = fc.desc;
+  if (tx < fmm::kCellInts) {
+    S.rec[0][tx] = D->cell[static_cast<size_t>(a) * fmm::kCellInts + tx];
+    S.rec[1][tx] = D->cell[static_cast<size_t>(b) * fmm::kCellInts + tx];
+  }
+  __syncthreads();
+  uint32_t k = 0;
+  if (tx == 0) {
+    const int32_t *A = S.rec[0], *B = S.rec[1];
+    const uint32_t br = fmm_branch(A, B, D);
+    S.n_m2l = 0;
+    S.n_p2p = 0;
+    S.pid[0][0] = a;
+    S.pid[0][1] = b;
+    S.prec[0][0] = 0;
+    S.prec[0][1] = 1;
+    if (br == 1) {
+      S.n_m2l = 1;
+      S.m2l_idx[0] = 0;
+    } else if (br == 2) {
+      S.n_p2p = 1;
+      S.p2p_idx[0] = 0;
+    } else {
+      // split the wider cell; on a tie the target unless it is a leaf; never a leaf
+      bool split_a = A[0] < B[0] ? true : (A[0] > B[0] ? false : A[7] != 0);
+      if (split_a && A[7] == 0) split_a = false;
+      if (!split_a && B[7] == 0) split_a = true;
+      const int32_t *Sp = split_a ? A : B;
+      k = static_cast<uint32_t>(Sp[7]);
+      for (uint32_t c = 0; c < k; ++c) {
+        const uint32_t ch = static_cast<uint32_t>(Sp[6]) + c;
+        S.pid[c][0] = split_a ? ch : a;
+        S.pid[c][1] = split_a ? b : ch;
+        S.prec[c][0] = static_cast<uint8_t>(split_a ? 2 + c : 0);
+        S.prec[c][1] = static_cast<uint8_t>(split_a ? 1 : 2 + c);
+      }
+      S.split_a = split_a ? 1u : 0u;
+    }
+    S.nchild = k;
+  }
+  __syncthreads();
+  k = S.nchild;
+  if (k > 0) {
+    // the new cells' records (one round of loads), then every child's branch
+    if (tx < k * fmm::kCellInts) {
+      const uint32_t c = tx / fmm::kCellInts, w = tx - c * fmm::kCellInts;
+      const uint32_t cell = S.split_a ? S.pid[c][0] : S.pid[c][1];
+      S.rec[2 + c][w] = D->cell[static_cast<size_t>(cell) * fmm::kCellInts + w];
+    }
+    __syncthreads();
+    if (tx < k) S.cbr[tx] = fmm_branch(S.rec[S.prec[tx][0]], S.rec[S.prec[tx][1]], D);
+    __syncthreads();
+    if (tx == 0) {
+      uint32_t nf = 0, nm = 0, np = 0;
+      for (uint32_t c = 0; c < k; ++c) {
+        const uint32_t br = S.cbr[c];
+        if (br == 1) S.m2l_idx[nm++] = c;
+        else if (br == 2) S.p2p_idx[np++] = c;
+        else {
+          S.child[nf][0] = S.pid[c][0];
+          S.child[nf][1] = S.pid[c][1];
+          ++nf;
+        }
+      }
+      S.n_m2l = nm;
+      S.n_p2p = np;
+      S.nchild = nf;
+    }
+    __syncthreads();
+  }
+  fmm_m2l_batch<NT>(p, S, D, fc);
+  const uint32_t np = S.n_p2p;
+  for (uint32_t i = 0; i < np; ++i) {
+    const uint32_t c = S.p2p_idx[i];
+    fmm_p2p<NT>(S, D, fc, S.pid[c][0], S.pid[c][1], S.rec[S.prec[c][0]], S.rec[S.prec[c][1]]);
   }
 }
 
@@ -378,15 +490,14 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
     for (uint32_t r = 0; r < C; ++r) {
       const uint32_t m = tx * C + r;  // this thread's r-th term
       uint32_t w = 0xFFu;
-      double c = 0.0;
       if (m < static_cast<uint32_t>(fmm::kM2LTerms)) {
         uint32_t at = 0;
         while (fmm::kTab.m2l_first[at + 1] <= m) ++at;
-        w = at | (static_cast<uint32_t>(fmm::kTab.m2l_b[m]) << 8) | (static_cast<uint32_t>(fmm::kTab.m2l_g[m]) << 16);
-        c = fmm::kTab.m2l_c[m];
+        const int32_t c = static_cast<int32_t>(fmm::kTab.m2l_c[m]);
+        w = at | (static_cast<uint32_t>(fmm::kTab.m2l_b[m]) << 8) | (static_cast<uint32_t>(fmm::kTab.m2l_g[m]) << 16) |
+            (static_cast<uint32_t>(static_cast<uint8_t>(static_cast<int8_t>(c))) << 24);
       }
       S.mab[r * NT + tx] = w;
-      S.mc[r * NT + tx] = c;
     }
   }
   for (uint32_t t = tx; t < static_cast<uint32_t>(fmm::kNc); t += NT) S.lacc[t] = 0.0;
@@ -577,10 +688,7 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
       if (tx == 0 && S.out_type == OUT_DONE) S.value = 1;
     } else if (kind == TK_FMM) {
       fmm_pair<NT>(p, S, job, fc);
-      if (tx == 0 && S.branch == 0) {
-        S.out_type = OUT_FORK;
-        // nchild set by the body
-      }
+      if (tx == 0 && S.nchild > 0) S.out_type = OUT_FORK;  // the pairs that split again
     }
     __syncthreads();
 
