@@ -494,6 +494,38 @@ typedef struct {
 int gtap_autotune(const gtap_config *base, const gtap_trace_job *calib, size_t n,
                   const gtap_tune_space *space, gtap_config *best, gtap_tune_report *report);
 
+/* ---- allocation-free batch run --------------------------------------------------- */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the same batch
+ * as gtap_init + one gtap_submit per job + gtap_run + gtap_result +
+ * gtap_finalize, but the runtime's workspace (control block, job table,
+ * deques, frame pools) is a static device array of GTAP_STATIC_SCRATCH_BYTES
+ * inside the library, one per device, held from the first call on that device
+ * until the process ends.  The call performs no hipMalloc, hipFree, host
+ * pinned allocation or event creation; it launches on cfg->stream and waits
+ * for it.
+ *   cfg:     as for gtap_init; max_jobs, workspace_dev and workspace_bytes are
+ *            ignored (the job table holds exactly n jobs);
+ *   jobs:    host array of n jobs (kind and argument struct as for
+ *            gtap_submit, arrival_s ignored); kinds GTAP_KIND_FIB, _NQUEENS,
+ *            _UTS and _KCLIQUE only (the other kinds allocate per-job buffers);
+ *            device pointers inside the arguments are borrowed until return;
+ *   results: host array receiving job i's result at index i;
+ *   report:  NULL, or receives the structured report of a device abort
+ *            (as gtap_last_error would), zeroed otherwise.
+ * n <= GTAP_STATIC_MAX_JOBS.  Errors: GTAP_E_INVAL (arguments, kinds,
+ * configuration), GTAP_E_NOMEM (the configuration's workspace, as reported by
+ * gtap_workspace_size for max_jobs = n, exceeds GTAP_STATIC_SCRATCH_BYTES:
+ * shrink the frame pools or deques), GTAP_E_CAPACITY / GTAP_E_TIMEOUT (the
+ * device run aborted: see *report), GTAP_E_HIP.  Every call on a device
+ * uses that device's one array: calls that overlap on one device (from two
+ * host threads, or on two streams) race and must not be made; each call
+ * clears the state it needs first, so back-to-back calls are independent. */
+#define GTAP_STATIC_SCRATCH_BYTES (256u << 20)
+#define GTAP_STATIC_MAX_JOBS 4096u
+int gtap_run_static(const gtap_config *cfg, const gtap_trace_job *jobs, size_t n, int64_t *results,
+                    gtap_error_report *report);
+
 /* ---- platform probes ------------------------------------------------------------ */
 /* Not in the paper: measurements of the two platform properties the runtime's
  * design rests on (its hand-offs use relaxed device-scope accesses ordered by

@@ -1628,3 +1628,126 @@ extern "C" int gtap_litmus(int32_t test, int32_t ordered, uint32_t pairs, uint32
   for (uint32_t q = 0; q < pairs; ++q) out->pairs_on_distinct_xcds += (hx[2 * q] & 15u) != (hx[2 * q + 1] & 15u);
   return GTAP_OK;
 }
+
+// ---- allocation-free batch run --------------------------------------------
+// The runtime's workspace (control block, job table, deques, depots, frame
+// pools) lives in a static device array instead of a hipMalloc'd buffer.  In
+// host code `scratch` names a host-side stand-in, never the device memory:
+// its device address is looked up once per device and used from then on.
+static __device__ __align__(256) char scratch[GTAP_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr size_t kStaticScratchBytes = static_cast<size_t>(GTAP_STATIC_SCRATCH_BYTES);
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up on the first call
+// on the device, with that device current).
+int static_scratch(char **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GTAP_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GTAP_E_HIP;
+    g_scratch_dev[dev] = static_cast<char *>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return GTAP_OK;
+}
+
+constexpr size_t kStaticChunk = 32;  // job slots staged per copy (4 KB on the stack)
+
+}  // namespace
+
+extern "C" int gtap_run_static(const gtap_config *cfg_in, const gtap_trace_job *jobs, size_t n, int64_t *results,
+                               gtap_error_report *report) {
+  if (report) *report = gtap_error_report{};
+  if (!cfg_in || (n > 0 && (!jobs || !results))) return GTAP_E_INVAL;
+  if (n > GTAP_STATIC_MAX_JOBS) return GTAP_E_INVAL;
+  if (n == 0) return GTAP_OK;
+  for (size_t i = 0; i < n; ++i) {
+    const int32_t k = jobs[i].kind;
+    if (k != GTAP_KIND_FIB && k != GTAP_KIND_NQUEENS && k != GTAP_KIND_UTS && k != GTAP_KIND_KCLIQUE)
+      return GTAP_E_INVAL;
+    if (jobs[i].args_bytes > sizeof(jobs[i].args)) return GTAP_E_INVAL;
+  }
+  gtap_config cfg = *cfg_in;
+  cfg.max_jobs = static_cast<uint32_t>(n);
+  cfg.workspace_dev = nullptr;
+  cfg.workspace_bytes = 0;
+  if (cfg.timeout_ms == 0) cfg.timeout_ms = 120000;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  uint32_t maxw = 0;
+  rc = max_resident_waves(cfg.mode, cfg.waves_per_group, &maxw);
+  if (rc) return rc;
+  uint32_t nw = cfg.num_waves ? std::min<uint32_t>(cfg.num_waves, maxw) : maxw;
+  nw = std::max<uint32_t>(nw / cfg.waves_per_group, 1) * cfg.waves_per_group;
+  const Layout L = make_layout(cfg, nw);
+  if (L.total > kStaticScratchBytes) return GTAP_E_NOMEM;
+  char *ws = nullptr;
+  rc = static_scratch(&ws);
+  if (rc) return rc;
+
+  // a context on the stack: the launch helpers read its configuration,
+  // grid, stream and kernel parameters (its containers stay empty)
+  gtap_ctx c;
+  c.cfg = cfg;
+  c.stream = static_cast<hipStream_t>(cfg.stream);
+  c.nwaves = nw;
+  c.lay = L;
+  c.ws = ws;
+  fill_params(cfg, nw, L, ws, c.params);
+  Params &p = c.params;
+  p.njobs = static_cast<uint32_t>(n);
+  p.serving = 0;
+
+  JobSlot buf[kStaticChunk];
+  for (size_t i0 = 0; i0 < n; i0 += kStaticChunk) {
+    const size_t m = std::min(kStaticChunk, n - i0);
+    for (size_t i = 0; i < m; ++i) {
+      rc = pack_job(cfg, c.stream, jobs[i0 + i].kind, jobs[i0 + i].args, jobs[i0 + i].args_bytes, buf[i]);
+      if (rc) return rc;
+    }
+    if (hipMemcpyAsync(p.jobs + i0, buf, m * sizeof(JobSlot), hipMemcpyHostToDevice, c.stream) != hipSuccess ||
+        hipStreamSynchronize(c.stream) != hipSuccess)
+      return GTAP_E_HIP;
+  }
+  const uint32_t ndq = nw * p.Q;
+  hipLaunchKernelGGL(reset_kernel, dim3(reset_blocks(ndq, p.ccap)), dim3(256), 0, c.stream, p, ndq);
+  if (hipGetLastError() != hipSuccess) return GTAP_E_HIP;
+  rc = launch_sched(&c);
+  if (rc) {
+    (void)hipStreamSynchronize(c.stream);
+    return rc;
+  }
+  Control ctl;
+  if (hipMemcpyAsync(&ctl, p.ctl, sizeof(Control), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+      hipStreamSynchronize(c.stream) != hipSuccess)
+    return GTAP_E_HIP;
+  if (ctl.error != 0) {
+    if (report) {
+      report->code = ctl.error;
+      report->pool = ctl.err_pool;
+      report->capacity = ctl.err_capacity;
+      report->requested = ctl.err_requested;
+      report->wave = ctl.err_wave;
+      report->job = ctl.err_job;
+    }
+    return ctl.error;
+  }
+  for (size_t i0 = 0; i0 < n; i0 += kStaticChunk) {
+    const size_t m = std::min(kStaticChunk, n - i0);
+    if (hipMemcpyAsync(buf, p.jobs + i0, m * sizeof(JobSlot), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+        hipStreamSynchronize(c.stream) != hipSuccess)
+      return GTAP_E_HIP;
+    for (size_t i = 0; i < m; ++i) {
+      if (buf[i].done != 1) return GTAP_E_STATE;
+      results[i0 + i] = buf[i].result;
+    }
+  }
+  return GTAP_OK;
+}

@@ -228,11 +228,13 @@ def _load() -> ctypes.CDLL:
     lib.gtap_probe_atomics.argtypes = [ctypes.c_int32, u32, u32, vp, u64, vp, P(ctypes.c_double),
                                        P(ctypes.c_double)]
     lib.gtap_litmus.argtypes = [ctypes.c_int32, ctypes.c_int32, u32, u32, vp, u64, vp, P(gtap_litmus_result)]
+    lib.gtap_run_static.argtypes = [P(gtap_config), P(gtap_trace_job), ctypes.c_size_t, P(ctypes.c_int64),
+                                    P(gtap_error_report)]
     for fn in ("gtap_workspace_size", "gtap_init", "gtap_submit", "gtap_run", "gtap_result",
                "gtap_finalize", "gtap_stats_get", "gtap_last_error", "gtap_serve_start",
                "gtap_serve_submit", "gtap_serve_poll", "gtap_serve_stop", "gtap_trace_run",
                "gtap_trace_run_plain", "gtap_autotune", "gtap_probe_atomics",
-               "gtap_litmus"):
+               "gtap_litmus", "gtap_run_static"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -244,7 +246,7 @@ EXPORTED = ("gtap_config_default", "gtap_workspace_size", "gtap_init", "gtap_sub
             "gtap_result", "gtap_finalize", "gtap_stats_get", "gtap_last_error",
             "gtap_status_string", "gtap_serve_start", "gtap_serve_submit", "gtap_serve_poll",
             "gtap_serve_stop", "gtap_trace_run", "gtap_trace_run_plain", "gtap_autotune",
-            "gtap_kclique_split_buffer_ints", "gtap_probe_atomics", "gtap_litmus")
+            "gtap_kclique_split_buffer_ints", "gtap_probe_atomics", "gtap_litmus", "gtap_run_static")
 
 
 class GtapError(RuntimeError):
@@ -387,6 +389,8 @@ def gtap_autotune(base: "gtap_config", jobs, space: "gtap_tune_space"):
 GTAP_PROBE_DISTINCT = 0
 GTAP_PROBE_PER_WAVE = 1
 GTAP_PROBE_ONE_WORD = 2
+GTAP_STATIC_SCRATCH_BYTES = 256 << 20   # workspace bytes of gtap_run_static (per device)
+GTAP_STATIC_MAX_JOBS = 4096
 
 
 def gtap_probe_atomics(mode: int, blocks: int, iters: int, words_dev_ptr: int, words: int, stream=None):
@@ -408,6 +412,17 @@ def gtap_litmus(test: int, ordered: bool, pairs: int, rounds: int, buf_dev_ptr: 
     if rc != GTAP_OK:
         raise GtapError(rc, "gtap_litmus")
     return out.as_dict()
+
+
+def gtap_run_static(cfg: "gtap_config", jobs) -> list:
+    """Results of a batch run in the library's static workspace (no device
+    allocation).  jobs: a ctypes array of gtap_trace_job (Runtime.trace)."""
+    out = (ctypes.c_int64 * max(1, len(jobs)))()
+    rep = gtap_error_report()
+    rc = _lib.gtap_run_static(ctypes.byref(cfg), jobs, len(jobs), out, ctypes.byref(rep))
+    if rc != GTAP_OK:
+        raise GtapError(rc, "gtap_run_static", rep.as_dict() if rep.code else None)
+    return list(out[:len(jobs)])
 
 
 def tune_space(num_queues=(1,), waves_per_group=(4,), num_waves=(0,), bounds=(), daq_policy=0,
