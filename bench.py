@@ -42,12 +42,19 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "thread_sched_kernel_hbm_traffic.t
 VALU_FILE = os.path.join(ROOT, "profiles", "thread_sched_kernel_kclique7_valu_daq.txt")
 
 
-def kernel_source_sha() -> str:
-    """Hash of the HIP sources the scheduler kernel is built from."""
+# The HIP sources each scheduler kernel is compiled from (the block-mode
+# kernel includes the thread-mode headers; the thread-mode kernel does not
+# include the block-mode one).
+THREAD_KERNEL_SOURCES = ("layout.h", "wave.h", "tasks.h", "kclique_bits.h", "sched_thread.h", "fmm.h", "fmm_lists.h")
+BLOCK_KERNEL_SOURCES = THREAD_KERNEL_SOURCES + ("sched_block.h",)
+
+
+def kernel_source_sha(files=THREAD_KERNEL_SOURCES) -> str:
+    """Hash of the HIP sources a scheduler kernel is built from."""
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(ROOT, "paper_2604_05982_amd", "csrc", "*"))):
-        with open(path, "rb") as fh:
-            h.update(os.path.basename(path).encode())
+    for name in sorted(files):
+        with open(os.path.join(ROOT, "paper_2604_05982_amd", "csrc", name), "rb") as fh:
+            h.update(name.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -39,12 +39,16 @@ struct alignas(128) ClDeque {
 static_assert(sizeof(ClDeque) == sizeof(DequeMeta), "block deques reuse the deque lines");
 
 constexpr uint32_t kMaxBlockThreads = 256;
+// Free small-frame stack per workgroup: two depot chunks (FMM tasks take
+// frames only when exposed to thieves; a smaller stack leaves room for a
+// sixth workgroup per CU)
+constexpr uint32_t kBlockStackSmall = 2 * kChunkSmall;
 constexpr uint32_t kP2PTile = 64;
 constexpr uint32_t kBlkLocal = 128;  // private stack of cell-pair task images
 constexpr uint32_t kM2LSlots = 1024; // >= ceil(924 / threads) * threads for 64, 128, 256 threads
 
 struct BlockLds {
-  uint32_t stk_s[kStackSmall];
+  uint32_t stk_s[kBlockStackSmall];
   uint32_t stk_b[kStackBig];
   uint32_t fw[kFrameWords];     // frame of the current task
   uint32_t task, next, next_cont, stop;
@@ -60,11 +64,16 @@ struct BlockLds {
   uint32_t cbr[8];              // branch of child c: 0 split again, 1 M2L, 2 P2P
   uint32_t n_m2l, n_p2p, m2l_idx[8], p2p_idx[8];
   uint32_t split_a;
+  // P2P batch: target point ranges x source point ranges (one side is one cell)
+  int32_t tr_b[8], tr_n[8], sr_b[8], sr_n[8];
+  uint32_t nt, ns;
   uint32_t first_fail;          // UTS: first failed draw in a batch
   int64_t bottom, top_seen;     // owner's view of its deque
-  double Tc[8][fmm::kNc];       // Taylor coefficients of the batch's M2L pairs
-  double QBc[8][fmm::kNc];      // and their source moments
-  double red[kMaxBlockThreads];
+  union {                       // the M2L batch completes before the P2P batch starts
+    double Tc[8][fmm::kNc];     // Taylor coefficients of the batch's M2L pairs
+    double red[kMaxBlockThreads];  // P2P: partial sums of the source groups
+  };
+  double QBc[8][fmm::kNc];      // source moments of the M2L pairs
   uint4 lstk[2 * kBlkLocal];    // private stack (frame words 0..7 of each task)
   uint32_t lbot, ltop, local, dry;
   // M2L term table, copied once per workgroup:
@@ -298,60 +307,102 @@ GTAP_DEV void fmm_m2l_batch(const Params &p, BlockLds &S, const fmm::FmmDesc *D,
   }
 }
 
-// P2P(A <- B), cooperative: target = tx mod 64, wavefront w takes the sources
-// w, w + G, ...: every lane of a wavefront reads the same source point at
-// once (wave-uniform loads, no staging, no barriers in the source loop).
+// P2P for the batch's leaf pairs p2p_idx[0 .. n).  They share one cell --
+// the target if the split took the source side, the source otherwise -- so
+// the batch is (target ranges) x (source ranges) and runs as one pass:
+// target = tx mod 64 over the concatenated target ranges, wavefront w takes
+// the sources w, w + G, ... of each source range, so every lane of a
+// wavefront reads the same source point at once (wave-uniform loads, no
+// staging, no barriers in the source loop).
 template <int NT>
-GTAP_DEV void fmm_p2p(BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc, uint32_t a, uint32_t b,
-                      const int32_t *A, const int32_t *B) {
+GTAP_DEV void fmm_p2p_batch(BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc) {
   const uint32_t tx = threadIdx.x;
+  const uint32_t n = S.n_p2p;
+  if (n == 0) return;
+  if (tx == 0) {
+    // ranges: the shared cell once, the other side per pair
+    uint32_t nt = 0, ns = 0;
+    for (uint32_t q = 0; q < n; ++q) {
+      const uint32_t k = S.p2p_idx[q];
+      const int32_t *A = S.rec[S.prec[k][0]], *B = S.rec[S.prec[k][1]];
+      const uint32_t a = S.pid[k][0], b = S.pid[k][1];
+      if (q == 0 || S.prec[k][0] != S.prec[S.p2p_idx[0]][0]) {
+        S.tr_b[nt] = A[4];
+        S.tr_n[nt] = A[5] - A[4];
+        ++nt;
+      }
+      if (q == 0 || S.prec[k][1] != S.prec[S.p2p_idx[0]][1]) {
+        S.sr_b[ns] = B[4];
+        S.sr_n[ns] = B[5] - B[4];
+        ++ns;
+      }
+      const int64_t na = A[5] - A[4], nb = B[5] - B[4];
+      fc.p2p += 1;
+      fc.p2p_hash += fmm::pair_hash(a, b);
+      fc.inter += static_cast<uint64_t>(na * nb - (a == b ? na : 0));
+    }
+    S.nt = nt;
+    S.ns = ns;
+  }
+  __syncthreads();
   constexpr uint32_t G = NT / kP2PTile;
   const int32_t wsrc = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(tx / kP2PTile));
-  const int32_t ab = A[4], ae = A[5], bb = B[4], be = B[5];
+  const uint32_t nt = S.nt, ns = S.ns;
+  int32_t total = 0;
+  for (uint32_t r = 0; r < nt; ++r) total += S.tr_n[r];
+  // one target cell of at most 64 points: its sums stay in LDS across tasks
+  const bool keep_sum = nt == 1 && total <= static_cast<int32_t>(kP2PTile);
+  if (keep_sum) fmm_target<NT>(S, D, S.pid[S.p2p_idx[0]][0], false, S.tr_b[0], total);
   uint32_t coinc = 0;
-  const bool keep_sum = (ae - ab) <= static_cast<int32_t>(kP2PTile);  // sums stay in LDS
-  if (keep_sum) fmm_target<NT>(S, D, a, false, ab, ae - ab);
-  for (int32_t t0 = ab; t0 < ae; t0 += kP2PTile) {
-    const int32_t i = t0 + static_cast<int32_t>(tx % kP2PTile);
-    const bool live = i < ae;
+  const double *__restrict__ px = D->px, *__restrict__ py = D->py, *__restrict__ pz = D->pz,
+               *__restrict__ pq = D->pq;
+  for (int32_t t0 = 0; t0 < total; t0 += kP2PTile) {
+    const int32_t g = t0 + static_cast<int32_t>(tx % kP2PTile);
+    const bool live = g < total;
+    int32_t i = 0;
+    if (live) {  // the g-th point of the concatenated target ranges
+      int32_t off = g;
+      uint32_t r = 0;
+      while (off >= S.tr_n[r]) {
+        off -= S.tr_n[r];
+        ++r;
+      }
+      i = S.tr_b[r] + off;
+    }
     double xi = 0.0, yi = 0.0, zi = 0.0;
     if (live) {
-      xi = D->px[i];
-      yi = D->py[i];
-      zi = D->pz[i];
+      xi = px[i];
+      yi = py[i];
+      zi = pz[i];
     }
     double acc = 0.0;
-    const double *__restrict__ px = D->px, *__restrict__ py = D->py, *__restrict__ pz = D->pz,
-                 *__restrict__ pq = D->pq;
+    for (uint32_t sr = 0; sr < ns; ++sr) {
+      const int32_t bb = S.sr_b[sr], be = bb + S.sr_n[sr];
 #pragma unroll 4
-    for (int32_t j = bb + wsrc; j < be; j += static_cast<int32_t>(G)) {
-      const double dx = xi - px[j], dy = yi - py[j], dz = zi - pz[j];
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 == 0.0) {
-        if (live && j != i) ++coinc;
-      } else {
-        acc += pq[j] * fmm::rsqrt_nr(r2);
+      for (int32_t j = bb + wsrc; j < be; j += static_cast<int32_t>(G)) {
+        const double dx = xi - px[j], dy = yi - py[j], dz = zi - pz[j];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 == 0.0) {
+          if (live && j != i) ++coinc;
+        } else {
+          acc += pq[j] * fmm::rsqrt_nr(r2);
+        }
       }
     }
     __syncthreads();
     S.red[tx] = acc;
     __syncthreads();
     if (tx < kP2PTile && live) {
-      double s = 0.0;
+      double sum = 0.0;
 #pragma unroll
-      for (uint32_t g = 0; g < G; ++g) s += S.red[tx + g * kP2PTile];
-      if (keep_sum) S.pacc[tx] += s;
-      else unsafeAtomicAdd(D->phi + i, s);
+      for (uint32_t q = 0; q < G; ++q) sum += S.red[tx + q * kP2PTile];
+      if (keep_sum) S.pacc[tx] += sum;
+      else unsafeAtomicAdd(D->phi + i, sum);
     }
   }
   if (coinc) atomicAdd(reinterpret_cast<unsigned long long *>(const_cast<uint64_t *>(&D->coincident)),
                        static_cast<unsigned long long>(coinc));
-  if (tx == 0) {
-    const int64_t na = ae - ab, nb = be - bb;
-    fc.p2p += 1;
-    fc.p2p_hash += fmm::pair_hash(a, b);
-    fc.inter += static_cast<uint64_t>(na * nb - (a == b ? na : 0));
-  }
+  __syncthreads();  // S.red and the ranges are free for the next pass
 }
 
 // One cell-pair task (A, B) of the dual-tree traversal.  An accepted pair
@@ -440,11 +491,7 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
     __syncthreads();
   }
   fmm_m2l_batch<NT>(p, S, D, fc);
-  const uint32_t np = S.n_p2p;
-  for (uint32_t i = 0; i < np; ++i) {
-    const uint32_t c = S.p2p_idx[i];
-    fmm_p2p<NT>(S, D, fc, S.pid[c][0], S.pid[c][1], S.rec[S.prec[c][0]], S.rec[S.prec[c][1]]);
-  }
+  fmm_p2p_batch<NT>(S, D, fc);
 }
 
 // Root frame of job j in block mode.
@@ -466,7 +513,7 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
   const uint32_t me = blockIdx.x;
   const uint32_t nw = gridDim.x;
   const uint64_t deadline = wall_ticks() + p.timeout_ticks;
-  PoolView PS{S.stk_s, 0, 0, 0, kStackSmall, kChunkSmall, p.bins_s, p.store_s,
+  PoolView PS{S.stk_s, 0, 0, 0, kBlockStackSmall, kChunkSmall, p.bins_s, p.store_s,
               p.bincap_s, &p.ctl->bump_small, p.nframes_s, 0u, 0};
   PoolView PB{S.stk_b, 0, 0, 0, kStackBig, kChunkBig, p.bins_b, p.store_b,
               p.bincap_b, &p.ctl->bump_big, p.nframes_b, kBigBit, 1};
