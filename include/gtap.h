@@ -365,8 +365,9 @@ typedef struct gtap_stats {
                                 claims and thieves' locks; one per lane)      */
     uint64_t data_bytes;     /* thread mode: bytes of task data the k-clique task
                                 bodies read or wrote (row bounds, candidate
-                                lists, neighbour lists, new candidate lists),
-                                each list counted once at its full length   */
+                                lists, neighbour lists, new candidate lists;
+                                split jobs: bit-matrix rows and node states),
+                                each list or row counted once at full length */
     double kernel_ms;        /* device time of the last run's persistent kernel */
     int32_t num_waves;
     int32_t waves_per_group;

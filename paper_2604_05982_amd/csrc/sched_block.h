@@ -195,6 +195,14 @@ GTAP_DEV void fmm_flush(const Params &p, FmmCounters &fc) {
   fc = FmmCounters{kNone, 0, 0, 0, 0, 0, nullptr};
 }
 
+// Lane k's value of x (k wave-uniform), read through two 32-bit lane reads.
+GTAP_DEV double lane_double(double x, int32_t k) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(b)), k));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(b >> 32)), k));
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 constexpr bool m2l_coefficients_fit_int8() {
   const fmm::Tables T = fmm::make_tables();
   for (int m = 0; m < fmm::kM2LTerms; ++m) {
@@ -310,10 +318,11 @@ GTAP_DEV void fmm_m2l_batch(const Params &p, BlockLds &S, const fmm::FmmDesc *D,
 // P2P for the batch's leaf pairs p2p_idx[0 .. n).  They share one cell --
 // the target if the split took the source side, the source otherwise -- so
 // the batch is (target ranges) x (source ranges) and runs as one pass:
-// target = tx mod 64 over the concatenated target ranges, wavefront w takes
-// the sources w, w + G, ... of each source range, so every lane of a
-// wavefront reads the same source point at once (wave-uniform loads, no
-// staging, no barriers in the source loop).
+// target = tx mod 64 over the concatenated target ranges; wavefront w takes
+// the chunks w, w + G, ... of 64 concatenated sources, loads a chunk with one
+// coalesced load per lane and walks it by reading each source from its lane
+// (one round of loads per 64 sources, no LDS staging, no barriers in the
+// source loop).
 template <int NT>
 GTAP_DEV void fmm_p2p_batch(BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc) {
   const uint32_t tx = threadIdx.x;
@@ -348,8 +357,10 @@ GTAP_DEV void fmm_p2p_batch(BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc)
   constexpr uint32_t G = NT / kP2PTile;
   const int32_t wsrc = static_cast<int32_t>(__builtin_amdgcn_readfirstlane(tx / kP2PTile));
   const uint32_t nt = S.nt, ns = S.ns;
-  int32_t total = 0;
+  const uint32_t ln = tx & (kWave - 1);
+  int32_t total = 0, stotal = 0;
   for (uint32_t r = 0; r < nt; ++r) total += S.tr_n[r];
+  for (uint32_t r = 0; r < ns; ++r) stotal += S.sr_n[r];
   // one target cell of at most 64 points: its sums stay in LDS across tasks
   const bool keep_sum = nt == 1 && total <= static_cast<int32_t>(kP2PTile);
   if (keep_sum) fmm_target<NT>(S, D, S.pid[S.p2p_idx[0]][0], false, S.tr_b[0], total);
@@ -376,16 +387,33 @@ GTAP_DEV void fmm_p2p_batch(BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc)
       zi = pz[i];
     }
     double acc = 0.0;
-    for (uint32_t sr = 0; sr < ns; ++sr) {
-      const int32_t bb = S.sr_b[sr], be = bb + S.sr_n[sr];
-#pragma unroll 4
-      for (int32_t j = bb + wsrc; j < be; j += static_cast<int32_t>(G)) {
-        const double dx = xi - px[j], dy = yi - py[j], dz = zi - pz[j];
+    for (int32_t c0 = wsrc * static_cast<int32_t>(kWave); c0 < stotal; c0 += static_cast<int32_t>(G * kWave)) {
+      // this lane's source of the chunk: the (c0 + lane)-th of the concatenated ranges
+      int32_t sj = -1;
+      double sx = 0.0, sy = 0.0, sz = 0.0, sq = 0.0;
+      int32_t off = c0 + static_cast<int32_t>(ln);
+      if (off < stotal) {
+        uint32_t r = 0;
+        while (off >= S.sr_n[r]) {
+          off -= S.sr_n[r];
+          ++r;
+        }
+        sj = S.sr_b[r] + off;
+        sx = px[sj];
+        sy = py[sj];
+        sz = pz[sj];
+        sq = pq[sj];
+      }
+      const int32_t nk = (stotal - c0) < static_cast<int32_t>(kWave) ? (stotal - c0) : static_cast<int32_t>(kWave);
+      for (int32_t k = 0; k < nk; ++k) {
+        const double bx = lane_double(sx, k), by = lane_double(sy, k), bz = lane_double(sz, k);
+        const double dx = xi - bx, dy = yi - by, dz = zi - bz;
         const double r2 = dx * dx + dy * dy + dz * dz;
+        const double bq = lane_double(sq, k);
         if (r2 == 0.0) {
-          if (live && j != i) ++coinc;
+          if (live && __builtin_amdgcn_readlane(sj, k) != i) ++coinc;
         } else {
-          acc += pq[j] * fmm::rsqrt_nr(r2);
+          acc += bq * fmm::rsqrt_nr(r2);
         }
       }
     }

@@ -292,6 +292,7 @@ GTAP_DEV void ks_row(const Params &p, Outcome &o, uint32_t u, uint32_t i) {
   const uint32_t dx = static_cast<uint32_t>(J.rp[x + 1] - J.rp[x]);
   uint64_t *D = M.D + static_cast<size_t>(i) * W;
   uint64_t *U = M.rows;
+  o.words = 4 + d + dx + (J.pivot ? 4 : 2) * W;  // row bounds, both lists, the row (and U's) written
   uint32_t cw = 0;
   uint64_t acc = 0;
   auto flush = [&]() {  // word cw of row i is complete
@@ -330,13 +331,15 @@ GTAP_DEV void ks_row(const Params &p, Outcome &o, uint32_t u, uint32_t i) {
 // A vertex with d <= threshold out-neighbours (k >= 4): its matrix in private
 // one-word rows (galloping as the row tasks do), then every edge's search in
 // place: edge i's candidates are row i.
-GTAP_DEV int64_t ks_vertex_in_place(const KsJob &J, uint32_t u, uint32_t d) {
+GTAP_DEV int64_t ks_vertex_in_place(const KsJob &J, uint32_t u, uint32_t d, uint32_t &words) {
   const int32_t *nu = J.col + J.rp[u];
   uint64_t A[kcs::kMaxThr], B[kcs::kMaxThr];
+  words += d;
   for (uint32_t i = 0; i < d; ++i) {
     const int32_t x = nu[i];
     const int32_t *nx = J.col + J.rp[x];
     const uint32_t dx = static_cast<uint32_t>(J.rp[x + 1] - J.rp[x]);
+    words += 2 + dx;
     uint64_t r = 0;
     if (d <= dx) {
       uint32_t t = 0;
@@ -380,12 +383,14 @@ GTAP_DEV void ks_edge(const Params &p, Outcome &o, uint32_t u, uint32_t i) {
   if (J.kk == 1) {
     const int32_t s0 = J.rp[u];
     const int32_t v = J.col[s0 + i];
-    o.value = kcs::isect(J.col + s0, static_cast<uint32_t>(J.rp[u + 1] - s0), J.col + J.rp[v],
-                         static_cast<uint32_t>(J.rp[v + 1] - J.rp[v]), nullptr, 0);
+    const uint32_t du = static_cast<uint32_t>(J.rp[u + 1] - s0), dv = static_cast<uint32_t>(J.rp[v + 1] - J.rp[v]);
+    o.words = 5 + du + dv;
+    o.value = kcs::isect(J.col + s0, du, J.col + J.rp[v], dv, nullptr, 0);
     return;
   }
   const KsMat M = ks_mat(J, u);
   const uint32_t W = M.W;
+  o.words = 4 + 2 * W;  // row bounds, matrix offset, the edge's row
   uint64_t S[kcs::kMaxW];
   uint32_t c = 0;
   for (uint32_t w = 0; w < W; ++w) {
@@ -394,6 +399,7 @@ GTAP_DEV void ks_edge(const Params &p, Outcome &o, uint32_t u, uint32_t i) {
   }
   if (c < J.kk) return;
   if (!J.pivot && J.kk == 2) {  // directed edges inside C
+    o.words += 2 * W * c;  // the candidates' rows
     int64_t e = 0;
     for (uint32_t w = 0; w < W; ++w)
       for (uint64_t t = S[w]; t; t &= t - 1) {
@@ -413,6 +419,7 @@ GTAP_DEV void ks_edge(const Params &p, Outcome &o, uint32_t u, uint32_t i) {
     return;
   }
   uint64_t A[kcs::kMaxThr];
+  o.words += 2 * W * c;  // the candidates' rows
   kcs::compact(M.rows, W, S, A);
   const uint64_t all = kcs::low_mask(c);
   o.value = J.pivot ? kcs::sct_count(A, all, 0, 0, J.kk) : kcs::dag_count(A, all, J.kk);
@@ -432,6 +439,7 @@ GTAP_DEV void ks_heavy(const Params &p, uint32_t *f, Outcome &o, uint32_t u, uin
   }
   uint64_t meta = J.kk;
   uint32_t nchild = c;
+  o.words = 4 + 2 * W + (J.pivot ? 2 * W * (c + 1) + 2 + 4 * W : 2 + 2 * W);  // row; pivot rows; node state
   if (J.pivot) {
     const uint32_t piv = ks_pivot(M.rows, W, P, R);
     meta = static_cast<uint64_t>(piv) << 32;  // no held vertices, no pivots yet
@@ -458,6 +466,7 @@ GTAP_DEV void ks_node(const Params &p, uint32_t *f, Outcome &o, uint32_t u, uint
   const uint64_t meta = co_ld64(pb);
   uint64_t P[kcs::kMaxW], S[kcs::kMaxW], R[kcs::kMaxW];
   for (uint32_t w = 0; w < W; ++w) P[w] = co_ld64(pb + 1 + w);
+  o.words = 6 + 4 * W;  // row bounds, matrix offset, node meta and set, one row
   uint32_t m = 0;
   uint64_t A[kcs::kMaxThr];
   if (!J.pivot) {
@@ -472,6 +481,7 @@ GTAP_DEV void ks_node(const Params &p, uint32_t *f, Outcome &o, uint32_t u, uint
       return;
     }
     if (m < l) return;
+    o.words += 2 * W * m;  // the rows of the node's candidates
     if (l == 2) {  // directed edges inside S
       int64_t e = 0;
       for (uint32_t w = 0; w < W; ++w)
@@ -517,6 +527,7 @@ GTAP_DEV void ks_node(const Params &p, uint32_t *f, Outcome &o, uint32_t u, uint
       return;
     }
     if (m + q < J.kk - h) return;
+    o.words += 2 * W * (m + (j == 0 ? 0 : 1));  // the candidates' rows (and R)
     if (m <= J.thr) {
       kcs::compact(rows, W, S, A);
       o.value = kcs::sct_count(A, kcs::low_mask(m), h, q, J.kk);
@@ -688,6 +699,7 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
       const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 0));
       const uint32_t k = static_cast<uint32_t>(job_arg(p, o.job, 3));
       const uint32_t deg = static_cast<uint32_t>(rp[p0 + 1] - rp[p0]);
+      o.words = 2;
       if (k <= 2) {
         o.value = k == 1 ? 1 : deg;
         return;
@@ -704,12 +716,13 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
       const KsJob J = ks_job(p, o.job);
       if (deg <= J.thr) {  // few out-neighbours: the whole vertex in place, one-word rows
         o.type = OUT_DONE;
-        o.value = ks_vertex_in_place(J, p0, deg);
+        o.value = ks_vertex_in_place(J, p0, deg, o.words);
         return;
       }
       if (J.pivot) {  // U is built by atomic ORs: cleared first
         const KsMat M = ks_mat(J, p0);
         for (uint32_t x = 0; x < deg * M.W; ++x) co_st64(M.rows + x, 0ull);
+        o.words += 2 * deg * M.W;
       }
       o.ckind = TK_KS_ROW;
       return;
