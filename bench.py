@@ -806,7 +806,7 @@ def c0_record(args, gtap, probe, torch, steps, warmup) -> dict:
     want = golden_kclique(C0_TAG, 4)
     if g.checksum() != want["checksum"]:
         raise SystemExit("C0 graph checksum differs from the golden file's")
-    rt = gtap.Runtime(waves_per_group=4, small_frames=1 << 20, big_frames=1 << 16,
+    rt = gtap.Runtime(waves_per_group=4, num_waves=args.c0_waves, small_frames=1 << 20, big_frames=1 << 16,
                       big_frame_ints=max(64, g.max_outdeg), timeout_ms=30000)
     rp, col = torch.as_tensor(g.row_ptr32).cuda(), torch.as_tensor(g.col).cuda()
     el, tot, kms, st = timed_launches(rt, lambda: [rt.submit_kclique(rp, col, 4, max_outdeg=g.max_outdeg)],
@@ -816,7 +816,7 @@ def c0_record(args, gtap, probe, torch, steps, warmup) -> dict:
                        "one task per call, one queue",
            "value": want["count"] * steps / el, "unit": "k-cliques/s", "steps": steps, "warmup": warmup,
            "ms_per_step": 1e3 * el / steps, "count": want["count"], "tasks_per_s": tot["tasks"] / el,
-           "matches_oracle": ok, "roofline": sched_roofline(tot, steps, kms, probe, ""),
+           "waves": st["num_waves"], "matches_oracle": ok, "roofline": sched_roofline(tot, steps, kms, probe, ""),
            "runtime_counters_per_step": {k: v // steps for k, v in tot.items()}}
     rt.close()
     if not args.no_cpu_baseline:
@@ -1209,6 +1209,7 @@ def main() -> int:
     ap.add_argument("--steal-below", type=int, default=64)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run only a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--c0-waves", type=int, default=1024, help="c0: wavefronts of the launch (the job is small)")
     ap.add_argument("--fmm-points", type=int, default=1000000, help="fmm: number of points")
     ap.add_argument("--fmm-wpg", type=int, default=2, help="fmm: wavefronts per workgroup (1, 2, 4)")
     ap.add_argument("--fib-n", type=int, default=35, help="schedulers: fib argument")

@@ -84,14 +84,22 @@ GTAP_DEV uint64_t mix64(uint64_t z) {
 GTAP_DEV uint64_t split_id(uint64_t a, uint64_t i) { return mix64(a + (i + 1) * 0x9E3779B97F4A7C15ull); }
 
 // Geometric child count: leading draws j = 1, 2, ... whose hash is below thr.
+// Four draws per round: they are independent, so their multiply chains
+// overlap; the count is the index of the first failed draw all the same.
 GTAP_DEV uint32_t uts_children(uint64_t id, uint32_t depth, uint64_t thr, uint32_t max_depth) {
   if (depth >= max_depth) return 0;
-  uint32_t c = 0;
-  for (uint64_t j = 1;; ++j) {
-    if (mix64(id ^ (j * 0xD1B54A32D192ED03ull)) < thr) ++c;
-    else break;
+  constexpr uint64_t kStep = 0xD1B54A32D192ED03ull;
+  for (uint32_t c = 0;; c += 4) {
+    const uint64_t j = c + 1;
+    const bool a0 = mix64(id ^ (j * kStep)) < thr;
+    const bool a1 = mix64(id ^ ((j + 1) * kStep)) < thr;
+    const bool a2 = mix64(id ^ ((j + 2) * kStep)) < thr;
+    const bool a3 = mix64(id ^ ((j + 3) * kStep)) < thr;
+    if (!a0) return c;
+    if (!a1) return c + 1;
+    if (!a2) return c + 2;
+    if (!a3) return c + 3;
   }
-  return c;
 }
 
 // First index in the ascending list b[lo, nb) whose element is >= x, by a
