@@ -199,6 +199,11 @@ def _load() -> ctypes.CDLL:
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP runtime first "
             "(python -c 'import __graft_entry__ as g; g.build()')")
+    # PyTorch's wheel carries its own HIP runtime.  Loading it first makes the
+    # library's libamdhip64 dependency resolve to that already-loaded copy, so
+    # the process has one HIP runtime and tensors, streams and this library
+    # share it; loading the library first would map a second runtime.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp = ctypes.c_void_p

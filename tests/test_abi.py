@@ -93,3 +93,17 @@ def test_kclique_split_buffer_size_without_device():
         assert gtap.kclique_split_buffer_ints(d) == 2 + 4 * w
     assert gtap.kclique_split_buffer_ints(-1) == 0 and gtap.kclique_split_buffer_ints(1025) == 0
 
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """Importing the binding before torch maps one HIP runtime, not two (the
+    library resolves its libamdhip64 dependency to the copy torch loaded)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2604_05982_amd import gtap\n"
+            "import torch\n"
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))") % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "1", r.stdout
