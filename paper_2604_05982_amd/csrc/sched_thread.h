@@ -56,6 +56,15 @@ struct WaveLds {
   uint32_t qbase[kMaxQueues];  // running rank per class in the build pass
 };
 
+// The child-generation descriptor of a fork, as make_child() reads it.
+GTAP_DEV Words<6> fork_words(const ForkDesc &dsc) {
+  Words<6> d;
+  d.w[0] = pack(dsc.d0, dsc.d1);
+  d.w[1] = pack(dsc.d2, dsc.d3);
+  d.w[2] = pack(dsc.d4, dsc.ckind_big_d5 >> 8);
+  return d;
+}
+
 // Per-wave statistics: wave-uniform counters kept in registers, added to the
 // control block when the wave leaves.
 struct WaveCounters {
@@ -329,6 +338,10 @@ GTAP_DEV uint32_t pop_batch(const Params &p, WaveLds &L, uint32_t me, uint32_t q
   const uint32_t t = L.tail[q] - static_cast<uint32_t>(claim);
   const uint32_t *ring = deque_ring(p, me, q);
   if (ln >= cnt && ln < cnt + static_cast<uint32_t>(claim)) tid = co_ld32(ring + ((t + ln - cnt) & (p.cap - 1)));
+  // the slot loads return here: left in flight, they would make the next
+  // iteration's first write of this register (the private-stack pop, on
+  // the busy path) wait for every memory operation issued before it
+  asm volatile("" : "+v"(tid));
   wave_sync();
   if (ln == 0) L.tail[q] = t;
   wave_sync();
@@ -737,10 +750,12 @@ GTAP_DEV uint32_t admit_jobs(const Params &p, WaveLds &L, uint32_t me, PoolView 
 }
 
 // Capacity of a wavefront's private LDS task stack (task images, 32 bytes
-// each): 16 KB per wavefront, 4 KB with eight wavefronts per workgroup.
+// each): 16 KB per wavefront, 8 KB with eight wavefronts per workgroup (the
+// largest power of two with which one such workgroup, 147 KB of LDS, still
+// fits a compute unit's 160 KB).
 template <int WPB>
 struct LocalCap {
-  static constexpr uint32_t v = WPB >= 8 ? 128u : 512u;
+  static constexpr uint32_t v = WPB >= 8 ? 256u : 512u;
 };
 
 // V selects the queue management (kSchedBatched, kSchedSingle, kSchedCentral;
@@ -830,6 +845,10 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   uint32_t pend_len = 0, pend_par = kNone;
   auto examine = [&]() {
     drain();
+    // both halves of the RMW result stay allocated until here (only the low
+    // half is examined; a register reused for anything else before this point
+    // would have to wait for the RMW first)
+    asm volatile("" : : "v"(pend_old));
     const bool resumed = pend_tail && (static_cast<uint64_t>(pend_old) & kJoinMask) == pend_len;
     const uint64_t m_res = ballot(resumed);
     wave_sync();
@@ -1076,11 +1095,14 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       drain();  // the large result is in place before the count can reach zero
     }
     wc.add(ST_RMW, static_cast<uint32_t>(__popcll(ballot(tail))) + static_cast<uint32_t>(__popcll(big_lanes)));
-    int64_t join_old = 0;
+    // The RMW returns straight into the register examine() reads next
+    // iteration (pend_old is dead from here on): a register copy of the
+    // result at the end of the iteration would make the wavefront wait for
+    // the RMW, and every store issued after it, there.
     if (tail) {
       const int64_t delta = (big_val ? 0 : run_val * (static_cast<int64_t>(1) << kJoinBits)) -
                             static_cast<int64_t>(run_len);
-      join_old = fetch_add_relaxed(join_ptr(frame_ptr(p, o.parent)), delta);
+      pend_old = fetch_add_relaxed(join_ptr(frame_ptr(p, o.parent)), delta);
     }
     const uint32_t pend_par_next = o.parent;
     if (ballot(root_done)) {
@@ -1145,7 +1167,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         if (g < F) {
           const uint32_t own = owner_of(L.offs, g);
           const ForkDesc dsc = L.desc[own];
-          const uint32_t d[6] = {dsc.d0, dsc.d1, dsc.d2, dsc.d3, dsc.d4, dsc.ckind_big_d5 >> 8};
+          const Words<6> d = fork_words(dsc);
           ChildInit ci;
           make_child<kExt>(dsc.ckind_big_d5 & 0x7Fu, d, g - L.offs[own], ci);
           c = child_class<kExt>(p, dsc.job, dsc.ckind_big_d5 & 0x7Fu, ci);
@@ -1256,7 +1278,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
         own = owner_of(L.offs, g);
         j = g - L.offs[own];
         dsc = L.desc[own];
-        const uint32_t d[6] = {dsc.d0, dsc.d1, dsc.d2, dsc.d3, dsc.d4, dsc.ckind_big_d5 >> 8};
+        const Words<6> d = fork_words(dsc);
         make_child<kExt>(dsc.ckind_big_d5 & 0x7Fu, d, j, ci);
         if (p.Q > 1) c = g < kClassCache ? L.cls[g] : child_class<kExt>(p, dsc.job, dsc.ckind_big_d5 & 0x7Fu, ci);
       }
@@ -1374,7 +1396,6 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     npend = 0;  // staged above
     pend_any = true;
     pend_tail = tail;
-    pend_old = join_old;
     pend_len = run_len;
     pend_par = pend_par_next;
     // serving: live-frame deltas reach the shared counters in batches (two

@@ -25,12 +25,36 @@ namespace gtap {
 
 enum OutType : uint32_t { OUT_NONE = 0, OUT_DONE = 1, OUT_FORK = 2 };
 
+// N 32-bit words kept in aligned 64-bit slots.  Every access is a whole-slot
+// read or read-modify-write, so no two accesses to the array partly overlap
+// (the optimizer merges two adjacent 32-bit stores of one 64-bit value into a
+// single 64-bit store; at an odd word offset that overlaps two slots and keeps
+// the array in memory -- here it would go to LDS -- instead of registers).
+template <uint32_t N>
+struct Words {
+  uint64_t w[(N + 1) / 2];
+  struct Ref {
+    uint64_t &s;
+    uint32_t hi;
+    GTAP_DEV operator uint32_t() const { return static_cast<uint32_t>(hi ? (s >> 32) : s); }
+    GTAP_DEV Ref &operator=(uint32_t v) {
+      s = hi ? ((s & 0xFFFFFFFFull) | (static_cast<uint64_t>(v) << 32)) : ((s & ~0xFFFFFFFFull) | v);
+      return *this;
+    }
+    GTAP_DEV Ref &operator=(const Ref &r) { return *this = static_cast<uint32_t>(r); }
+  };
+  GTAP_DEV Ref operator[](uint32_t i) { return Ref{w[i >> 1], i & 1u}; }
+  GTAP_DEV uint32_t operator[](uint32_t i) const {
+    return static_cast<uint32_t>((i & 1u) ? (w[i >> 1] >> 32) : w[i >> 1]);
+  }
+};
+
 struct Outcome {
   uint32_t type;
   uint32_t nchild;   // OUT_FORK: number of children
   uint32_t big;      // OUT_FORK: children need big frames
   uint32_t ckind;    // OUT_FORK: children's task kind
-  uint32_t d[6];     // OUT_FORK: child-generation descriptor
+  Words<6> d;        // OUT_FORK: child-generation descriptor
   int64_t value;     // OUT_DONE: return value
   uint32_t parent;   // parent task ID (kNone for a root)
   uint32_t job;
@@ -43,7 +67,7 @@ struct Outcome {
 
 // Payload of a new frame (words 3..7).
 struct ChildInit {
-  uint32_t p[kPayloadWords];
+  Words<kPayloadWords> p;
 };
 
 GTAP_DEV uint32_t *frame_ptr(const Params &p, uint32_t tid) {
@@ -981,7 +1005,7 @@ GTAP_DEV uint32_t nth_set_bit(uint32_t m, uint32_t j) {
 // Payload of child j of a forked parent with child kind `ckind` and
 // descriptor d.
 template <bool kExt = false>
-GTAP_DEV void make_child(uint32_t ckind, const uint32_t *d, uint32_t j, ChildInit &c) {
+GTAP_DEV void make_child(uint32_t ckind, const Words<6> &d, uint32_t j, ChildInit &c) {
   for (uint32_t i = 0; i < kPayloadWords; ++i) c.p[i] = 0;
   if constexpr (kExt) {
     if (ckind == TK_SORT) {  // half j into the other buffer
