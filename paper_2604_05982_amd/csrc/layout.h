@@ -142,6 +142,8 @@ struct alignas(128) Control {
   int64_t live_small;       // serving: frames handed out and not yet returned
   int64_t live_big;
   uint64_t pad5[14];
+  int32_t hungry;           // thread mode: wavefronts that found no work (a hint for exposure)
+  int32_t pad6[31];
   uint64_t stats[ST_COUNT];
 };
 

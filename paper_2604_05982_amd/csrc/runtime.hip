@@ -190,6 +190,7 @@ __global__ void reset_kernel(Params p, uint32_t ndeques) {
     c->admitted = 0;
     c->live_small = 0;
     c->live_big = 0;
+    c->hungry = 0;
     for (int s = 0; s < static_cast<int>(ST_COUNT); ++s) c->stats[s] = 0;
   }
 }

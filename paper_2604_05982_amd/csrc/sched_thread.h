@@ -771,7 +771,8 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   // Private task stack: children a wavefront cannot run in its lanes this
   // iteration stay here as frameless images and are popped (newest first)
   // before the shared deque; only the oldest are exposed to thieves, with
-  // frames, when the stack overflows or the wavefront's deque runs dry.
+  // frames, when the stack overflows or when the wavefront's deque runs dry
+  // while another wavefront is looking for work.
   constexpr uint32_t LC = LocalCap<WPB>::v;
   __shared__ uint4 lstk_all[WPB][2 * LC];
   const uint32_t wv = threadIdx.x >> 6;
@@ -827,6 +828,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
 
   uint32_t idle = 0;
   uint32_t iter = 0;
+  bool hungry = false;  // counted in the control block's hungry-wavefront hint
   bool tcont = false;  // this lane's task is a resumed parent (runs its continuation)
   fmm::ListChunks lchunks{nullptr, {0, 0}, {fmm::kListChunk, fmm::kListChunk}};  // FMM list traversal only
   uint64_t t_loop = clock64();
@@ -943,6 +945,10 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     if (cnt == 0) {
       ++idle;
       wc.add(ST_IDLE, 1);
+      if (!hungry) {
+        if (ln == 0) fetch_add_relaxed(&p.ctl->hungry, 1);
+        hungry = true;
+      }
       // termination: every root completed (the implicit join at each task's
       // end makes a root the last task of its job), an error, or the watchdog
       uint32_t stop = 0;
@@ -970,6 +976,10 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       continue;
     }
     idle = 0;
+    if (hungry) {
+      if (ln == 0) fetch_add_relaxed(&p.ctl->hungry, -1);
+      hungry = false;
+    }
     ++iter;
     if (p.Q > 1 && (iter & 7u) == 0) {
       // DAQ queue pressure: tasks waiting in this wavefront's class queues
@@ -1193,7 +1203,8 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     const uint32_t keep = (kWave - nres) < nR ? (kWave - nres) : nR;
     // ---- private stack (one queue): small children beyond the lanes stay in
     // LDS; the oldest entries are exposed when it would overflow, or when the
-    // wavefront's own deque has run dry (thieves then find work) ----
+    // wavefront's own deque has run dry and some wavefront has found no work
+    // (thieves then find some) ----
     const bool use_local = !kNoLocal && (p.Q == 1);
     uint32_t E = 0, direct = 0, nsmall = 0;
     if (use_local) {
@@ -1202,9 +1213,13 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       uint32_t ex = (have + nsmall > LC) ? (have + nsmall - LC) : 0u;
       if (ex > have) ex = have;
       if ((iter & 7u) == 0 && have >= 2 * kWave) {
+        // half the stack goes to the deque when it runs low and some
+        // wavefront is looking for work (both words read in one round trip)
         int32_t c = 0;
         if (ln == 0) c = ld_relaxed(&deque_meta(p, me, 0)->count);
-        if (uniform(c) < static_cast<int32_t>(kWave) && have / 2 > ex) ex = have / 2;
+        if (ln == 1) c = ld_relaxed(&p.ctl->hungry);
+        const int32_t own = __builtin_amdgcn_readlane(c, 0), seekers = __builtin_amdgcn_readlane(c, 1);
+        if (own < static_cast<int32_t>(kWave) && seekers > 0 && have / 2 > ex) ex = have / 2;
       }
       E = ex;
       const uint32_t free_slots = LC - (have - E);
