@@ -43,7 +43,6 @@ struct alignas(16) ForkDesc {
 struct WaveLds {
   uint32_t stk_s[kStackSmall];
   uint32_t stk_b[kStackBig];
-  uint32_t offs[kWave + 1];
   ForkDesc desc[kWave];
   uint32_t res[kWave];         // parents resumed last iteration, staged this one
   uint32_t next_tid[kWave];    // retained children, by lane, for the next iteration
@@ -54,6 +53,7 @@ struct WaveLds {
   uint32_t head_seen[kMaxQueues];  // last head read by the owner (a lower bound)
   uint32_t qn[kMaxQueues];     // children per class this iteration
   uint32_t qbase[kMaxQueues];  // running rank per class in the build pass
+  uint32_t mark[kWave];        // chunk_owner: forking lane + 1 at the slot of its first child
 };
 
 // The child-generation descriptor of a fork, as make_child() reads it.
@@ -606,15 +606,24 @@ GTAP_DEV int32_t central_pop(const Params &p, uint32_t me, uint32_t cnt, uint32_
 }
 
 // ---------------------------------------------------------------------------
-// Largest index l in [0,64) with offs[l] <= g (offs ascending, offs[64] = F > g).
-GTAP_DEV uint32_t owner_of(const uint32_t *offs, uint32_t g) {
-  uint32_t lo = 0, hi = kWave;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (offs[mid] <= g) lo = mid;
-    else hi = mid;
-  }
-  return lo;
+// Owner (forking lane) of child g0 + lane, for one 64-child chunk of a
+// wavefront's forks: each forking lane whose first child falls in the chunk
+// marks that slot, and a prefix maximum over the lanes carries every mark to
+// the children after it; `carry` holds the owner of the chunk's first child
+// when no mark precedes it (the previous chunk's last owner) and is updated.
+// One LDS round trip instead of a binary search over the offsets.  Must be
+// called with every lane active.
+GTAP_DEV uint32_t chunk_owner(uint32_t *mark, uint32_t nchild, uint32_t off, uint32_t g0, uint32_t &carry) {
+  const uint32_t ln = lane_id();
+  mark[ln] = 0;
+  wave_sync();
+  if (nchild > 0 && off >= g0 && off - g0 < kWave) mark[off - g0] = ln + 1;
+  wave_sync();
+  const uint32_t m = wave_inclusive_max(mark[ln]);
+  const uint32_t own = m ? m - 1 : carry;
+  carry = __builtin_amdgcn_readlane(own, 63);
+  wave_sync();
+  return own;
 }
 
 // Root frame of job slot j (payload from the job's arguments).
@@ -1135,8 +1144,6 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     const uint32_t off = wave_exclusive_scan(fork ? o.nchild : 0u, &F);
     const uint64_t m_self = ballot(need_self);
     const uint32_t nres = npend;
-    L.offs[ln] = off;
-    if (ln == 0) L.offs[kWave] = F;
     AllocResult aself;
     if (!alloc_frames(p, PS, me, __popcll(m_self), aself, wc)) break;
     wave_sync();
@@ -1171,15 +1178,17 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     if (p.Q > 1 && F > 0) {
       if (ln < kMaxQueues) L.qn[ln] = 0;
       wave_sync();
+      uint32_t own_carry = 0;
       for (uint32_t g0 = 0; g0 < F; g0 += kWave) {
         const uint32_t g = g0 + ln;
+        const uint32_t own = chunk_owner(L.mark, fork ? o.nchild : 0u, off, g0, own_carry);
+        const uint32_t own_off = static_cast<uint32_t>(__shfl(static_cast<int>(off), static_cast<int>(own), 64));
         uint32_t c = kNone;
         if (g < F) {
-          const uint32_t own = owner_of(L.offs, g);
           const ForkDesc dsc = L.desc[own];
           const Words<6> d = fork_words(dsc);
           ChildInit ci;
-          make_child<kExt>(dsc.ckind_big_d5 & 0x7Fu, d, g - L.offs[own], ci);
+          make_child<kExt>(dsc.ckind_big_d5 & 0x7Fu, d, g - own_off, ci);
           c = child_class<kExt>(p, dsc.job, dsc.ckind_big_d5 & 0x7Fu, ci);
           if (g < kClassCache) L.cls[g] = static_cast<uint8_t>(c);
         }
@@ -1283,15 +1292,17 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     if (ln < kMaxQueues) L.qbase[ln] = 0;
     wave_sync();
     bool alloc_ok = true;
+    uint32_t own_carry = 0;
     for (uint32_t g0 = 0; g0 < F; g0 += kWave) {
       const uint32_t g = g0 + ln;
       const bool act = g < F;
-      uint32_t own = 0, j = 0, c = 0;
+      const uint32_t own = chunk_owner(L.mark, fork ? o.nchild : 0u, off, g0, own_carry);
+      const uint32_t own_off = static_cast<uint32_t>(__shfl(static_cast<int>(off), static_cast<int>(own), 64));
+      uint32_t j = 0, c = 0;
       ForkDesc dsc{};
       ChildInit ci;
       if (act) {
-        own = owner_of(L.offs, g);
-        j = g - L.offs[own];
+        j = g - own_off;
         dsc = L.desc[own];
         const Words<6> d = fork_words(dsc);
         make_child<kExt>(dsc.ckind_big_d5 & 0x7Fu, d, j, ci);
