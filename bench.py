@@ -1042,6 +1042,18 @@ def c4_record(args, gtap, g, probe, torch, steps, warmup, say) -> dict:
                                       steps, warmup, check, torch)
     say(f"C4 batched: {steps} steps, {el / steps:.2f} s per step")
     headroom = int(tuned["small_frames"]) // 4
+    if args.c4_batched_only:
+        # counter runs: the tuned batched launches alone (one launch per job
+        # under per-dispatch counter collection would take minutes)
+        rt.close()
+        del cal_keep, keep
+        return {"value": n_jobs * steps / el, "unit": "jobs/s", "steps": steps, "warmup": warmup,
+                "ms_per_step": 1e3 * el / steps, "batched_only": True,
+                "tasks_per_step": tot["tasks"] // steps, "tasks_per_s": tot["tasks"] / el,
+                "kernel_ms": sum(kms) / len(kms), "matches_oracle": golden is not None,
+                "autotune": {"chosen": {k: v for k, v in tuned.items() if not isinstance(v, (list, tuple))}},
+                "roofline": sched_roofline(tot, steps, kms, probe, "serving"),
+                "runtime_counters_per_step": {k: v // steps for k, v in tot.items()}}
 
     def served(arrivals):
         jobs = rt.trace([(t, e) for t, e in zip(arrivals, entries)])
@@ -1228,6 +1240,8 @@ def main() -> int:
     ap.add_argument("--jobs", type=int, default=20000, help="serving: jobs in the trace")
     ap.add_argument("--inflight", type=int, default=4096, help="serving: admission limit")
     ap.add_argument("--calib-jobs", type=int, default=400, help="serving: autotuner calibration jobs")
+    ap.add_argument("--c4-batched-only", action="store_true",
+                    help="c4: only the autotuner and the batched launches (for counter runs)")
     ap.add_argument("--sweep", action="store_true", help="serving: also rho 0.3/0.5/0.7/0.9")
     ap.add_argument("--queues", type=int, default=1, help="kclique7: DAQ queues (1 = off)")
     ap.add_argument("--kclique-split", default="none", choices=("none", "orient", "pivot"),
