@@ -193,13 +193,14 @@ def test_adversarial_configs(gtap, opts):
 
 
 def test_small_deques_wrap_around(gtap):
-    """Two waves with 4096-slot rings: more IDs pass through the rings than
-    they hold, so slots are reused after wrap-around."""
+    """Two waves with 1024-slot rings: more IDs pass through the rings than
+    they hold (about 4,100 for fib(33)), so slots are reused after
+    wrap-around."""
     say("small deques wrap around")
-    with make_rt(gtap, num_waves=2, waves_per_group=2, deque_capacity=4096) as r:
-        got, st = run_single(r, r.submit_fib, 31)
-        check(got, st, oracle.fib(31))
-        assert st["pushed"] > 2 * 4096
+    with make_rt(gtap, num_waves=2, waves_per_group=2, deque_capacity=1024) as r:
+        got, st = run_single(r, r.submit_fib, 33)
+        check(got, st, oracle.fib(33))
+        assert st["pushed"] > 2 * 1024
         assert st["local_pushed"] > 0
 
 
