@@ -1049,6 +1049,7 @@ def c4_record(args, gtap, g, probe, torch, steps, warmup, say) -> dict:
         del cal_keep, keep
         return {"value": n_jobs * steps / el, "unit": "jobs/s", "steps": steps, "warmup": warmup,
                 "ms_per_step": 1e3 * el / steps, "batched_only": True,
+                "workload": f"{n_jobs} jobs, trace seed 5, the tuned batched launches alone",
                 "tasks_per_step": tot["tasks"] // steps, "tasks_per_s": tot["tasks"] / el,
                 "kernel_ms": sum(kms) / len(kms), "matches_oracle": golden is not None,
                 "autotune": {"chosen": {k: v for k, v in tuned.items() if not isinstance(v, (list, tuple))}},
