@@ -61,7 +61,6 @@ struct BlockLds {
   int32_t rec[10][fmm::kCellInts];
   uint32_t pid[8][2];
   uint8_t prec[8][2];
-  uint32_t cbr[8];              // branch of child c: 0 split again, 1 M2L, 2 P2P
   uint32_t n_m2l, n_p2p, m2l_idx[8], p2p_idx[8];
   uint32_t split_a;
   // P2P batch: target point ranges x source point ranges (one side is one cell)
@@ -74,6 +73,8 @@ struct BlockLds {
     double red[kMaxBlockThreads];  // P2P: partial sums of the source groups
   };
   double QBc[8][fmm::kNc];      // source moments of the M2L pairs
+  double dl[8][4];              // M2L pair i: centre difference A - B and its squared length
+  uint32_t dmt[fmm::kNc][2];    // Taylor recursion indices of coefficient t: g - e_c (byte c of [0]), g - 2 e_c ([1])
   uint4 lstk[2 * kBlkLocal];    // private stack (frame words 0..7 of each task)
   uint32_t lbot, ltop, local, dry;
   // M2L term table, copied once per workgroup:
@@ -180,6 +181,7 @@ struct FmmCounters {
   uint32_t job;
   uint64_t m2l, p2p, m2l_hash, p2p_hash, inter;
   const fmm::FmmDesc *desc;  // descriptor of `job` (read once per job)
+  int64_t ta, tb;            // its MAC parameter theta = ta / tb
 };
 
 GTAP_DEV void fmm_flush(const Params &p, FmmCounters &fc) {
@@ -192,7 +194,7 @@ GTAP_DEV void fmm_flush(const Params &p, FmmCounters &fc) {
     if (fc.p2p_hash) fetch_add_relaxed(&D->p2p_hash, fc.p2p_hash);
     if (fc.inter) fetch_add_relaxed(&D->p2p_inter, fc.inter);
   }
-  fc = FmmCounters{kNone, 0, 0, 0, 0, 0, nullptr};
+  fc = FmmCounters{kNone, 0, 0, 0, 0, 0, nullptr, 0, 1};
 }
 
 // Lane k's value of x (k wave-uniform), read through two 32-bit lane reads.
@@ -215,8 +217,8 @@ static_assert(m2l_coefficients_fit_int8(), "the M2L term table packs its coeffic
 
 // Branch of the pair of cell records (A, B): 1 accept (M2L), 2 both leaves
 // (P2P), 0 split.
-GTAP_DEV uint32_t fmm_branch(const int32_t *A, const int32_t *B, const fmm::FmmDesc *D) {
-  if (fmm::mac_accept(A, B, D->ta, D->tb)) return 1;
+GTAP_DEV uint32_t fmm_branch(const int32_t *A, const int32_t *B, const FmmCounters &fc) {
+  if (fmm::mac_accept(A, B, fc.ta, fc.tb)) return 1;
   return (A[7] == 0 && B[7] == 0) ? 2u : 0u;
 }
 
@@ -267,33 +269,50 @@ GTAP_DEV void fmm_m2l_batch(const Params &p, BlockLds &S, const fmm::FmmDesc *D,
   if (tx < n) {
     double d0, d1, d2;
     delta(tx, d0, d1, d2);
-    S.Tc[tx][0] = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    S.dl[tx][0] = d0;
+    S.dl[tx][1] = d1;
+    S.dl[tx][2] = d2;
+    S.dl[tx][3] = r2;
+    S.Tc[tx][0] = 1.0 / sqrt(r2);
   }
   __syncthreads();
-  for (int deg = 1; deg <= fmm::kP; ++deg) {
-    const uint32_t lo = static_cast<uint32_t>(fmm::ncoef(deg - 1)), nd = static_cast<uint32_t>(fmm::ncoef(deg)) - lo;
-    for (uint32_t x = tx; x < n * nd; x += NT) {
-      const uint32_t i = x / nd, t = lo + (x - i * nd);
-      double dd[3];
-      delta(i, dd[0], dd[1], dd[2]);
-      const double r2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
-      double s1 = 0.0, s2 = 0.0;
+  // Degree by degree; wavefront w takes the pairs w, w + G, ..., so every
+  // coefficient a lane reads was written by its own wavefront in an earlier
+  // degree (LDS accesses of one wavefront complete in order): one barrier
+  // after the last degree instead of one per degree.
+  {
+    constexpr uint32_t G = NT / kWave;
+    const uint32_t wv = tx / kWave, ln = tx % kWave;
+    const uint32_t nw = n > wv ? (n - wv + G - 1) / G : 0u;
+    for (int deg = 1; deg <= fmm::kP; ++deg) {
+      const uint32_t lo = static_cast<uint32_t>(fmm::ncoef(deg - 1)), nd = static_cast<uint32_t>(fmm::ncoef(deg)) - lo;
+      for (uint32_t x = ln; x < nw * nd; x += kWave) {
+        const uint32_t ii = x / nd, t = lo + (x - ii * nd);
+        const uint32_t i = wv + ii * G;
+        const uint32_t m1w = S.dmt[t][0], m2w = S.dmt[t][1];
+        double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const uint8_t m1 = fmm::kTab.dm1[t][c], m2 = fmm::kTab.dm2[t][c];
-        if (m1 != 0xFF) s1 += dd[c] * S.Tc[i][m1];
-        if (m2 != 0xFF) s2 += S.Tc[i][m2];
+        for (int c = 0; c < 3; ++c) {
+          const uint32_t m1 = (m1w >> (8 * c)) & 0xFFu, m2 = (m2w >> (8 * c)) & 0xFFu;
+          if (m1 != 0xFFu) s1 += S.dl[i][c] * S.Tc[i][m1];
+          if (m2 != 0xFFu) s2 += S.Tc[i][m2];
+        }
+        S.Tc[i][t] = -((2.0 * deg - 1.0) * s1 + (deg - 1.0) * s2) / (deg * S.dl[i][3]);
       }
-      S.Tc[i][t] = -((2.0 * deg - 1.0) * s1 + (deg - 1.0) * s2) / (deg * r2);
+      wave_sync();
     }
-    __syncthreads();
   }
+  __syncthreads();
+  // Consecutive pairs with the same target (all of them when the split took
+  // the source side) share one pass over the terms: each term adds its
+  // coefficient times the sum over those pairs.
   constexpr uint32_t C = (fmm::kM2LTerms + NT - 1) / NT;
-  for (uint32_t i = 0; i < n; ++i) {
-    const uint32_t k = S.m2l_idx[i];
-    const uint32_t a = S.pid[k][0], b = S.pid[k][1];
+  for (uint32_t i = 0; i < n;) {
+    const uint32_t a = S.pid[S.m2l_idx[i]][0];
+    uint32_t j = i + 1;
+    while (j < n && S.pid[S.m2l_idx[j]][0] == a) ++j;
     fmm_target<NT>(S, D, a, true);
-    const double *T = S.Tc[i], *QB = S.QBc[i];
     uint32_t cur = 0xFFu;
     double acc = 0.0;
 #pragma unroll
@@ -305,13 +324,20 @@ GTAP_DEV void fmm_m2l_batch(const Params &p, BlockLds &S, const fmm::FmmDesc *D,
         acc = 0.0;
         cur = at;
       }
-      if (at != 0xFFu)
-        acc += static_cast<double>(static_cast<int8_t>(w >> 24)) * T[(w >> 16) & 0xFFu] * QB[(w >> 8) & 0xFFu];
+      if (at != 0xFFu) {
+        const uint32_t g = (w >> 16) & 0xFFu, bq = (w >> 8) & 0xFFu;
+        double sum = 0.0;
+        for (uint32_t q = i; q < j; ++q) sum += S.Tc[q][g] * S.QBc[q][bq];
+        acc += static_cast<double>(static_cast<int8_t>(w >> 24)) * sum;
+      }
     }
     if (cur != 0xFFu) atomicAdd(&S.lacc[cur], acc);
-    fc.m2l += 1;
-    fc.m2l_hash += fmm::pair_hash(a, b);
+    for (uint32_t q = i; q < j; ++q) {
+      fc.m2l += 1;
+      fc.m2l_hash += fmm::pair_hash(a, S.pid[S.m2l_idx[q]][1]);
+    }
     __syncthreads();  // the sums are complete before a change of target adds them to memory
+    i = j;
   }
 }
 
@@ -328,30 +354,48 @@ GTAP_DEV void fmm_p2p_batch(BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc)
   const uint32_t tx = threadIdx.x;
   const uint32_t n = S.n_p2p;
   if (n == 0) return;
-  if (tx == 0) {
-    // ranges: the shared cell once, the other side per pair
-    uint32_t nt = 0, ns = 0;
-    for (uint32_t q = 0; q < n; ++q) {
-      const uint32_t k = S.p2p_idx[q];
-      const int32_t *A = S.rec[S.prec[k][0]], *B = S.rec[S.prec[k][1]];
+  if (tx < kWave) {
+    // ranges, pair q on lane q of wavefront 0: the shared cell once (from the
+    // first pair), the other side per pair, compacted in pair order
+    const bool act = tx < n;
+    const int32_t *A = S.rec[0], *B = S.rec[0];
+    bool ft = false, fs = false;
+    uint64_t h = 0, in = 0;
+    if (act) {
+      const uint32_t k = S.p2p_idx[tx], k0 = S.p2p_idx[0];
+      A = S.rec[S.prec[k][0]];
+      B = S.rec[S.prec[k][1]];
       const uint32_t a = S.pid[k][0], b = S.pid[k][1];
-      if (q == 0 || S.prec[k][0] != S.prec[S.p2p_idx[0]][0]) {
-        S.tr_b[nt] = A[4];
-        S.tr_n[nt] = A[5] - A[4];
-        ++nt;
-      }
-      if (q == 0 || S.prec[k][1] != S.prec[S.p2p_idx[0]][1]) {
-        S.sr_b[ns] = B[4];
-        S.sr_n[ns] = B[5] - B[4];
-        ++ns;
-      }
+      ft = tx == 0 || S.prec[k][0] != S.prec[k0][0];
+      fs = tx == 0 || S.prec[k][1] != S.prec[k0][1];
       const int64_t na = A[5] - A[4], nb = B[5] - B[4];
-      fc.p2p += 1;
-      fc.p2p_hash += fmm::pair_hash(a, b);
-      fc.inter += static_cast<uint64_t>(na * nb - (a == b ? na : 0));
+      h = fmm::pair_hash(a, b);
+      in = static_cast<uint64_t>(na * nb - (a == b ? na : 0));
     }
-    S.nt = nt;
-    S.ns = ns;
+    const uint64_t mt = ballot(ft), ms = ballot(fs);
+    if (ft) {
+      const uint32_t r = rank_below(mt);
+      S.tr_b[r] = A[4];
+      S.tr_n[r] = A[5] - A[4];
+    }
+    if (fs) {
+      const uint32_t r = rank_below(ms);
+      S.sr_b[r] = B[4];
+      S.sr_n[r] = B[5] - B[4];
+    }
+    const uint64_t hs = wave_inclusive_sum64(h), is = wave_inclusive_sum64(in);
+    const uint64_t hsum = (static_cast<uint64_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(hs >> 32), 63)) << 32) |
+                          __builtin_amdgcn_readlane(static_cast<uint32_t>(hs), 63);
+    const uint64_t isum = (static_cast<uint64_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(is >> 32), 63)) << 32) |
+                          __builtin_amdgcn_readlane(static_cast<uint32_t>(is), 63);
+    if (tx == 0) {
+      // thread 0 keeps the job's statistics
+      fc.p2p += n;
+      fc.p2p_hash += hsum;
+      fc.inter += isum;
+      S.nt = __popcll(mt);
+      S.ns = __popcll(ms);
+    }
   }
   __syncthreads();
   constexpr uint32_t G = NT / kP2PTile;
@@ -447,6 +491,8 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
     fmm_flush(p, fc);
     fc.job = job;
     fc.desc = reinterpret_cast<const fmm::FmmDesc *>(co_ld64(&p.jobs[job].a[0]));
+    fc.ta = fc.desc->ta;
+    fc.tb = fc.desc->tb;
   }
   const fmm::FmmDesc *D = fc.desc;
   if (tx < fmm::kCellInts) {
@@ -457,7 +503,7 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
   uint32_t k = 0;
   if (tx == 0) {
     const int32_t *A = S.rec[0], *B = S.rec[1];
-    const uint32_t br = fmm_branch(A, B, D);
+    const uint32_t br = fmm_branch(A, B, fc);
     S.n_m2l = 0;
     S.n_p2p = 0;
     S.pid[0][0] = a;
@@ -498,23 +544,26 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
       S.rec[2 + c][w] = D->cell[static_cast<size_t>(cell) * fmm::kCellInts + w];
     }
     __syncthreads();
-    if (tx < k) S.cbr[tx] = fmm_branch(S.rec[S.prec[tx][0]], S.rec[S.prec[tx][1]], D);
-    __syncthreads();
-    if (tx == 0) {
-      uint32_t nf = 0, nm = 0, np = 0;
-      for (uint32_t c = 0; c < k; ++c) {
-        const uint32_t br = S.cbr[c];
-        if (br == 1) S.m2l_idx[nm++] = c;
-        else if (br == 2) S.p2p_idx[np++] = c;
-        else {
-          S.child[nf][0] = S.pid[c][0];
-          S.child[nf][1] = S.pid[c][1];
-          ++nf;
-        }
+    // child c's branch on lane c of wavefront 0; ballots compact the M2L,
+    // P2P and split-again lists in child order
+    if (tx < kWave) {
+      const bool act = tx < k;
+      const uint32_t br = act ? fmm_branch(S.rec[S.prec[tx][0]], S.rec[S.prec[tx][1]], fc) : 3u;
+      const uint64_t mm = ballot(br == 1), mp = ballot(br == 2), mf = ballot(br == 0);
+      if (br == 1) {
+        S.m2l_idx[rank_below(mm)] = tx;
+      } else if (br == 2) {
+        S.p2p_idx[rank_below(mp)] = tx;
+      } else if (br == 0) {
+        const uint32_t f = rank_below(mf);
+        S.child[f][0] = S.pid[tx][0];
+        S.child[f][1] = S.pid[tx][1];
       }
-      S.n_m2l = nm;
-      S.n_p2p = np;
-      S.nchild = nf;
+      if (tx == 0) {
+        S.n_m2l = __popcll(mm);
+        S.n_p2p = __popcll(mp);
+        S.nchild = __popcll(mf);
+      }
     }
     __syncthreads();
   }
@@ -547,7 +596,7 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
               p.bincap_b, &p.ctl->bump_big, p.nframes_b, kBigBit, 1};
   WaveCounters wc;
   for (int i = 0; i < static_cast<int>(ST_COUNT); ++i) wc.v[i] = 0;
-  FmmCounters fc{kNone, 0, 0, 0, 0, 0, nullptr};
+  FmmCounters fc{kNone, 0, 0, 0, 0, 0, nullptr, 0, 1};
   uint32_t rng = 0x9E3779B9u ^ (me * 0x85EBCA6Bu + 1u);
   uint64_t t_loop = clock64(), busy_cycles = 0, idle_cycles = 0;
   if (tx == 0) {
@@ -575,7 +624,11 @@ __global__ __launch_bounds__(NT) void block_sched_kernel(Params p) {
       S.mab[r * NT + tx] = w;
     }
   }
-  for (uint32_t t = tx; t < static_cast<uint32_t>(fmm::kNc); t += NT) S.lacc[t] = 0.0;
+  for (uint32_t t = tx; t < static_cast<uint32_t>(fmm::kNc); t += NT) {
+    S.lacc[t] = 0.0;
+    S.dmt[t][0] = fmm::kTab.dm1[t][0] | (fmm::kTab.dm1[t][1] << 8) | (fmm::kTab.dm1[t][2] << 16);
+    S.dmt[t][1] = fmm::kTab.dm2[t][0] | (fmm::kTab.dm2[t][1] << 8) | (fmm::kTab.dm2[t][2] << 16);
+  }
   for (uint32_t t = tx; t < kP2PTile; t += NT) S.pacc[t] = 0.0;
   if (tx == 0) {
     S.lcell = kNone;
