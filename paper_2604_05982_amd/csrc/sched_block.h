@@ -384,10 +384,7 @@ GTAP_DEV void fmm_p2p_batch(BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc)
       S.sr_n[r] = B[5] - B[4];
     }
     const uint64_t hs = wave_inclusive_sum64(h), is = wave_inclusive_sum64(in);
-    const uint64_t hsum = (static_cast<uint64_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(hs >> 32), 63)) << 32) |
-                          __builtin_amdgcn_readlane(static_cast<uint32_t>(hs), 63);
-    const uint64_t isum = (static_cast<uint64_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(is >> 32), 63)) << 32) |
-                          __builtin_amdgcn_readlane(static_cast<uint32_t>(is), 63);
+    const uint64_t hsum = readlane64(hs, 63), isum = readlane64(is, 63);
     if (tx == 0) {
       // thread 0 keeps the job's statistics
       fc.p2p += n;

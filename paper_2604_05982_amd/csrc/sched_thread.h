@@ -1442,9 +1442,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   if constexpr (kExt) fmm::chunks_close(lchunks);
   // ---- flush counters ----
   const uint64_t wave_words = wave_inclusive_sum64(data_words);
-  const uint64_t words_total =
-      (static_cast<uint64_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(wave_words >> 32), 63)) << 32) |
-      __builtin_amdgcn_readlane(static_cast<uint32_t>(wave_words), 63);
+  const uint64_t words_total = readlane64(wave_words, 63);
   if (ln == 0) {
     if (words_total) fetch_add_relaxed(&p.ctl->stats[ST_DATA_WORDS], words_total);
     for (int i = 0; i < static_cast<int>(ST_COUNT); ++i)

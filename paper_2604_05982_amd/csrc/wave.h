@@ -107,6 +107,13 @@ GTAP_DEV uint32_t wave_from_above(uint32_t x, uint32_t fill) {
       __builtin_amdgcn_update_dpp(static_cast<int>(fill), static_cast<int>(x), 0x130, 0xF, 0xF, false));
 }
 
+// Lane k's 64-bit value x (k wave-uniform), as two 32-bit lane reads.
+GTAP_DEV uint64_t readlane64(uint64_t x, int k) {
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(x)), k));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(x >> 32)), k));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 // Exclusive prefix sum over the 64 lanes; *total = sum over all lanes.
 GTAP_DEV uint32_t wave_exclusive_scan(uint32_t x, uint32_t *total) {
   const uint32_t s = wave_inclusive_sum(x);
