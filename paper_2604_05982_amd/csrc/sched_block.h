@@ -71,9 +71,10 @@ struct BlockLds {
   union {                       // the M2L batch completes before the P2P batch starts
     double Tc[8][fmm::kNc];     // Taylor coefficients of the batch's M2L pairs
     double red[kMaxBlockThreads];  // P2P: partial sums of the source groups
+    double pstage[8 * fmm::kNc];   // P2P: [kMaxBlockThreads, +256) staged source chunks
   };
   double QBc[8][fmm::kNc];      // source moments of the M2L pairs
-  double dl[8][4];              // M2L pair i: centre difference A - B and its squared length
+  double dl[8][4];              // M2L pair i: centre difference A - B and the reciprocal of its squared length
   uint32_t dmt[fmm::kNc][2];    // Taylor recursion indices of coefficient t: g - e_c (byte c of [0]), g - 2 e_c ([1])
   uint4 lstk[2 * kBlkLocal];    // private stack (frame words 0..7 of each task)
   uint32_t lbot, ltop, local, dry;
@@ -249,6 +250,9 @@ GTAP_DEV void fmm_target(BlockLds &S, const fmm::FmmDesc *D, uint32_t a, bool m2
 // M2L(A <- B) for the batch's pairs m2l_idx[0 .. n): Taylor coefficients of
 // 1/|d + h| degree by degree for all of them at once, then each pair's 924
 // terms spread evenly over the workgroup into the running sums of its target.
+constexpr double kInvDeg[fmm::kP + 1] = {0.0, 1.0, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6};
+static_assert(fmm::kP == 6, "reciprocal table of the Taylor degrees");
+
 template <int NT>
 GTAP_DEV void fmm_m2l_batch(const Params &p, BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc) {
   const uint32_t tx = threadIdx.x;
@@ -273,7 +277,7 @@ GTAP_DEV void fmm_m2l_batch(const Params &p, BlockLds &S, const fmm::FmmDesc *D,
     S.dl[tx][0] = d0;
     S.dl[tx][1] = d1;
     S.dl[tx][2] = d2;
-    S.dl[tx][3] = r2;
+    S.dl[tx][3] = 1.0 / r2;
     S.Tc[tx][0] = 1.0 / sqrt(r2);
   }
   __syncthreads();
@@ -298,7 +302,7 @@ GTAP_DEV void fmm_m2l_batch(const Params &p, BlockLds &S, const fmm::FmmDesc *D,
           if (m1 != 0xFFu) s1 += S.dl[i][c] * S.Tc[i][m1];
           if (m2 != 0xFFu) s2 += S.Tc[i][m2];
         }
-        S.Tc[i][t] = -((2.0 * deg - 1.0) * s1 + (deg - 1.0) * s2) / (deg * S.dl[i][3]);
+        S.Tc[i][t] = -((2.0 * deg - 1.0) * s1 + (deg - 1.0) * s2) * (S.dl[i][3] * kInvDeg[deg]);
       }
       wave_sync();
     }
@@ -345,10 +349,10 @@ GTAP_DEV void fmm_m2l_batch(const Params &p, BlockLds &S, const fmm::FmmDesc *D,
 // the target if the split took the source side, the source otherwise -- so
 // the batch is (target ranges) x (source ranges) and runs as one pass:
 // target = tx mod 64 over the concatenated target ranges; wavefront w takes
-// the chunks w, w + G, ... of 64 concatenated sources, loads a chunk with one
-// coalesced load per lane and walks it by reading each source from its lane
-// (one round of loads per 64 sources, no LDS staging, no barriers in the
-// source loop).
+// the chunks w, w + G, ... of 64 / G concatenated sources (G wavefronts),
+// loads a chunk with one coalesced load per lane and walks it by reading each
+// source from its lane (one round of loads per chunk, no LDS staging, no
+// barriers in the source loop).
 template <int NT>
 GTAP_DEV void fmm_p2p_batch(BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc) {
   const uint32_t tx = threadIdx.x;
@@ -428,12 +432,20 @@ GTAP_DEV void fmm_p2p_batch(BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc)
       zi = pz[i];
     }
     double acc = 0.0;
-    for (int32_t c0 = wsrc * static_cast<int32_t>(kWave); c0 < stotal; c0 += static_cast<int32_t>(G * kWave)) {
+    // chunks of SC = 64 / G sources, so that a batch of up to 64 sources
+    // still keeps every wavefront busy
+    constexpr int32_t SC = static_cast<int32_t>(kWave / G);
+    // each wavefront's chunk, staged in LDS behind the reduction slots (the
+    // M2L coefficients' space, free during P2P) and read back by all lanes
+    // from one address per source
+    static_assert(kMaxBlockThreads + kWave * 4 <= 8 * fmm::kNc, "P2P staging space");
+    double *const stage = S.pstage + kMaxBlockThreads + static_cast<uint32_t>(wsrc) * static_cast<uint32_t>(SC) * 4u;
+    for (int32_t c0 = wsrc * SC; c0 < stotal; c0 += static_cast<int32_t>(G) * SC) {
       // this lane's source of the chunk: the (c0 + lane)-th of the concatenated ranges
       int32_t sj = -1;
       double sx = 0.0, sy = 0.0, sz = 0.0, sq = 0.0;
       int32_t off = c0 + static_cast<int32_t>(ln);
-      if (off < stotal) {
+      if (static_cast<int32_t>(ln) < SC && off < stotal) {
         uint32_t r = 0;
         while (off >= S.sr_n[r]) {
           off -= S.sr_n[r];
@@ -445,18 +457,24 @@ GTAP_DEV void fmm_p2p_batch(BlockLds &S, const fmm::FmmDesc *D, FmmCounters &fc)
         sz = pz[sj];
         sq = pq[sj];
       }
-      const int32_t nk = (stotal - c0) < static_cast<int32_t>(kWave) ? (stotal - c0) : static_cast<int32_t>(kWave);
+      if (static_cast<int32_t>(ln) < SC) {
+        reinterpret_cast<double2 *>(stage)[2 * ln] = make_double2(sx, sy);
+        reinterpret_cast<double2 *>(stage)[2 * ln + 1] = make_double2(sz, sq);
+      }
+      wave_sync();
+      const int32_t nk = (stotal - c0) < SC ? (stotal - c0) : SC;
       for (int32_t k = 0; k < nk; ++k) {
-        const double bx = lane_double(sx, k), by = lane_double(sy, k), bz = lane_double(sz, k);
-        const double dx = xi - bx, dy = yi - by, dz = zi - bz;
+        const double2 s0 = reinterpret_cast<const double2 *>(stage)[2 * k];
+        const double2 s1 = reinterpret_cast<const double2 *>(stage)[2 * k + 1];
+        const double dx = xi - s0.x, dy = yi - s0.y, dz = zi - s1.x;
         const double r2 = dx * dx + dy * dy + dz * dz;
-        const double bq = lane_double(sq, k);
         if (r2 == 0.0) {
           if (live && __builtin_amdgcn_readlane(sj, k) != i) ++coinc;
         } else {
-          acc += bq * fmm::rsqrt_nr(r2);
+          acc += s1.y * fmm::rsqrt_nr(r2);
         }
       }
+      wave_sync();  // the chunk's reads are issued before the next chunk overwrites it
     }
     __syncthreads();
     S.red[tx] = acc;
