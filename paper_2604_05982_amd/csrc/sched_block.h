@@ -62,7 +62,6 @@ struct BlockLds {
   uint32_t pid[8][2];
   uint8_t prec[8][2];
   uint32_t n_m2l, n_p2p, m2l_idx[8], p2p_idx[8];
-  uint32_t split_a;
   // P2P batch: target point ranges x source point ranges (one side is one cell)
   int32_t tr_b[8], tr_n[8], sr_b[8], sr_n[8];
   uint32_t nt, ns;
@@ -515,55 +514,58 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
     S.rec[1][tx] = D->cell[static_cast<size_t>(b) * fmm::kCellInts + tx];
   }
   __syncthreads();
-  uint32_t k = 0;
-  if (tx == 0) {
-    const int32_t *A = S.rec[0], *B = S.rec[1];
-    const uint32_t br = fmm_branch(A, B, fc);
-    S.n_m2l = 0;
-    S.n_p2p = 0;
-    S.pid[0][0] = a;
-    S.pid[0][1] = b;
-    S.prec[0][0] = 0;
-    S.prec[0][1] = 1;
-    if (br == 1) {
-      S.n_m2l = 1;
-      S.m2l_idx[0] = 0;
-    } else if (br == 2) {
-      S.n_p2p = 1;
-      S.p2p_idx[0] = 0;
-    } else {
-      // split the wider cell; on a tie the target unless it is a leaf; never a leaf
-      bool split_a = A[0] < B[0] ? true : (A[0] > B[0] ? false : A[7] != 0);
-      if (split_a && A[7] == 0) split_a = false;
-      if (!split_a && B[7] == 0) split_a = true;
-      const int32_t *Sp = split_a ? A : B;
-      k = static_cast<uint32_t>(Sp[7]);
-      for (uint32_t c = 0; c < k; ++c) {
-        const uint32_t ch = static_cast<uint32_t>(Sp[6]) + c;
-        S.pid[c][0] = split_a ? ch : a;
-        S.pid[c][1] = split_a ? b : ch;
-        S.prec[c][0] = static_cast<uint8_t>(split_a ? 2 + c : 0);
-        S.prec[c][1] = static_cast<uint8_t>(split_a ? 1 : 2 + c);
-      }
-      S.split_a = split_a ? 1u : 0u;
-    }
-    S.nchild = k;
+  // Every thread decides the pair's branch and, for a split, which cell
+  // splits, from the records in LDS (the same values): the children's
+  // records are loaded right away, with no round through thread 0.
+  const int32_t *A = S.rec[0], *B = S.rec[1];
+  const uint32_t br0 = fmm_branch(A, B, fc);
+  uint32_t k = 0, first = 0;
+  bool split_a = false;
+  if (br0 == 0) {
+    // split the wider cell; on a tie the target unless it is a leaf; never a leaf
+    split_a = A[0] < B[0] ? true : (A[0] > B[0] ? false : A[7] != 0);
+    if (split_a && A[7] == 0) split_a = false;
+    if (!split_a && B[7] == 0) split_a = true;
+    const int32_t *Sp = split_a ? A : B;
+    k = static_cast<uint32_t>(Sp[7]);
+    first = static_cast<uint32_t>(Sp[6]);
   }
-  __syncthreads();
-  k = S.nchild;
-  if (k > 0) {
+  if (k == 0) {
+    if (tx == 0) {
+      S.n_m2l = br0 == 1 ? 1u : 0u;
+      S.n_p2p = br0 == 2 ? 1u : 0u;
+      S.pid[0][0] = a;
+      S.pid[0][1] = b;
+      S.prec[0][0] = 0;
+      S.prec[0][1] = 1;
+      S.m2l_idx[0] = 0;
+      S.p2p_idx[0] = 0;
+      S.nchild = 0;
+    }
+    __syncthreads();
+  } else {
     // the new cells' records (one round of loads), then every child's branch
     if (tx < k * fmm::kCellInts) {
       const uint32_t c = tx / fmm::kCellInts, w = tx - c * fmm::kCellInts;
-      const uint32_t cell = S.split_a ? S.pid[c][0] : S.pid[c][1];
-      S.rec[2 + c][w] = D->cell[static_cast<size_t>(cell) * fmm::kCellInts + w];
+      S.rec[2 + c][w] = D->cell[static_cast<size_t>(first + c) * fmm::kCellInts + w];
     }
     __syncthreads();
-    // child c's branch on lane c of wavefront 0; ballots compact the M2L,
-    // P2P and split-again lists in child order
+    // child c on lane c of wavefront 0: its pair and records, its branch;
+    // ballots compact the M2L, P2P and split-again lists in child order
     if (tx < kWave) {
       const bool act = tx < k;
-      const uint32_t br = act ? fmm_branch(S.rec[S.prec[tx][0]], S.rec[S.prec[tx][1]], fc) : 3u;
+      uint32_t br = 3u, p0 = 0, p1 = 0;
+      if (act) {
+        const uint32_t ch = first + tx;
+        p0 = split_a ? ch : a;
+        p1 = split_a ? b : ch;
+        const uint32_t r0 = split_a ? 2 + tx : 0u, r1 = split_a ? 1u : 2 + tx;
+        S.pid[tx][0] = p0;
+        S.pid[tx][1] = p1;
+        S.prec[tx][0] = static_cast<uint8_t>(r0);
+        S.prec[tx][1] = static_cast<uint8_t>(r1);
+        br = fmm_branch(S.rec[r0], S.rec[r1], fc);
+      }
       const uint64_t mm = ballot(br == 1), mp = ballot(br == 2), mf = ballot(br == 0);
       if (br == 1) {
         S.m2l_idx[rank_below(mm)] = tx;
@@ -571,8 +573,8 @@ GTAP_DEV void fmm_pair(const Params &p, BlockLds &S, uint32_t job, FmmCounters &
         S.p2p_idx[rank_below(mp)] = tx;
       } else if (br == 0) {
         const uint32_t f = rank_below(mf);
-        S.child[f][0] = S.pid[tx][0];
-        S.child[f][1] = S.pid[tx][1];
+        S.child[f][0] = p0;
+        S.child[f][1] = p1;
       }
       if (tx == 0) {
         S.n_m2l = __popcll(mm);
