@@ -225,14 +225,30 @@ GTAP_DEV uint32_t fmm_branch(const int32_t *A, const int32_t *B, const FmmCounte
 // Make cell `a` the target of the workgroup's running sums (M2L: local
 // coefficients, P2P: potentials of its points), adding the previous target's
 // sums to memory first.  All threads; every thread reads the same state
-// because the last change was followed by a barrier.
+// because the last change was followed by a barrier (the callers end their
+// pass with one, which also orders thread 0's update of the target before
+// the next check).
 template <int NT>
 GTAP_DEV void fmm_target(BlockLds &S, const fmm::FmmDesc *D, uint32_t a, bool m2l, int32_t pbegin = 0,
                          int32_t pn = 0) {
   const bool same = m2l ? (S.lcell == a && S.ldesc == D) : (S.pcell == a && S.pdesc == D);
   if (same) return;
-  fmm_flush_acc<NT>(S, m2l, !m2l);
-  if (threadIdx.x == 0) {
+  const uint32_t tx = threadIdx.x;
+  if (m2l) {
+    if (S.lcell != kNone) {
+      for (uint32_t t = tx; t < static_cast<uint32_t>(fmm::kNc); t += NT) {
+        unsafeAtomicAdd(S.ldesc->L + static_cast<size_t>(S.lcell) * fmm::kNc + t, S.lacc[t]);
+        S.lacc[t] = 0.0;
+      }
+    }
+  } else if (S.pcell != kNone) {
+    for (uint32_t t = tx; t < static_cast<uint32_t>(S.pn); t += NT) {
+      unsafeAtomicAdd(S.pdesc->phi + S.pbegin + t, S.pacc[t]);
+      S.pacc[t] = 0.0;
+    }
+  }
+  __syncthreads();  // every thread has read the old target and cleared its sums
+  if (tx == 0) {
     if (m2l) {
       S.lcell = a;
       S.ldesc = D;
@@ -243,7 +259,6 @@ GTAP_DEV void fmm_target(BlockLds &S, const fmm::FmmDesc *D, uint32_t a, bool m2
       S.pn = pn;
     }
   }
-  __syncthreads();
 }
 
 // M2L(A <- B) for the batch's pairs m2l_idx[0 .. n): Taylor coefficients of
