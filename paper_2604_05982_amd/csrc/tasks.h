@@ -127,41 +127,64 @@ GTAP_DEV uint32_t uts_children(uint64_t id, uint32_t depth, uint64_t thr, uint32
 }
 
 // First index in the ascending list b[lo, nb) whose element is >= x, by a
-// galloping search (doubling steps from lo, then bisection); kCo: b is read
-// coherently (a buffer another wavefront wrote).
+// galloping search (doubling steps from lo, then bisection), and in *v that
+// element (when the index is below nb: every candidate for the answer was
+// loaded on the way, so the caller needs no second load of it); kCo: b is
+// read coherently (a buffer another wavefront wrote).
 template <bool kCo>
 GTAP_DEV int32_t ld_list(const int32_t *b, uint32_t i) {
   if constexpr (kCo) return co_ld32i(b + i);
   else return b[i];
 }
 template <bool kCo>
-GTAP_DEV uint32_t gallop_list(const int32_t *b, uint32_t lo, uint32_t nb, int32_t x) {
-  if (lo >= nb || ld_list<kCo>(b, lo) >= x) return lo;
+GTAP_DEV uint32_t gallop_list(const int32_t *b, uint32_t lo, uint32_t nb, int32_t x, int32_t *v) {
+  if (lo >= nb) return nb;
+  const int32_t y = ld_list<kCo>(b, lo);
+  if (y >= x) {
+    *v = y;
+    return lo;
+  }
   uint32_t step = 1, prev = lo;
-  while (prev + step < nb && ld_list<kCo>(b, prev + step) < x) {
+  int32_t vh = 0;
+  while (prev + step < nb) {
+    const int32_t t = ld_list<kCo>(b, prev + step);
+    if (t >= x) {
+      vh = t;
+      break;
+    }
     prev += step;
     step <<= 1;
   }
   uint32_t l = prev + 1, h = prev + step < nb ? prev + step : nb;
   while (l < h) {
     const uint32_t mid = l + (h - l) / 2;
-    if (ld_list<kCo>(b, mid) < x) l = mid + 1;
-    else h = mid;
+    const int32_t t = ld_list<kCo>(b, mid);
+    if (t < x) {
+      l = mid + 1;
+    } else {
+      h = mid;
+      vh = t;
+    }
   }
+  *v = vh;
   return l;
 }
-// Common elements of the ascending lists s (walked) and l (galloped into).
+// Common elements of the ascending lists s (walked) and l (galloped into);
+// the next element of s is loaded while the current one's search runs.
 template <bool kCoS, bool kCoL>
 GTAP_DEV uint32_t isect_gallop(const int32_t *s, uint32_t ns, const int32_t *l, uint32_t nl, int32_t *out) {
   uint32_t j = 0, o = 0;
+  int32_t x = ld_list<kCoS>(s, 0);
   for (uint32_t i = 0; i < ns && j < nl; ++i) {
-    const int32_t x = ld_list<kCoS>(s, i);
-    j = gallop_list<kCoL>(l, j, nl, x);
-    if (j < nl && ld_list<kCoL>(l, j) == x) {
+    const int32_t xn = i + 1 < ns ? ld_list<kCoS>(s, i + 1) : 0;
+    int32_t v = 0;
+    j = gallop_list<kCoL>(l, j, nl, x, &v);
+    if (j < nl && v == x) {
       if (out) co_st32i(out + o, x);
       ++o;
       ++j;
     }
+    x = xn;
   }
   return o;
 }
