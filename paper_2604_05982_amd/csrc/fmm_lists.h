@@ -337,87 +337,138 @@ GTAP_DEV double rsqrt_nr(double x) {
   return y;
 }
 
-// P2P over the sorted list: workgroup = target leaf a; wavefront w takes the
-// source leaves w, w + 4, ... of a's segment.  A tile of at most 16 targets is
-// padded to a power of two P, and the wavefront's lanes form 64 / P groups of
-// P: lane = (target, group), group g takes the source points g, g + 64/P, ...
-// of each source leaf, so small leaves still keep most lanes busy; larger
-// tiles take one target per lane and read each source point as one
-// wavefront-uniform (scalar) load.  Partial
-// sums meet by lane shuffles, then across the four wavefronts in LDS; phi[i]
-// receives the sum once; interactions and coincident pairs are counted.
+// P2P over the sorted list, balanced over its entries: wavefront w takes the
+// 64 entries 64 w .. 64 w + 63 (one per lane), so a target whose segment is
+// long (a large leaf next to a dense region meets tens of thousands of source
+// leaves) is spread over many wavefronts, and adds its potentials atomically.
+// The entries form runs of one target.  Per run, the sources of its leaves
+// are concatenated (exclusive prefix of the leaf sizes over the run's lanes)
+// and walked in chunks of 64 points: the owner of chunk position c is the
+// last leaf starting at or before it (marks in LDS and a prefix maximum), each
+// lane loads one point, the chunk is staged in LDS as (x, y, z, q), and the
+// next chunk is loaded while this one is evaluated.  A tile of at most 64
+// targets is padded to a power of two P; the lanes form 64 / P groups of P
+// (lane = target + P * group), group g takes the chunk's sources g, g + 64/P,
+// ..., and the groups' partial sums meet by lane shuffles.  Interactions are
+// counted, and coincident pairs as the pairs at distance zero less the
+// points' meetings with themselves (one per target point and self pair).
 __global__ __launch_bounds__(kP2PThreads) void k_p2p_list(const int32_t *__restrict__ cell,
                                                           const double *__restrict__ px,
                                                           const double *__restrict__ py,
                                                           const double *__restrict__ pz,
                                                           const double *__restrict__ pq, double *phi,
-                                                          const uint64_t *__restrict__ pairs,
-                                                          const uint64_t *__restrict__ seg_lo,
-                                                          const uint64_t *__restrict__ seg_hi, uint64_t *inter_out,
-                                                          uint64_t *coinc_out) {
-  const uint32_t a = blockIdx.x;
-  const uint64_t lo = seg_lo[a], hi = seg_hi[a];
-  if (lo == hi) return;
+                                                          const uint64_t *__restrict__ pairs, uint64_t n,
+                                                          uint32_t ncells, uint64_t *inter_out, uint64_t *coinc_out) {
   constexpr uint32_t W = kP2PThreads / kWave;
-  __shared__ double red[W][kWave];
-  // wave-uniform source indices let the source reads be scalar loads
+  __shared__ double2 stage[W][2 * kWave];
+  __shared__ uint32_t mark[W][kWave];
   const uint32_t tx = threadIdx.x, ln = tx % kWave;
   const uint32_t wv = __builtin_amdgcn_readfirstlane(tx / kWave);
-  const int32_t ab = cell[static_cast<size_t>(a) * kCellInts + 4], ae = cell[static_cast<size_t>(a) * kCellInts + 5];
-  uint64_t coinc = 0, inter = 0;
-  for (int32_t t0 = ab; t0 < ae; t0 += kP2PTileL) {
-    const int32_t nt = min(static_cast<int32_t>(kP2PTileL), ae - t0);
-    // (tiles of more than 16 targets keep one group: their lanes read the
-    // same source point, which the scalar loads serve best)
-    uint32_t P = 1;
-    while (P < static_cast<uint32_t>(nt)) P <<= 1;
-    if (P > 16) P = kWave;
-    const uint32_t ng = __builtin_amdgcn_readfirstlane(kWave / P), tl = ln % P, grp = ln / P;
-    const int32_t i = t0 + static_cast<int32_t>(tl);
-    const bool live = static_cast<int32_t>(tl) < nt;
-    const double xi = live ? px[i] : 0.0, yi = live ? py[i] : 0.0, zi = live ? pz[i] : 0.0;
-    double acc = 0.0;
-    for (uint64_t s = lo + wv; s < hi; s += W) {
-      const uint32_t b = static_cast<uint32_t>(pairs[s]);
-      const int32_t bb = cell[static_cast<size_t>(b) * kCellInts + 4], be = cell[static_cast<size_t>(b) * kCellInts + 5];
-      if (t0 == ab) inter += static_cast<uint64_t>(static_cast<int64_t>(ae - ab) * (be - bb) - (a == b ? ae - ab : 0));
-      if (ng == 1) {
-        // one group: every lane reads the same source point (scalar loads)
-#pragma unroll 4
-        for (int32_t j = bb; j < be; ++j) {
-          const double dx = xi - px[j], dy = yi - py[j], dz = zi - pz[j];
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 == 0.0) {
-            if (live && j != i) ++coinc;
-          } else {
-            acc += pq[j] * rsqrt_nr(r2);
-          }
-        }
-      } else {
-        for (int32_t j = bb + static_cast<int32_t>(grp); j < be; j += static_cast<int32_t>(ng)) {
-          const double dx = xi - px[j], dy = yi - py[j], dz = zi - pz[j];
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 == 0.0) {
-            if (live && j != i) ++coinc;
-          } else {
-            acc += pq[j] * rsqrt_nr(r2);
-          }
-        }
-      }
+  const uint64_t e0 = (static_cast<uint64_t>(blockIdx.x) * W + wv) * kWave;
+  if (e0 >= n) return;
+  const uint32_t ne = static_cast<uint32_t>(min(static_cast<uint64_t>(kWave), n - e0));
+  double2 *const st = stage[wv];
+  uint32_t *const mk = mark[wv];
+  // entry e0 + ln: target ta (ncells for the gaps, which sort last, and past
+  // the end), source leaf sb with points rb .. rb + rn - 1, target points
+  // tb .. tb + tn - 1
+  uint32_t ta = ncells, sb = 0;
+  int32_t rb = 0, rn = 0, tb = 0, tn = 0;
+  if (ln < ne) {
+    const uint64_t e = pairs[e0 + ln];
+    if (static_cast<uint32_t>(e >> 32) < ncells) {
+      ta = static_cast<uint32_t>(e >> 32);
+      sb = static_cast<uint32_t>(e);
+      rb = cell[static_cast<size_t>(sb) * kCellInts + 4];
+      rn = cell[static_cast<size_t>(sb) * kCellInts + 5] - rb;
+      tb = cell[static_cast<size_t>(ta) * kCellInts + 4];
+      tn = cell[static_cast<size_t>(ta) * kCellInts + 5] - tb;
     }
-    for (uint32_t d = P; d < kWave; d <<= 1) acc += __shfl_xor(acc, static_cast<int>(d), 64);
-    red[wv][ln] = acc;
-    __syncthreads();
-    if (wv == 0 && live && grp == 0) {
-      double sum = 0.0;
-#pragma unroll
-      for (uint32_t g = 0; g < W; ++g) sum += red[g][ln];
-      phi[i] += sum;
-    }
-    __syncthreads();
   }
+  const uint32_t nv = static_cast<uint32_t>(__popcll(ballot(ta < ncells)));
+  uint64_t inter = 0, selfm = 0;
+  uint32_t zc = 0;
+  for (uint32_t k0 = 0; k0 < nv;) {
+    // the run of target a: lanes k0 .. k1 - 1
+    const uint32_t a = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ta), static_cast<int>(k0)));
+    const uint64_t other = ballot(ta != a) & (~0ull << k0);
+    const uint32_t k1 = other ? static_cast<uint32_t>(__builtin_ctzll(other)) : kWave;
+    const bool in_run = ln >= k0 && ln < k1;
+    const int32_t rn_run = in_run ? rn : 0;
+    const int32_t incl = static_cast<int32_t>(wave_inclusive_sum(static_cast<uint32_t>(rn_run)));
+    const int32_t pre = incl - rn_run;  // first concatenated position of this lane's leaf
+    const int32_t stotal = __builtin_amdgcn_readlane(incl, static_cast<int>(k1 - 1));
+    const int32_t ab = __builtin_amdgcn_readlane(tb, static_cast<int>(k0));
+    const int32_t na = __builtin_amdgcn_readlane(tn, static_cast<int>(k0));
+    const uint32_t nself = static_cast<uint32_t>(__popcll(ballot(in_run && sb == a)));
+    inter += static_cast<uint64_t>(static_cast<int64_t>(na) * stotal - static_cast<int64_t>(nself) * na);
+    selfm += static_cast<uint64_t>(nself) * static_cast<uint64_t>(na);
+    // Loads chunk c's points into (sx, sy, sz, sq).
+    double sx = 0.0, sy = 0.0, sz = 0.0, sq = 0.0;
+    auto fetch = [&](int32_t c) {
+      mk[ln] = 0;
+      wave_sync();
+      if (in_run && rn > 0 && pre < c + static_cast<int32_t>(kWave) && pre + rn > c)
+        mk[pre > c ? pre - c : 0] = ln + 1;
+      wave_sync();
+      const uint32_t m = wave_inclusive_max(mk[ln]);
+      wave_sync();
+      const int32_t own = m ? static_cast<int32_t>(m) - 1 : 0;
+      const int32_t ob = __shfl(rb, own, 64), op = __shfl(pre, own, 64);
+      const int32_t pos = c + static_cast<int32_t>(ln);
+      if (pos < stotal) {
+        const int32_t sj = ob + (pos - op);
+        sx = px[sj];
+        sy = py[sj];
+        sz = pz[sj];
+        sq = pq[sj];
+      }
+    };
+    for (int32_t t0 = 0; t0 < na; t0 += static_cast<int32_t>(kP2PTileL)) {
+      const int32_t nt = min(static_cast<int32_t>(kP2PTileL), na - t0);
+      uint32_t P = 1;
+      while (P < static_cast<uint32_t>(nt)) P <<= 1;
+      const int32_t ng = static_cast<int32_t>(kWave / P);
+      const uint32_t tl = ln % P;
+      const int32_t grp = static_cast<int32_t>(ln / P);
+      const int32_t i = ab + t0 + static_cast<int32_t>(tl);
+      const bool live = static_cast<int32_t>(tl) < nt;
+      double xi = live ? px[i] : 0.0, yi = live ? py[i] : 0.0, zi = live ? pz[i] : 0.0;
+      // taken as written here, so that the source loop's waits do not cover
+      // the source prefetch
+      asm volatile("" : "+v"(xi), "+v"(yi), "+v"(zi));
+      double acc = 0.0;
+      fetch(0);
+      for (int32_t c0 = 0; c0 < stotal; c0 += static_cast<int32_t>(kWave)) {
+        const int32_t cnt = min(static_cast<int32_t>(kWave), stotal - c0);
+        if (static_cast<int32_t>(ln) < cnt) {
+          st[2 * ln] = make_double2(sx, sy);
+          st[2 * ln + 1] = make_double2(sz, sq);
+        }
+        wave_sync();
+        if (c0 + static_cast<int32_t>(kWave) < stotal) fetch(c0 + static_cast<int32_t>(kWave));
+#pragma unroll 4
+        for (int32_t u = 0; u < cnt; u += ng) {
+          // u + grp < 64: u is a multiple of ng below cnt <= 64, grp < ng
+          const int32_t j = u + grp;
+          const bool ok = j < cnt;
+          const double2 s01 = st[2 * j], s23 = st[2 * j + 1];
+          const double dx = xi - s01.x, dy = yi - s01.y, dz = zi - s23.x;
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          const bool z = r2 == 0.0;
+          const double ri = rsqrt_nr(z ? 1.0 : r2);
+          acc += (ok && !z) ? s23.y * ri : 0.0;
+          zc += (ok && z && live) ? 1u : 0u;
+        }
+        wave_sync();  // the chunk's reads are issued before the next one overwrites it
+      }
+      for (uint32_t d = P; d < kWave; d <<= 1) acc += __shfl_xor(acc, static_cast<int>(d), 64);
+      if (live && grp == 0) unsafeAtomicAdd(phi + i, acc);
+    }
+    k0 = k1;
+  }
+  const uint64_t coinc = readlane64(wave_inclusive_sum64(zc), 63) - selfm;
   if (ln == 0 && inter) fetch_add_relaxed(inter_out, inter);
-  coinc = readlane64(wave_inclusive_sum64(coinc), 63);
   if (ln == 0 && coinc) fetch_add_relaxed(coinc_out, coinc);
 }
 

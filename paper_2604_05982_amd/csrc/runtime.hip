@@ -926,9 +926,9 @@ int fmm_eval_lists(gtap_ctx *c, FmmJobMem &m, uint64_t n_m2l, uint64_t n_p2p, gt
   if (hipEventRecord(m.lev[4], st) != hipSuccess) return GTAP_E_HIP;
   if ((rc = prepare(m.p2p, n_p2p, &D->p2p_hash, &D->p2p_pairs))) return rc;
   if (hipEventRecord(m.lev[5], st) != hipSuccess) return GTAP_E_HIP;
-  hipLaunchKernelGGL(fmm::k_p2p_list, dim3(m.ncells), dim3(fmm::kP2PThreads), 0, st, m.hdesc.cell, m.hdesc.px,
-                     m.hdesc.py, m.hdesc.pz, m.hdesc.pq, m.hdesc.phi, m.sorted, lo, hi, &D->p2p_inter,
-                     &D->coincident);
+  hipLaunchKernelGGL(fmm::k_p2p_list, dim3(nblk(static_cast<int64_t>((n_p2p + kWave - 1) / kWave), fmm::kP2PThreads / kWave)),
+                     dim3(fmm::kP2PThreads), 0, st, m.hdesc.cell, m.hdesc.px, m.hdesc.py, m.hdesc.pz, m.hdesc.pq,
+                     m.hdesc.phi, m.sorted, n_p2p, static_cast<uint32_t>(m.ncells), &D->p2p_inter, &D->coincident);
   if (hipEventRecord(m.lev[6], st) != hipSuccess) return GTAP_E_HIP;
   if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) return GTAP_E_HIP;
   float s1 = 0.f, mm = 0.f, s2 = 0.f, pp = 0.f;
