@@ -6,11 +6,11 @@
 // level-synchronous worklist (ping-pong frontiers, one launch per frontier).
 //
 // MI355X choices: appends are aggregated per wavefront (one atomic per
-// wavefront and list); the lists are sorted by target cell so that one
-// workgroup owns a target and adds its result once, without atomics; M2L
-// stages 32 sources at a time in LDS (Taylor coefficients and moments) and
-// spreads the 924 (target, source) coefficient terms over 256 threads, each
-// accumulating its terms across all sources in registers.
+// wavefront and list); the lists are sorted by target cell.  M2L gives each
+// target one wavefront, one source per lane, and adds its sums once.  P2P is
+// balanced over the list entries instead (64 per wavefront), because a target
+// leaf's segment can be tens of thousands of entries long; the wavefronts
+// that share a target add their potentials with fp64 atomics.
 #pragma once
 #include "fmm.h"
 #include "wave.h"
