@@ -20,7 +20,7 @@
 
 #include "../../include/gtap.h"
 #include "fmm.h"
-#include "fmm_lists.h"
+#include "fmm_eval.h"
 #include "kclique_bits.h"
 #include "layout.h"
 #include "probes.h"
