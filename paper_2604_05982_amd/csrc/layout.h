@@ -72,6 +72,13 @@ enum TaskKind : uint32_t {
   TK_KS_ROW = 16,     //   one row of a vertex's bit matrix
 };
 
+// Extension task sets of the thread-mode kernel, each compiled in only where
+// a launch needs it: the split k-clique bodies alone add private memory and
+// registers to every task of the kernel.
+constexpr uint32_t kExtLists = 1;  // FMM list-building cell pairs, Cilksort sorts and merges
+constexpr uint32_t kExtSplit = 2;  // k-clique with bitset candidate subgraphs (TK_KS_*)
+constexpr uint32_t kExtAll = kExtLists | kExtSplit;
+
 struct alignas(128) DequeMeta {
   int32_t count;   // unclaimed entries (every claim is a CAS on this word)
   uint32_t head;   // steal end, advanced by the lock holder after loading

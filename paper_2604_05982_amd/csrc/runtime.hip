@@ -562,7 +562,7 @@ static int record_run(gtap_ctx *c, const Control &ctl, float ms) {
   return GTAP_OK;
 }
 
-static int launch_sched(gtap_ctx *c, bool ext_kinds = false) {
+static int launch_sched(gtap_ctx *c, uint32_t ext = 0) {
   const uint32_t wpb = static_cast<uint32_t>(c->cfg.waves_per_group);
   const dim3 grid(c->nwaves / wpb), block(64 * wpb);
   if (c->cfg.mode == GTAP_MODE_BLOCK) {
@@ -589,8 +589,10 @@ static int launch_sched(gtap_ctx *c, bool ext_kinds = false) {
           hipLaunchKernelGGL((thread_sched_kernel<4, kSchedBatchedNoLocal>), grid, block, 0, c->stream, c->params);
           break;
         default:
-          if (ext_kinds)  // FMM list traversal, Cilksort
-            hipLaunchKernelGGL((thread_sched_kernel<4, kSchedBatched, true>), grid, block, 0, c->stream, c->params);
+          if (ext == kExtLists)  // FMM list traversal, Cilksort
+            hipLaunchKernelGGL((thread_sched_kernel<4, kSchedBatched, kExtLists>), grid, block, 0, c->stream, c->params);
+          else if (ext != 0)  // and split k-clique
+            hipLaunchKernelGGL((thread_sched_kernel<4, kSchedBatched, kExtAll>), grid, block, 0, c->stream, c->params);
           else
             hipLaunchKernelGGL(thread_sched_kernel<4>, grid, block, 0, c->stream, c->params);
           break;
@@ -1000,11 +1002,12 @@ int gtap_run(gtap_ctx *c) {
   // FMM jobs: tree and upward pass before the launch; the worklist traversal
   // runs here too (its root task in the launch is empty)
   std::vector<FmmJobMem> fm;
-  bool any_fmm = false, any_ext = false;
+  bool any_fmm = false;
+  uint32_t ext = 0;  // extension task sets the batch needs
   for (size_t j = 0; j < nj; ++j) {
     any_fmm |= c->pending[j].kind == GTAP_KIND_FMM;
-    any_ext |= c->pending[j].kind == GTAP_KIND_FMM || c->pending[j].kind == GTAP_KIND_CILKSORT ||
-               c->pending[j].kind == GTAP_KIND_KCLIQUE_SPLIT;
+    if (c->pending[j].kind == GTAP_KIND_FMM || c->pending[j].kind == GTAP_KIND_CILKSORT) ext |= kExtLists;
+    if (c->pending[j].kind == GTAP_KIND_KCLIQUE_SPLIT) ext |= kExtSplit;
   }
   std::vector<void *> ks_mem;
   auto drop_pending = [&]() {
@@ -1066,7 +1069,7 @@ int gtap_run(gtap_ctx *c) {
     const uint32_t ndq = c->nwaves * p.Q;
     hipLaunchKernelGGL(reset_kernel, dim3(reset_blocks(ndq, p.ccap)), dim3(256), 0, c->stream, p, ndq);
     if (hipGetLastError() != hipSuccess || hipEventRecord(c->ev0, c->stream) != hipSuccess) rc = GTAP_E_HIP;
-    if (rc == GTAP_OK) rc = launch_sched(c, any_ext && !block);
+    if (rc == GTAP_OK) rc = launch_sched(c, block ? 0u : ext);
     if (rc == GTAP_OK && hipEventRecord(c->ev1, c->stream) != hipSuccess) rc = GTAP_E_HIP;
     if (rc != GTAP_OK) {
       (void)hipStreamSynchronize(c->stream);

@@ -627,7 +627,7 @@ GTAP_DEV uint32_t chunk_owner(uint32_t *mark, uint32_t nchild, uint32_t off, uin
 }
 
 // Root frame of job slot j (payload from the job's arguments).
-template <bool kExt = false>
+template <uint32_t kExt = 0>
 GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
   const uint32_t jkind = static_cast<uint32_t>(co_ld64(reinterpret_cast<const uint64_t *>(p.jobs + j)));
   ChildInit c;
@@ -662,29 +662,33 @@ GTAP_DEV void write_root(const Params &p, uint32_t id, uint32_t j) {
       break;
   }
   if constexpr (kExt) {
-    if (jkind == 7) {  // k-clique with splitting: the whole vertex range
-      kind = TK_KS_RANGE;
-      c.p[0] = 0;
-      c.p[1] = static_cast<uint32_t>(job_arg(p, j, 2));
+    if constexpr ((kExt & kExtSplit) != 0) {
+      if (jkind == 7) {  // k-clique with splitting: the whole vertex range
+        kind = TK_KS_RANGE;
+        c.p[0] = 0;
+        c.p[1] = static_cast<uint32_t>(job_arg(p, j, 2));
+      }
     }
-    if (jkind == 6) {  // Cilksort: sort the whole array into the key buffer
-      kind = TK_SORT;
-      c.p[0] = 0;
-      c.p[1] = static_cast<uint32_t>(job_arg(p, j, 2));
-      c.p[2] = 0;
-    }
-    // FMM in thread mode: the list-building traversal starts at the pair
-    // (root, root); a job whose lists the worklist builds has an empty root
-    // (a[0] descriptor, a[1] traversal, a[2] = theta_num | theta_den << 8)
-    if (jkind == 5) {
-      const uint64_t desc = job_arg(p, j, 0);
-      kind = TK_FIB;
-      c.p[0] = 0;
-      if (job_arg(p, j, 1) == 1) {
-        kind = TK_DTT;
-        c.p[2] = static_cast<uint32_t>(desc);
-        c.p[3] = static_cast<uint32_t>(desc >> 32);
-        c.p[4] = static_cast<uint32_t>(job_arg(p, j, 2));
+    if constexpr ((kExt & kExtLists) != 0) {
+      if (jkind == 6) {  // Cilksort: sort the whole array into the key buffer
+        kind = TK_SORT;
+        c.p[0] = 0;
+        c.p[1] = static_cast<uint32_t>(job_arg(p, j, 2));
+        c.p[2] = 0;
+      }
+      // FMM in thread mode: the list-building traversal starts at the pair
+      // (root, root); a job whose lists the worklist builds has an empty root
+      // (a[0] descriptor, a[1] traversal, a[2] = theta_num | theta_den << 8)
+      if (jkind == 5) {
+        const uint64_t desc = job_arg(p, j, 0);
+        kind = TK_FIB;
+        c.p[0] = 0;
+        if (job_arg(p, j, 1) == 1) {
+          kind = TK_DTT;
+          c.p[2] = static_cast<uint32_t>(desc);
+          c.p[3] = static_cast<uint32_t>(desc >> 32);
+          c.p[4] = static_cast<uint32_t>(job_arg(p, j, 2));
+        }
       }
     }
   }
@@ -770,8 +774,9 @@ struct LocalCap {
 // V selects the queue management (kSchedBatched, kSchedSingle, kSchedCentral;
 // kSchedBatchedNoLocal = batched without the private stack) at compile time,
 // so the comparison variants add nothing to the scheduler as designed; kExt
-// adds the FMM list-building cell-pair tasks and their list appends.
-template <int WPB, uint32_t V = kSchedBatched, bool kExt = false>
+// adds extension task sets (kExtLists: the FMM list-building cell pairs and
+// their list appends, Cilksort; kExtSplit: split k-clique).
+template <int WPB, uint32_t V = kSchedBatched, uint32_t kExt = 0>
 __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
   constexpr bool kCentral = (V == kSchedCentral);
   constexpr bool kSingle = (V == kSchedSingle);
@@ -1036,7 +1041,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
       }
       exec_task<kExt>(p, tid, img, o);
     }
-    if constexpr (kExt) {
+    if constexpr ((kExt & kExtLists) != 0) {
       // FMM list traversal: accepted pairs and leaf pairs go to their lists,
       // through this wavefront's chunks of them
       const bool em = o.type == OUT_DONE && o.emit != 0;
@@ -1439,7 +1444,7 @@ __global__ __launch_bounds__(64 * WPB) void thread_sched_kernel(Params p) {
     t_loop = now;
   }
 
-  if constexpr (kExt) fmm::chunks_close(lchunks);
+  if constexpr ((kExt & kExtLists) != 0) fmm::chunks_close(lchunks);
   // ---- flush counters ----
   const uint64_t wave_words = wave_inclusive_sum64(data_words);
   const uint64_t words_total = readlane64(wave_words, 63);

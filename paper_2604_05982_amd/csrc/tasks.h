@@ -605,9 +605,9 @@ GTAP_DEV void ks_node(const Params &p, uint32_t *f, Outcome &o, uint32_t u, uint
 // ---------------------------------------------------------------------------
 // Execute one task on this lane.  tid is its frame, or kNone for a task
 // without one (then it runs at resume point 0 and needs no buffer).  kExt
-// adds the list-building FMM cell-pair task (instantiated separately, so the
+// adds the extension task sets it names (instantiated separately, so the
 // other task kinds compile unchanged).
-template <bool kExt = false>
+template <uint32_t kExt = 0>
 GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Outcome &o) {
   uint32_t *f = tid != kNone ? frame_ptr(p, tid) : nullptr;
   const uint64_t w01 = img.w01;
@@ -626,32 +626,36 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
   if constexpr (kExt) {
     o.emit = 0;
     o.pc_next = 1;
-    if (pc != 0 && kind == TK_SORT) {
-      // after the two sorts: merge them back (resume point 2 follows); after
-      // the merge: done, the result is the range's length
-      uint32_t *f = frame_ptr(p, tid);
-      const uint32_t lo = co_ld32(f + FW_P0), n = co_ld32(f + FW_P0 + 1), dst = co_ld32(f + FW_P0 + 2);
-      if (pc == 1) {
-        const uint32_t h = n / 2;
+    if constexpr ((kExt & kExtLists) != 0) {
+      if (pc != 0 && kind == TK_SORT) {
+        // after the two sorts: merge them back (resume point 2 follows); after
+        // the merge: done, the result is the range's length
+        uint32_t *f = frame_ptr(p, tid);
+        const uint32_t lo = co_ld32(f + FW_P0), n = co_ld32(f + FW_P0 + 1), dst = co_ld32(f + FW_P0 + 2);
+        if (pc == 1) {
+          const uint32_t h = n / 2;
+          o.type = OUT_FORK;
+          o.nchild = 1;
+          o.ckind = TK_MERGE;
+          o.d[0] = lo; o.d[1] = h; o.d[2] = lo + h; o.d[3] = n - h; o.d[4] = lo | (dst << 31); o.d[5] = 0;
+          o.pc_next = 2;
+          return;
+        }
+        o.value = n;
+        return;
+      }
+    }
+    if constexpr ((kExt & kExtSplit) != 0) {
+      if (pc == 1 && kind == TK_KS_VERTEX) {  // the matrix is complete: the edge tasks
+        const uint32_t u = co_ld32(frame_ptr(p, tid) + FW_P0);  // (written at spawn or when it forked)
+        const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 0));
         o.type = OUT_FORK;
-        o.nchild = 1;
-        o.ckind = TK_MERGE;
-        o.d[0] = lo; o.d[1] = h; o.d[2] = lo + h; o.d[3] = n - h; o.d[4] = lo | (dst << 31); o.d[5] = 0;
+        o.nchild = static_cast<uint32_t>(rp[u + 1] - rp[u]);
+        o.ckind = TK_KS_EDGE;
+        o.d[0] = u;
         o.pc_next = 2;
         return;
       }
-      o.value = n;
-      return;
-    }
-    if (pc == 1 && kind == TK_KS_VERTEX) {  // the matrix is complete: the edge tasks
-      const uint32_t u = co_ld32(frame_ptr(p, tid) + FW_P0);  // (written at spawn or when it forked)
-      const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 0));
-      o.type = OUT_FORK;
-      o.nchild = static_cast<uint32_t>(rp[u + 1] - rp[u]);
-      o.ckind = TK_KS_EDGE;
-      o.d[0] = u;
-      o.pc_next = 2;
-      return;
     }
   }
 
@@ -669,157 +673,163 @@ GTAP_DEV void exec_task(const Params &p, uint32_t tid, const TaskImage &img, Out
   const uint32_t p1 = static_cast<uint32_t>(w45), p2 = static_cast<uint32_t>(w45 >> 32);
   const uint32_t p3 = static_cast<uint32_t>(w67), p4 = static_cast<uint32_t>(w67 >> 32);
   if constexpr (kExt) {
-    if (kind == TK_SORT) {
-      // sort(lo, n, dst): serial below the cutoff, else both halves into the
-      // other buffer first (resume point 1 merges them)
-      const uint32_t lo = p0, n = p1, dst = p2;
-      const uint32_t sc = static_cast<uint32_t>(job_arg(p, o.job, 3));
-      if (n <= sc) {
-        const uint32_t *X = reinterpret_cast<const uint32_t *>(job_arg(p, o.job, 0));
-        uint32_t *D = reinterpret_cast<uint32_t *>(job_arg(p, o.job, dst ? 1 : 0));
-        uint32_t v[kSortNet];
-#pragma unroll
-        for (uint32_t i = 0; i < kSortNet; ++i) v[i] = i < n ? co_ld32(X + lo + i) : 0xFFFFFFFFu;
-        sort_net64(v);
-#pragma unroll
-        for (uint32_t i = 0; i < kSortNet; ++i)
-          if (i < n) co_st32(D + lo + i, v[i]);
-        o.value = n;
+    if constexpr ((kExt & kExtLists) != 0) {
+      if (kind == TK_SORT) {
+        // sort(lo, n, dst): serial below the cutoff, else both halves into the
+        // other buffer first (resume point 1 merges them)
+        const uint32_t lo = p0, n = p1, dst = p2;
+        const uint32_t sc = static_cast<uint32_t>(job_arg(p, o.job, 3));
+        if (n <= sc) {
+          const uint32_t *X = reinterpret_cast<const uint32_t *>(job_arg(p, o.job, 0));
+          uint32_t *D = reinterpret_cast<uint32_t *>(job_arg(p, o.job, dst ? 1 : 0));
+          uint32_t v[kSortNet];
+  #pragma unroll
+          for (uint32_t i = 0; i < kSortNet; ++i) v[i] = i < n ? co_ld32(X + lo + i) : 0xFFFFFFFFu;
+          sort_net64(v);
+  #pragma unroll
+          for (uint32_t i = 0; i < kSortNet; ++i)
+            if (i < n) co_st32(D + lo + i, v[i]);
+          o.value = n;
+          return;
+        }
+        o.type = OUT_FORK;
+        o.nchild = 2;
+        o.ckind = TK_SORT;
+        o.d[0] = lo; o.d[1] = n; o.d[2] = dst;
         return;
       }
-      o.type = OUT_FORK;
-      o.nchild = 2;
-      o.ckind = TK_SORT;
-      o.d[0] = lo; o.d[1] = n; o.d[2] = dst;
-      return;
-    }
-    if (kind == TK_MERGE) {
-      // merge(A, B -> D): payload A = (p0, p1), B = (p2, p3), p4 = destination
-      // start | split pending << 29 | side << 30 | destination buffer << 31.
-      // A pending split first takes its side of the parent's ranges.
-      uint32_t a0 = p0, na = p1, b0 = p2, nb = p3;
-      const uint32_t dst = p4 >> 31;
-      uint32_t d0 = p4 & kMergeD;
-      const uint32_t *S = reinterpret_cast<const uint32_t *>(job_arg(p, o.job, dst ? 0 : 1));
-      uint32_t *D = reinterpret_cast<uint32_t *>(job_arg(p, o.job, dst ? 1 : 0));
-      if ((p4 >> 29) & 1u) {
-        const uint32_t ma = na / 2, mb = count_below(S + b0, nb, co_ld32(S + a0 + ma));
-        if ((p4 >> 30) & 1u) {
-          a0 += ma; na -= ma; b0 += mb; nb -= mb; d0 += ma + mb;
-        } else {
-          na = ma; nb = mb;
-        }
-      }
-      if (nb > na) {
-        const uint32_t t0 = a0, t1 = na;
-        a0 = b0; na = nb; b0 = t0; nb = t1;
-      }
-      const uint32_t mc = static_cast<uint32_t>(job_arg(p, o.job, 3) >> 32);
-      if (na + nb <= mc) {
-        uint32_t i = 0, j = 0, k = d0;
-        while (i < na && j < nb) {
-          const uint32_t x = co_ld32(S + a0 + i), y = co_ld32(S + b0 + j);
-          if (y < x) {
-            co_st32(D + k++, y);
-            ++j;
+      if (kind == TK_MERGE) {
+        // merge(A, B -> D): payload A = (p0, p1), B = (p2, p3), p4 = destination
+        // start | split pending << 29 | side << 30 | destination buffer << 31.
+        // A pending split first takes its side of the parent's ranges.
+        uint32_t a0 = p0, na = p1, b0 = p2, nb = p3;
+        const uint32_t dst = p4 >> 31;
+        uint32_t d0 = p4 & kMergeD;
+        const uint32_t *S = reinterpret_cast<const uint32_t *>(job_arg(p, o.job, dst ? 0 : 1));
+        uint32_t *D = reinterpret_cast<uint32_t *>(job_arg(p, o.job, dst ? 1 : 0));
+        if ((p4 >> 29) & 1u) {
+          const uint32_t ma = na / 2, mb = count_below(S + b0, nb, co_ld32(S + a0 + ma));
+          if ((p4 >> 30) & 1u) {
+            a0 += ma; na -= ma; b0 += mb; nb -= mb; d0 += ma + mb;
           } else {
-            co_st32(D + k++, x);
-            ++i;
+            na = ma; nb = mb;
           }
         }
-        while (i < na) co_st32(D + k++, co_ld32(S + a0 + i++));
-        while (j < nb) co_st32(D + k++, co_ld32(S + b0 + j++));
+        if (nb > na) {
+          const uint32_t t0 = a0, t1 = na;
+          a0 = b0; na = nb; b0 = t0; nb = t1;
+        }
+        const uint32_t mc = static_cast<uint32_t>(job_arg(p, o.job, 3) >> 32);
+        if (na + nb <= mc) {
+          uint32_t i = 0, j = 0, k = d0;
+          while (i < na && j < nb) {
+            const uint32_t x = co_ld32(S + a0 + i), y = co_ld32(S + b0 + j);
+            if (y < x) {
+              co_st32(D + k++, y);
+              ++j;
+            } else {
+              co_st32(D + k++, x);
+              ++i;
+            }
+          }
+          while (i < na) co_st32(D + k++, co_ld32(S + a0 + i++));
+          while (j < nb) co_st32(D + k++, co_ld32(S + b0 + j++));
+          return;
+        }
+        o.type = OUT_FORK;
+        o.nchild = 2;
+        o.ckind = TK_MERGE;
+        o.d[0] = a0; o.d[1] = na; o.d[2] = b0; o.d[3] = nb; o.d[4] = d0 | (dst << 31); o.d[5] = 1;
         return;
       }
-      o.type = OUT_FORK;
-      o.nchild = 2;
-      o.ckind = TK_MERGE;
-      o.d[0] = a0; o.d[1] = na; o.d[2] = b0; o.d[3] = nb; o.d[4] = d0 | (dst << 31); o.d[5] = 1;
-      return;
     }
-    if (kind == TK_KS_RANGE) {  // vertex range: halves, then one vertex task per vertex
-      const uint32_t lo = p0, hi = p1;
-      const uint32_t leaf = static_cast<uint32_t>(job_arg(p, o.job, 4));
-      if (hi <= lo) return;
-      o.type = OUT_FORK;
-      o.d[0] = lo; o.d[1] = hi;
-      o.nchild = hi - lo > leaf ? 2 : hi - lo;
-      o.ckind = hi - lo > leaf ? TK_KS_RANGE : TK_KS_VERTEX;
-      return;
-    }
-    if (kind == TK_KS_VERTEX) {
-      // k = 3: one edge task per out-neighbour.  k >= 4 (at least k-1
-      // out-neighbours): the row tasks of the vertex's matrix first (resume
-      // point 1 forks the edge tasks, resume point 2 sums them)
-      const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 0));
-      const uint32_t k = static_cast<uint32_t>(job_arg(p, o.job, 3));
-      const uint32_t deg = static_cast<uint32_t>(rp[p0 + 1] - rp[p0]);
-      o.words = 2;
-      if (k <= 2) {
-        o.value = k == 1 ? 1 : deg;
+    if constexpr ((kExt & kExtSplit) != 0) {
+      if (kind == TK_KS_RANGE) {  // vertex range: halves, then one vertex task per vertex
+        const uint32_t lo = p0, hi = p1;
+        const uint32_t leaf = static_cast<uint32_t>(job_arg(p, o.job, 4));
+        if (hi <= lo) return;
+        o.type = OUT_FORK;
+        o.d[0] = lo; o.d[1] = hi;
+        o.nchild = hi - lo > leaf ? 2 : hi - lo;
+        o.ckind = hi - lo > leaf ? TK_KS_RANGE : TK_KS_VERTEX;
         return;
       }
-      if (deg == 0 || (k >= 4 && deg < k - 1)) return;
-      o.type = OUT_FORK;
-      o.nchild = deg;
-      o.d[0] = p0;
-      if (k == 3) {  // no matrix: the edge tasks now, the sum at resume point 2
-        o.ckind = TK_KS_EDGE;
-        o.pc_next = 2;
+      if (kind == TK_KS_VERTEX) {
+        // k = 3: one edge task per out-neighbour.  k >= 4 (at least k-1
+        // out-neighbours): the row tasks of the vertex's matrix first (resume
+        // point 1 forks the edge tasks, resume point 2 sums them)
+        const int32_t *rp = reinterpret_cast<const int32_t *>(job_arg(p, o.job, 0));
+        const uint32_t k = static_cast<uint32_t>(job_arg(p, o.job, 3));
+        const uint32_t deg = static_cast<uint32_t>(rp[p0 + 1] - rp[p0]);
+        o.words = 2;
+        if (k <= 2) {
+          o.value = k == 1 ? 1 : deg;
+          return;
+        }
+        if (deg == 0 || (k >= 4 && deg < k - 1)) return;
+        o.type = OUT_FORK;
+        o.nchild = deg;
+        o.d[0] = p0;
+        if (k == 3) {  // no matrix: the edge tasks now, the sum at resume point 2
+          o.ckind = TK_KS_EDGE;
+          o.pc_next = 2;
+          return;
+        }
+        const KsJob J = ks_job(p, o.job);
+        if (deg <= J.thr) {  // few out-neighbours: the whole vertex in place, one-word rows
+          o.type = OUT_DONE;
+          o.value = ks_vertex_in_place(J, p0, deg, o.words);
+          return;
+        }
+        if (J.pivot) {  // U is built by atomic ORs: cleared first
+          const KsMat M = ks_mat(J, p0);
+          for (uint32_t x = 0; x < deg * M.W; ++x) co_st64(M.rows + x, 0ull);
+          o.words += 2 * deg * M.W;
+        }
+        o.ckind = TK_KS_ROW;
         return;
       }
-      const KsJob J = ks_job(p, o.job);
-      if (deg <= J.thr) {  // few out-neighbours: the whole vertex in place, one-word rows
-        o.type = OUT_DONE;
-        o.value = ks_vertex_in_place(J, p0, deg, o.words);
+      if (kind == TK_KS_ROW) {
+        ks_row(p, o, p0, p1);
         return;
       }
-      if (J.pivot) {  // U is built by atomic ORs: cleared first
-        const KsMat M = ks_mat(J, p0);
-        for (uint32_t x = 0; x < deg * M.W; ++x) co_st64(M.rows + x, 0ull);
-        o.words += 2 * deg * M.W;
-      }
-      o.ckind = TK_KS_ROW;
-      return;
-    }
-    if (kind == TK_KS_ROW) {
-      ks_row(p, o, p0, p1);
-      return;
-    }
-    if (kind == TK_KS_EDGE) {
-      ks_edge(p, o, p0, p1);
-      return;
-    }
-    if (kind == TK_KS_HEAVY) {
-      ks_heavy(p, f, o, p0, p1);
-      return;
-    }
-    if (kind == TK_KS_NODE) {
-      ks_node(p, f, o, p0, p1, p2);
-      return;
-    }
-    if (kind == TK_DTT) {
-      // FMM cell pair (A, B) (Sec. 6.4.1): an accepted pair or a pair of
-      // leaves goes to its list (the scheduler appends it, one atomic per
-      // wavefront), any other pair forks the pairs of the wider cell's
-      // children.  Payload: A, B, descriptor (p2, p3), theta = p4 & 255 over
-      // p4 >> 8.
-      const fmm::FmmDesc *D = reinterpret_cast<const fmm::FmmDesc *>(pack(p2, p3));
-      int32_t A[fmm::kCellInts], B[fmm::kCellInts];
-      fmm::load_cell(D->cell, p0, A);
-      fmm::load_cell(D->cell, p1, B);
-      bool split_a = false;
-      const uint32_t dec = fmm::dtt_decide(A, B, static_cast<int64_t>(p4 & 0xFFu), static_cast<int64_t>(p4 >> 8), split_a);
-      o.d[0] = p0; o.d[1] = p1; o.d[3] = p2; o.d[4] = p3; o.d[5] = p4;
-      if (dec != 0) {
-        o.emit = dec;
+      if (kind == TK_KS_EDGE) {
+        ks_edge(p, o, p0, p1);
         return;
       }
-      o.type = OUT_FORK;
-      o.nchild = static_cast<uint32_t>(split_a ? A[7] : B[7]);
-      o.ckind = TK_DTT;
-      o.d[2] = static_cast<uint32_t>(split_a ? A[6] : B[6]) | (split_a ? 0x80000000u : 0u);
-      return;
+      if (kind == TK_KS_HEAVY) {
+        ks_heavy(p, f, o, p0, p1);
+        return;
+      }
+      if (kind == TK_KS_NODE) {
+        ks_node(p, f, o, p0, p1, p2);
+        return;
+      }
+    }
+    if constexpr ((kExt & kExtLists) != 0) {
+      if (kind == TK_DTT) {
+        // FMM cell pair (A, B) (Sec. 6.4.1): an accepted pair or a pair of
+        // leaves goes to its list (the scheduler appends it, one atomic per
+        // wavefront), any other pair forks the pairs of the wider cell's
+        // children.  Payload: A, B, descriptor (p2, p3), theta = p4 & 255 over
+        // p4 >> 8.
+        const fmm::FmmDesc *D = reinterpret_cast<const fmm::FmmDesc *>(pack(p2, p3));
+        int32_t A[fmm::kCellInts], B[fmm::kCellInts];
+        fmm::load_cell(D->cell, p0, A);
+        fmm::load_cell(D->cell, p1, B);
+        bool split_a = false;
+        const uint32_t dec = fmm::dtt_decide(A, B, static_cast<int64_t>(p4 & 0xFFu), static_cast<int64_t>(p4 >> 8), split_a);
+        o.d[0] = p0; o.d[1] = p1; o.d[3] = p2; o.d[4] = p3; o.d[5] = p4;
+        if (dec != 0) {
+          o.emit = dec;
+          return;
+        }
+        o.type = OUT_FORK;
+        o.nchild = static_cast<uint32_t>(split_a ? A[7] : B[7]);
+        o.ckind = TK_DTT;
+        o.d[2] = static_cast<uint32_t>(split_a ? A[6] : B[6]) | (split_a ? 0x80000000u : 0u);
+        return;
+      }
     }
   }
   switch (kind) {
@@ -963,39 +973,43 @@ GTAP_DEV uint32_t bucket_of(const Params &p, uint32_t x) {
 // of its intersection and thus on its cost; a vertex task by its out-degree
 // (its candidate set is N+(v)); a vertex-range task, whose subtree spans many
 // vertices, by the highest class.
-template <bool kExt = false>
+template <uint32_t kExt = 0>
 GTAP_DEV uint32_t child_class(const Params &p, uint32_t job, uint32_t ckind, const ChildInit &c) {
   if (p.Q <= 1) return 0;
   if constexpr (kExt) {
-    if (p.daq_policy == 3) {  // Cilksort: recursive 0, serial sort 1, serial merge 2
-      const uint64_t cut = job_arg(p, job, 3);
-      if (ckind == TK_SORT) return (c.p[1] <= static_cast<uint32_t>(cut) ? 1u : 0u) % p.Q;
-      if (ckind == TK_MERGE) {
-        const uint32_t m = c.p[1] + c.p[3];  // a pending split takes about half
-        const uint32_t est = ((c.p[4] >> 29) & 1u) ? m / 2 : m;
-        return (est <= static_cast<uint32_t>(cut >> 32) ? 2u : 0u) % p.Q;
+    if constexpr ((kExt & kExtLists) != 0) {
+      if (p.daq_policy == 3) {  // Cilksort: recursive 0, serial sort 1, serial merge 2
+        const uint64_t cut = job_arg(p, job, 3);
+        if (ckind == TK_SORT) return (c.p[1] <= static_cast<uint32_t>(cut) ? 1u : 0u) % p.Q;
+        if (ckind == TK_MERGE) {
+          const uint32_t m = c.p[1] + c.p[3];  // a pending split takes about half
+          const uint32_t est = ((c.p[4] >> 29) & 1u) ? m / 2 : m;
+          return (est <= static_cast<uint32_t>(cut >> 32) ? 2u : 0u) % p.Q;
+        }
+        return 0;
       }
-      return 0;
     }
-    if (p.daq_policy == 2 && ckind >= TK_KS_RANGE) {
-      // split k-clique: a vertex by its out-degree; an edge by its candidate
-      // count when its row of the vertex's matrix is built (k >= 4; its
-      // parent forks the edges only then), else by min(outdeg u, outdeg v);
-      // ranges, row tasks, a heavy edge's search and its branches in the
-      // highest class
-      if (ckind != TK_KS_EDGE && ckind != TK_KS_VERTEX) return p.Q - 1;
-      const KsJob J = ks_job(p, job);
-      const uint32_t u = c.p[0];
-      if (ckind == TK_KS_VERTEX) return bucket_of(p, static_cast<uint32_t>(J.rp[u + 1] - J.rp[u]));
-      if (J.kk >= 2) {
-        const KsMat M = ks_mat(J, u);
-        uint32_t n = 0;
-        for (uint32_t w = 0; w < M.W; ++w) n += __popcll(co_ld64(M.D + static_cast<size_t>(c.p[1]) * M.W + w));
-        return bucket_of(p, n);
+    if constexpr ((kExt & kExtSplit) != 0) {
+      if (p.daq_policy == 2 && ckind >= TK_KS_RANGE) {
+        // split k-clique: a vertex by its out-degree; an edge by its candidate
+        // count when its row of the vertex's matrix is built (k >= 4; its
+        // parent forks the edges only then), else by min(outdeg u, outdeg v);
+        // ranges, row tasks, a heavy edge's search and its branches in the
+        // highest class
+        if (ckind != TK_KS_EDGE && ckind != TK_KS_VERTEX) return p.Q - 1;
+        const KsJob J = ks_job(p, job);
+        const uint32_t u = c.p[0];
+        if (ckind == TK_KS_VERTEX) return bucket_of(p, static_cast<uint32_t>(J.rp[u + 1] - J.rp[u]));
+        if (J.kk >= 2) {
+          const KsMat M = ks_mat(J, u);
+          uint32_t n = 0;
+          for (uint32_t w = 0; w < M.W; ++w) n += __popcll(co_ld64(M.D + static_cast<size_t>(c.p[1]) * M.W + w));
+          return bucket_of(p, n);
+        }
+        const int32_t v = J.col[J.rp[u] + c.p[1]];
+        const uint32_t du = static_cast<uint32_t>(J.rp[u + 1] - J.rp[u]), dv = static_cast<uint32_t>(J.rp[v + 1] - J.rp[v]);
+        return bucket_of(p, du < dv ? du : dv);
       }
-      const int32_t v = J.col[J.rp[u] + c.p[1]];
-      const uint32_t du = static_cast<uint32_t>(J.rp[u + 1] - J.rp[u]), dv = static_cast<uint32_t>(J.rp[v + 1] - J.rp[v]);
-      return bucket_of(p, du < dv ? du : dv);
     }
   }
   switch (p.daq_policy) {
@@ -1027,57 +1041,63 @@ GTAP_DEV uint32_t nth_set_bit(uint32_t m, uint32_t j) {
 
 // Payload of child j of a forked parent with child kind `ckind` and
 // descriptor d.
-template <bool kExt = false>
+template <uint32_t kExt = 0>
 GTAP_DEV void make_child(uint32_t ckind, const Words<6> &d, uint32_t j, ChildInit &c) {
   for (uint32_t i = 0; i < kPayloadWords; ++i) c.p[i] = 0;
   if constexpr (kExt) {
-    if (ckind == TK_SORT) {  // half j into the other buffer
-      const uint32_t h = d[1] / 2;
-      c.p[0] = d[0] + (j ? h : 0u);
-      c.p[1] = j ? d[1] - h : h;
-      c.p[2] = d[2] ^ 1u;
-      return;
+    if constexpr ((kExt & kExtLists) != 0) {
+      if (ckind == TK_SORT) {  // half j into the other buffer
+        const uint32_t h = d[1] / 2;
+        c.p[0] = d[0] + (j ? h : 0u);
+        c.p[1] = j ? d[1] - h : h;
+        c.p[2] = d[2] ^ 1u;
+        return;
+      }
+      if (ckind == TK_MERGE) {  // d[5] = 0: the merge of a sort; 1: side j of a split
+        c.p[0] = d[0]; c.p[1] = d[1]; c.p[2] = d[2]; c.p[3] = d[3];
+        c.p[4] = d[5] ? (d[4] | (1u << 29) | (j << 30)) : d[4];
+        return;
+      }
     }
-    if (ckind == TK_MERGE) {  // d[5] = 0: the merge of a sort; 1: side j of a split
-      c.p[0] = d[0]; c.p[1] = d[1]; c.p[2] = d[2]; c.p[3] = d[3];
-      c.p[4] = d[5] ? (d[4] | (1u << 29) | (j << 30)) : d[4];
-      return;
+    if constexpr ((kExt & kExtSplit) != 0) {
+      if (ckind == TK_KS_RANGE) {
+        const uint32_t lo = d[0], hi = d[1], mid = lo + (hi - lo) / 2;
+        c.p[0] = j == 0 ? lo : mid;
+        c.p[1] = j == 0 ? mid : hi;
+        return;
+      }
+      if (ckind == TK_KS_VERTEX) {
+        c.p[0] = d[0] + j;
+        return;
+      }
+      if (ckind == TK_KS_EDGE || ckind == TK_KS_ROW) {  // (u, index of the out-neighbour)
+        c.p[0] = d[0];
+        c.p[1] = j;
+        return;
+      }
+      if (ckind == TK_KS_HEAVY) {  // the only child: the forking edge's own (u, index)
+        c.p[0] = d[0];
+        c.p[1] = d[1];
+        return;
+      }
+      if (ckind == TK_KS_NODE) {  // (vertex, branch, parent's node-state offset)
+        c.p[0] = d[0];
+        c.p[1] = j;
+        c.p[2] = d[1];
+        return;
+      }
     }
-    if (ckind == TK_KS_RANGE) {
-      const uint32_t lo = d[0], hi = d[1], mid = lo + (hi - lo) / 2;
-      c.p[0] = j == 0 ? lo : mid;
-      c.p[1] = j == 0 ? mid : hi;
-      return;
-    }
-    if (ckind == TK_KS_VERTEX) {
-      c.p[0] = d[0] + j;
-      return;
-    }
-    if (ckind == TK_KS_EDGE || ckind == TK_KS_ROW) {  // (u, index of the out-neighbour)
-      c.p[0] = d[0];
-      c.p[1] = j;
-      return;
-    }
-    if (ckind == TK_KS_HEAVY) {  // the only child: the forking edge's own (u, index)
-      c.p[0] = d[0];
-      c.p[1] = d[1];
-      return;
-    }
-    if (ckind == TK_KS_NODE) {  // (vertex, branch, parent's node-state offset)
-      c.p[0] = d[0];
-      c.p[1] = j;
-      c.p[2] = d[1];
-      return;
-    }
-    if (ckind == TK_DTT) {  // pair (child j of the split cell, the other cell)
-      const bool sa = (d[2] >> 31) != 0;
-      const uint32_t c0 = d[2] & 0x7FFFFFFFu;
-      c.p[0] = sa ? c0 + j : d[0];
-      c.p[1] = sa ? d[1] : c0 + j;
-      c.p[2] = d[3];
-      c.p[3] = d[4];
-      c.p[4] = d[5];
-      return;
+    if constexpr ((kExt & kExtLists) != 0) {
+      if (ckind == TK_DTT) {  // pair (child j of the split cell, the other cell)
+        const bool sa = (d[2] >> 31) != 0;
+        const uint32_t c0 = d[2] & 0x7FFFFFFFu;
+        c.p[0] = sa ? c0 + j : d[0];
+        c.p[1] = sa ? d[1] : c0 + j;
+        c.p[2] = d[3];
+        c.p[3] = d[4];
+        c.p[4] = d[5];
+        return;
+      }
     }
   }
   switch (ckind) {
